@@ -1,0 +1,166 @@
+/* bandsolve.h -- C ABI of libbandsolve, batched band-SLAE solvers for
+ * MI355X (gfx950).
+ *
+ * The library solves many independent pentadiagonal (kind 5) or tridiagonal
+ * (kind 3) systems at once -- the N systems that each sweep of an ADI scheme
+ * for a parabolic PDE produces, d times per time step (Veneva & Ayriyan,
+ * arXiv:1804.09666, Sec. 1).  Methods:
+ *   - NPDM / NTDM: LU-based direct solvers for PD / TD matrices (Sec. 1;
+ *     complexity 19N-29 and 9N+2, Sec. 4);
+ *   - MNPDM: NPDM that skips the work on the sparse outer diagonals
+ *     (Sec. 1; 13N+7K-14, Sec. 4);
+ *   - ILU(0) of the band and the Stone method SIP (Sec. 2, Algorithm 1),
+ *     optionally with Hotelling-Bodewig approximate inverses of L and U in
+ *     place of the triangular solves (Remark of Sec. 2; Appendix).
+ *
+ * MEMORY.  Every array argument is a DEVICE pointer owned by the caller; the
+ * library keeps no pointer after a call returns and allocates nothing.
+ * Scratch memory, where a call needs any, is the caller's `workspace`, sized
+ * by bs_workspace_bytes().
+ *
+ * LAYOUT.  Batch-interleaved: element (row i, system s) of every per-row array
+ * is at p[i*ld + s], 0 <= i < n, 0 <= s < batch, ld >= batch.  Consecutive
+ * systems are contiguous, so one row of 64 systems is one 512-byte (FP64)
+ * transaction; ld a multiple of 64 is recommended.  Row i of a system reads
+ *     e_i x_{i-2} + c_i x_{i-1} + d_i x_i + a_i x_{i+1} + b_i x_{i+2} = y_i
+ * with diags[0]=e, [1]=c, [2]=d, [3]=a, [4]=b.  Kind 3 reads only c, d, a
+ * (diags[0] and diags[4] may be NULL).  The corner slots e_0, e_1, c_0,
+ * a_{n-1}, b_{n-2}, b_{n-1} are never read (they may hold anything, NaN
+ * included).  Inputs are never written.  x may alias rhs.
+ *
+ * PRECISION.  dtype BS_F64: every array is double.  dtype BS_F32 (band_solve
+ * only): diags, rhs and x are float; pivots and recurrences run in FP32.
+ *
+ * STREAMS.  `stream` is a hipStream_t passed as void* (NULL = the default
+ * stream).  Every call only enqueues work on it and returns; results, info,
+ * iters and relres are valid once the stream has reached that point.
+ *
+ * ERRORS.  The return value is a bs_status decided on the host, before
+ * anything is enqueued, except BS_ELAUNCH (a launch failed; some work of the
+ * call may already be enqueued).  Numerical outcomes are written per system,
+ * asynchronously, to `info`:
+ *     0      success
+ *     i+1    (> 0) the first pivot that is exactly zero or not finite is in
+ *            row i; x of that system is unspecified
+ *    -1      SIP: not converged within max_iter
+ *    -2      SIP: diverged (residual not finite, or relative residual above
+ *            1e3 * max(1, relative residual of x0))
+ *    -3      MNPDM: the outer-entry list of the system is not strictly
+ *            ascending or names a row outside 0..n-1
+ */
+#ifndef BANDSOLVE_H
+#define BANDSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum bs_status_code {
+  BS_OK = 0,
+  BS_EINVAL = 1,     /* an argument is out of range, NULL or misaligned   */
+  BS_ELAUNCH = 2,    /* a kernel launch failed (HIP error)                 */
+  BS_EWORKSPACE = 3, /* ws_bytes smaller than bs_workspace_bytes() asks    */
+  BS_ENODEV = 4      /* no usable gfx950 device for the current HIP device */
+};
+
+enum bs_dtype_code { BS_F64 = 0, BS_F32 = 1 };
+
+enum bs_op_code {
+  BS_OP_FACTOR = 0,       /* band_factor                                   */
+  BS_OP_SOLVE = 1,        /* band_solve with factors == NULL (fused)       */
+  BS_OP_SOLVE_FACTORED = 2, /* band_solve with factors from band_factor    */
+  BS_OP_MNPDM = 3,        /* band_solve_mnpdm                              */
+  BS_OP_SIP = 4           /* sip_solve                                     */
+};
+
+/* Human-readable name of a status code (static string). */
+const char* bs_status_str(int32_t status);
+
+/* Library ABI version (major*100 + minor). */
+int32_t bs_version(void);
+
+/* Bytes of device workspace the call `op` needs for (kind, dtype, n, batch);
+ * 0 when it needs none.  Returns (size_t)-1 for arguments the call would
+ * reject.  Host-only, never touches the GPU. */
+size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
+                          int64_t batch);
+
+/* ILU(0) of every system: the band Doolittle factorization A = L U with L
+ * unit lower (l2, l1 on diagonals -2, -1) and U upper (u0, u1, u2 on 0, +1,
+ * +2, u2 = b), which for a band is its exact LU (Sec. 2: ILU(0) keeps the
+ * zero pattern of A; a band has no fill outside it).
+ *   l2_i = e_i / u0_{i-2};  l1_i = (c_i - l2_i u1_{i-2}) / u0_{i-1};
+ *   u0_i = (d_i - l2_i u2_{i-2}) - l1_i u1_{i-1};  u1_i = a_i - l1_i u2_{i-1}.
+ * factors: kind 5 -> 4 arrays [l2 | l1 | u0 | u1], kind 3 -> 2 arrays
+ * [l1 | u0], each n*ld elements in the batch-interleaved layout (array k at
+ * factors + k*n*ld).  Entries outside the band (l2 of rows 0,1, l1 of row 0,
+ * u1 of row n-1) are written as 0.  info[s]: 0 or i+1 for the first bad u0_i.
+ * dtype must be BS_F64. */
+int32_t band_factor(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
+                    int64_t ld, const void* const diags[5], void* factors,
+                    int32_t* info, void* stream);
+
+/* Solve A x = rhs for every system.
+ * factors == NULL: fused factor + solve, NPDM (kind 5) or NTDM (kind 3)
+ *   (Sec. 1): LU without pivoting, L = (e, gamma, mu), U unit upper
+ *   (alpha, beta); info[s] reports the first bad pivot.  For large enough
+ *   batches each system is one lane and the arithmetic is that of the
+ *   sequential recurrence; for few, long systems the rows of a system are
+ *   split over several lanes (partitioned elimination with a reduced
+ *   interface system), which changes the rounding but not the result beyond
+ *   it (info then reports the first bad pivot of the elimination performed).
+ * factors != NULL: substitution with the factors of band_factor (same kind
+ *   and layout): L z = rhs, U x = z.  info[s] is set to 0.
+ * workspace / ws_bytes: as bs_workspace_bytes(BS_OP_SOLVE or
+ *   BS_OP_SOLVE_FACTORED, ...); may be NULL / 0 when that is 0. */
+int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
+                   int64_t ld, const void* const diags[5], const void* factors,
+                   const void* rhs, void* x, int32_t* info, void* workspace,
+                   size_t ws_bytes, void* stream);
+
+/* MNPDM (Sec. 1): pentadiagonal solve in which the outer diagonals e and b
+ * are given sparsely.  cda = {c, d, a} (batch-interleaved, n*ld each).
+ * For system s, list entry k (0 <= k < kmax) is at outer_row[k*ld + s] (an
+ * int32 row index, -1 = unused; used entries strictly ascending and first),
+ * with values outer_e[k*ld + s] (coefficient e of that row) and
+ * outer_b[k*ld + s] (coefficient b of that row).  All other e_i, b_i are 0.
+ * Products with absent entries are skipped; on finite data the result equals
+ * NPDM on the full diagonals.  kmax may be 0 (then the three list pointers
+ * may be NULL).  dtype must be BS_F64. */
+int32_t band_solve_mnpdm(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
+                         const void* const cda[3], int32_t kmax,
+                         const int32_t* outer_row, const void* outer_e,
+                         const void* outer_b, const void* rhs, void* x,
+                         int32_t* info, void* workspace, size_t ws_bytes,
+                         void* stream);
+
+/* Stone method / SIP (Sec. 2, Algorithm 1) for pentadiagonal systems.
+ * factors: ILU(0) factors from band_factor (kind 5), or NULL to have them
+ *   computed into the workspace first.
+ * x: in = x0 (zeros, previous time step, or a learned guess), out = result.
+ * hb_s_L, hb_s_U: Hotelling-Bodewig steps X_{j+1} = X_j (2I - T X_j),
+ *   X_0 = diag(T)^{-1} (Appendix), used in place of the L and U solves
+ *   (Remark of Sec. 2).  A negative value keeps the exact substitution for
+ *   that factor; both negative runs Algorithm 1 as written
+ *   (x <- U^{-1} L^{-1} (K x + b), K = LU - A).  Otherwise the step is
+ *   x <- x + X_U X_L (b - A x).  Allowed: s <= 6, or any s with 2^s >= n
+ *   (HB is then exact and the exact substitution is used).
+ * Stop when ||b - A x||_inf < tol * ||b||_inf (relative form of the paper's
+ *   errorMargin test, checked before every step) or after max_iter steps.
+ * iters[s] (int32), relres[s] (double, final relative residual) and info[s]
+ * (0, -1, -2 or a pivot row + 1) are written per system.  dtype BS_F64. */
+int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
+                  const void* const diags[5], const void* factors,
+                  const void* rhs, void* x, double tol, int32_t max_iter,
+                  int32_t hb_s_L, int32_t hb_s_U, int32_t* iters,
+                  double* relres, int32_t* info, void* workspace,
+                  size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BANDSOLVE_H */

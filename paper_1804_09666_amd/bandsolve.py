@@ -1,0 +1,228 @@
+"""Python binding of libbandsolve (include/bandsolve.h).
+
+Argument marshalling only: tensors are checked for device, dtype, layout and
+shape, their device pointers and the current HIP stream are handed to the C
+ABI, and any non-zero status becomes a BandSolveError.  Every step of every
+solve runs in the library's HIP kernels; this module computes nothing.  If the
+library is not built, loading fails loudly -- there is no fallback.
+
+Layout: every per-row array is a 2-D float64 (or float32) tensor [n, ld] in
+the batch-interleaved layout -- element (row i, system s) at [i, s] -- with
+systems 0..batch-1 in the first `batch` columns (batch <= ld).  Diagonals are
+passed as a 5-list (e, c, d, a, b); for tridiagonal systems (kind 3) e and b
+may be None.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbandsolve.so")
+
+BS_OK, BS_EINVAL, BS_ELAUNCH, BS_EWORKSPACE, BS_ENODEV = range(5)
+BS_F64, BS_F32 = 0, 1
+OP_FACTOR, OP_SOLVE, OP_SOLVE_FACTORED, OP_MNPDM, OP_SIP = range(5)
+
+EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "band_factor",
+            "band_solve", "band_solve_mnpdm", "sip_solve")
+
+
+class BandSolveError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        super().__init__(f"{what}: {status_str(status)}")
+
+
+_lib = None
+
+
+def load():
+    """Load libbandsolve.so (built by __graft_entry__.build()).  No fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    vp5 = ctypes.c_void_p * 5
+    vp3 = ctypes.c_void_p * 3
+    sig = {
+        "bs_status_str": (ctypes.c_char_p, [i32]),
+        "bs_version": (i32, []),
+        "bs_workspace_bytes": (sz, [i32, i32, i32, i64, i64]),
+        "band_factor": (i32, [i32, i32, i64, i64, i64, vp5, vp, vp, vp]),
+        "band_solve": (i32, [i32, i32, i64, i64, i64, vp5, vp, vp, vp, vp, vp, sz, vp]),
+        "band_solve_mnpdm": (i32, [i32, i64, i64, i64, vp3, i32, vp, vp, vp, vp, vp,
+                                   vp, vp, sz, vp]),
+        "sip_solve": (i32, [i32, i64, i64, i64, vp5, vp, vp, vp, ctypes.c_double, i32,
+                            i32, i32, vp, vp, vp, vp, sz, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    lib.VP5 = vp5
+    lib.VP3 = vp3
+    _lib = lib
+    return lib
+
+
+def status_str(status):
+    return load().bs_status_str(int(status)).decode()
+
+
+def workspace_bytes(op, kind, n, batch, dtype=BS_F64):
+    v = load().bs_workspace_bytes(op, kind, dtype, n, batch)
+    if v == ctypes.c_size_t(-1).value:
+        raise BandSolveError(BS_EINVAL, "bs_workspace_bytes")
+    return v
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check2d(t, name, n, dtype):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype or t.dim() != 2 or t.shape[0] != n or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape [n={n}, ld]")
+    return t.shape[1]
+
+
+def _dtype_code(dtype):
+    return {torch.float64: BS_F64, torch.float32: BS_F32}[dtype]
+
+
+def _prep(diags, rhs, kind, batch):
+    d = diags[2]
+    n = d.shape[0]
+    dtype = d.dtype
+    if kind is None:
+        kind = 5 if (diags[0] is not None and diags[4] is not None) else 3
+    need = range(5) if kind == 5 else (1, 2, 3)
+    ld = None
+    for k in need:
+        l_k = _check2d(diags[k], "diags[%d]" % k, n, dtype)
+        if ld is None:
+            ld = l_k
+        elif l_k != ld:
+            raise ValueError("all arrays must share one leading dimension")
+    if rhs is not None and _check2d(rhs, "rhs", n, dtype) != ld:
+        raise ValueError("rhs leading dimension differs")
+    batch = ld if batch is None else int(batch)
+    return kind, n, ld, batch, dtype
+
+
+def _ws(nbytes, device):
+    if nbytes == 0:
+        return None
+    return torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device)
+
+
+def _raise(st, what):
+    if st != BS_OK:
+        raise BandSolveError(st, what)
+
+
+def factor(diags, *, kind=None, batch=None, out=None, info=None, stream=None):
+    """ILU(0) (band Doolittle) of every system -> (factors [nf, n, ld], info)."""
+    lib = load()
+    kind, n, ld, batch, dtype = _prep(diags, None, kind, batch)
+    nf = 4 if kind == 5 else 2
+    dev = diags[2].device
+    out = torch.empty((nf, n, ld), dtype=dtype, device=dev) if out is None else out
+    info = torch.empty(batch, dtype=torch.int32, device=dev) if info is None else info
+    st = lib.band_factor(kind, _dtype_code(dtype), n, batch, ld,
+                         lib.VP5(*[_ptr(t) for t in diags]), _ptr(out), _ptr(info),
+                         _stream(stream))
+    _raise(st, "band_factor")
+    return out, info
+
+
+def solve(diags, rhs, x=None, *, kind=None, batch=None, factors=None, info=None,
+          workspace=None, stream=None):
+    """x = A^{-1} rhs for every system (NPDM / NTDM, or substitution with
+    `factors` from factor()).  Returns (x, info)."""
+    lib = load()
+    kind, n, ld, batch, dtype = _prep(diags, rhs, kind, batch)
+    dev = rhs.device
+    x = torch.empty_like(rhs) if x is None else x
+    _check2d(x, "x", n, dtype)
+    info = torch.empty(batch, dtype=torch.int32, device=dev) if info is None else info
+    op = OP_SOLVE if factors is None else OP_SOLVE_FACTORED
+    nbytes = workspace_bytes(op, kind, n, batch, _dtype_code(dtype))
+    if workspace is None:
+        workspace = _ws(nbytes, dev)
+    st = lib.band_solve(kind, _dtype_code(dtype), n, batch, ld,
+                        lib.VP5(*[_ptr(t) for t in diags]), _ptr(factors), _ptr(rhs),
+                        _ptr(x), _ptr(info), _ptr(workspace),
+                        0 if workspace is None else workspace.numel() * workspace.element_size(),
+                        _stream(stream))
+    _raise(st, "band_solve")
+    return x, info
+
+
+def solve_mnpdm(cda, outer_row, outer_e, outer_b, rhs, x=None, *, batch=None,
+                info=None, workspace=None, stream=None):
+    """MNPDM: c, d, a as [n, ld] tensors; the outer entries as [kmax, ld]
+    tensors (int32 rows, -1 = unused; float64 e and b values)."""
+    lib = load()
+    c, d, a = cda
+    n = d.shape[0]
+    ld = _check2d(d, "d", n, torch.float64)
+    for t, nm in ((c, "c"), (a, "a"), (rhs, "rhs")):
+        if _check2d(t, nm, n, torch.float64) != ld:
+            raise ValueError("leading dimension mismatch")
+    batch = ld if batch is None else int(batch)
+    kmax = 0 if outer_row is None else outer_row.shape[0]
+    if kmax:
+        for t, dt in ((outer_row, torch.int32), (outer_e, torch.float64), (outer_b, torch.float64)):
+            if t.dtype != dt or t.shape != (kmax, ld) or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("outer lists must be contiguous [kmax, ld] device tensors")
+    dev = rhs.device
+    x = torch.empty_like(rhs) if x is None else x
+    info = torch.empty(batch, dtype=torch.int32, device=dev) if info is None else info
+    nbytes = workspace_bytes(OP_MNPDM, 5, n, batch)
+    workspace = _ws(nbytes, dev) if workspace is None else workspace
+    st = lib.band_solve_mnpdm(BS_F64, n, batch, ld, lib.VP3(*[_ptr(t) for t in cda]), kmax,
+                              _ptr(outer_row) if kmax else None,
+                              _ptr(outer_e) if kmax else None,
+                              _ptr(outer_b) if kmax else None, _ptr(rhs), _ptr(x),
+                              _ptr(info), _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _stream(stream))
+    _raise(st, "band_solve_mnpdm")
+    return x, info
+
+
+def sip(diags, rhs, x0=None, *, tol, max_iter, s_L=-1, s_U=-1, factors=None,
+        batch=None, x=None, workspace=None, stream=None):
+    """Stone method over ILU(0) -> (x, iters, relres, info).  x0 (or x) is the
+    start vector; zeros when both are None."""
+    lib = load()
+    kind, n, ld, batch, dtype = _prep(diags, rhs, 5, batch)
+    dev = rhs.device
+    if x is None:
+        x = torch.zeros_like(rhs) if x0 is None else x0.clone()
+    elif x0 is not None:
+        x.copy_(x0)
+    iters = torch.empty(batch, dtype=torch.int32, device=dev)
+    relres = torch.empty(batch, dtype=torch.float64, device=dev)
+    info = torch.empty(batch, dtype=torch.int32, device=dev)
+    nbytes = workspace_bytes(OP_SIP, 5, n, batch)
+    workspace = _ws(nbytes, dev) if workspace is None else workspace
+    st = lib.sip_solve(BS_F64, n, batch, ld, lib.VP5(*[_ptr(t) for t in diags]),
+                       _ptr(factors), _ptr(rhs), _ptr(x), float(tol), int(max_iter),
+                       int(s_L), int(s_U), _ptr(iters), _ptr(relres), _ptr(info),
+                       _ptr(workspace), workspace.numel() * workspace.element_size(),
+                       _stream(stream))
+    _raise(st, "sip_solve")
+    return x, iters, relres, info

@@ -1,0 +1,236 @@
+// abi.hip -- the exported C ABI of libbandsolve (declared in
+// include/bandsolve.h): host-side argument checks, workspace sizing and the
+// choice of kernel, then an asynchronous launch on the caller's stream.
+//
+// Every check that can fail happens before the first HIP call, so a rejected
+// call never touches the device (and can be exercised on a machine without a
+// GPU).
+#include <stdint.h>
+#include <string.h>
+
+#include "../../include/bandsolve.h"
+#include "bs_internal.h"
+
+namespace {
+
+constexpr int64_t kMaxElems = int64_t(1) << 50;  // guards n*ld overflow
+
+bool aligned(const void* p, size_t a) {
+  return (reinterpret_cast<uintptr_t>(p) % a) == 0;
+}
+
+bool shape_ok(int64_t n, int64_t batch, int64_t ld) {
+  if (n < 1 || batch < 1 || ld < batch) return false;
+  if (n > (int64_t(1) << 31) || batch > (int64_t(1) << 31)) return false;
+  if (ld > kMaxElems / n) return false;
+  return true;
+}
+
+bool kind_ok(int32_t kind) { return kind == 3 || kind == 5; }
+
+size_t elem_size(int32_t dtype) { return dtype == BS_F32 ? 4 : 8; }
+
+bool array_ok(const void* p, int32_t dtype) {
+  return p != nullptr && aligned(p, elem_size(dtype));
+}
+
+// Diagonals a kind reads: PD all five, TD c, d, a.
+bool diags_ok(int32_t kind, const void* const diags[5], int32_t dtype) {
+  if (diags == nullptr) return false;
+  for (int k = 0; k < 5; ++k) {
+    const bool needed = (kind == 5) || (k >= 1 && k <= 3);
+    if (needed && !array_ok(diags[k], dtype)) return false;
+  }
+  return true;
+}
+
+bs::Diags as_diags(int32_t kind, const void* const diags[5]) {
+  bs::Diags A;
+  A.e = kind == 5 ? static_cast<const double*>(diags[0]) : nullptr;
+  A.c = static_cast<const double*>(diags[1]);
+  A.d = static_cast<const double*>(diags[2]);
+  A.a = static_cast<const double*>(diags[3]);
+  A.b = kind == 5 ? static_cast<const double*>(diags[4]) : nullptr;
+  return A;
+}
+
+// Scratch arrays of n * ws_ld(batch) elements each a variant streams through.
+int64_t solve_ws_planes(int32_t kind, int64_t n, int64_t batch) {
+  if (bs::part_supported(kind, n, batch)) return 0;
+  return kind == 5 ? 2 : 1;  // alpha (+ beta); z is kept in x
+}
+
+int32_t launched(hipError_t e) { return e == hipSuccess ? BS_OK : BS_ELAUNCH; }
+
+bool have_device() {
+  int count = 0;
+  return hipGetDeviceCount(&count) == hipSuccess && count > 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bs_status_str(int32_t status) {
+  switch (status) {
+    case BS_OK: return "BS_OK";
+    case BS_EINVAL: return "BS_EINVAL: invalid argument";
+    case BS_ELAUNCH: return "BS_ELAUNCH: kernel launch failed";
+    case BS_EWORKSPACE: return "BS_EWORKSPACE: workspace too small";
+    case BS_ENODEV: return "BS_ENODEV: no usable GPU";
+    default: return "unknown bs_status";
+  }
+}
+
+int32_t bs_version(void) { return 100; }
+
+size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
+                          int64_t batch) {
+  const size_t bad = (size_t)-1;
+  if (!shape_ok(n, batch, batch)) return bad;
+  if (dtype != BS_F64) return bad;
+  const int64_t plane = n * bs::ws_ld(batch);
+  switch (op) {
+    case BS_OP_FACTOR:
+      return kind_ok(kind) ? 0 : bad;
+    case BS_OP_SOLVE:
+      return kind_ok(kind) ? (size_t)(solve_ws_planes(kind, n, batch) * plane) * 8 : bad;
+    case BS_OP_SOLVE_FACTORED:
+      return kind_ok(kind) ? 0 : bad;
+    case BS_OP_MNPDM:
+      return (size_t)(2 * plane) * 8;
+    case BS_OP_SIP:
+      // ILU(0) factors (4 planes, batch-interleaved with ld = ws_ld) + 1 plane
+      // for the forward pass result
+      return (size_t)(5 * plane) * 8;
+    default:
+      return bad;
+  }
+}
+
+int32_t band_factor(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
+                    int64_t ld, const void* const diags[5], void* factors,
+                    int32_t* info, void* stream) {
+  if (!kind_ok(kind) || dtype != BS_F64 || !shape_ok(n, batch, ld)) return BS_EINVAL;
+  if (!diags_ok(kind, diags, dtype) || !array_ok(factors, dtype) ||
+      info == nullptr || !aligned(info, 4))
+    return BS_EINVAL;
+  if (!have_device()) return BS_ENODEV;
+  return launched(bs::launch_factor_lane(kind, n, batch, ld, as_diags(kind, diags),
+                                         static_cast<double*>(factors), ld, info,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
+                   int64_t ld, const void* const diags[5], const void* factors,
+                   const void* rhs, void* x, int32_t* info, void* workspace,
+                   size_t ws_bytes, void* stream) {
+  if (!kind_ok(kind) || dtype != BS_F64 || !shape_ok(n, batch, ld)) return BS_EINVAL;
+  if (!diags_ok(kind, diags, dtype) || !array_ok(rhs, dtype) ||
+      !array_ok(x, dtype) || info == nullptr || !aligned(info, 4))
+    return BS_EINVAL;
+  if (factors != nullptr && !array_ok(factors, dtype)) return BS_EINVAL;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const bs::Diags A = as_diags(kind, diags);
+  if (factors != nullptr) {
+    if (!have_device()) return BS_ENODEV;
+    return launched(bs::launch_subst_lane(kind, n, batch, ld, A,
+                                          static_cast<const double*>(factors),
+                                          static_cast<const double*>(rhs),
+                                          static_cast<double*>(x), info, st));
+  }
+  const size_t need = bs_workspace_bytes(BS_OP_SOLVE, kind, dtype, n, batch);
+  if (ws_bytes < need) return BS_EWORKSPACE;
+  if (need > 0 && !array_ok(workspace, dtype)) return BS_EINVAL;
+  if (!have_device()) return BS_ENODEV;
+  if (bs::part_supported(kind, n, batch))
+    return launched(bs::launch_part(kind, n, batch, ld, A,
+                                    static_cast<const double*>(rhs),
+                                    static_cast<double*>(x), info, st));
+  double* ws = static_cast<double*>(workspace);
+  if (kind == 5)
+    return launched(bs::launch_npdm_lane(n, batch, ld, A,
+                                         static_cast<const double*>(rhs),
+                                         static_cast<double*>(x), info, ws, st));
+  return launched(bs::launch_ntdm_lane(n, batch, ld, A,
+                                       static_cast<const double*>(rhs),
+                                       static_cast<double*>(x), info, ws, st));
+}
+
+int32_t band_solve_mnpdm(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
+                         const void* const cda[3], int32_t kmax,
+                         const int32_t* outer_row, const void* outer_e,
+                         const void* outer_b, const void* rhs, void* x,
+                         int32_t* info, void* workspace, size_t ws_bytes,
+                         void* stream) {
+  if (dtype != BS_F64 || !shape_ok(n, batch, ld) || kmax < 0) return BS_EINVAL;
+  if (cda == nullptr || !array_ok(cda[0], dtype) || !array_ok(cda[1], dtype) ||
+      !array_ok(cda[2], dtype) || !array_ok(rhs, dtype) || !array_ok(x, dtype) ||
+      info == nullptr || !aligned(info, 4))
+    return BS_EINVAL;
+  if (kmax > 0 && (outer_row == nullptr || !aligned(outer_row, 4) ||
+                   !array_ok(outer_e, dtype) || !array_ok(outer_b, dtype)))
+    return BS_EINVAL;
+  const size_t need = bs_workspace_bytes(BS_OP_MNPDM, 5, dtype, n, batch);
+  if (ws_bytes < need) return BS_EWORKSPACE;
+  if (!array_ok(workspace, dtype)) return BS_EINVAL;
+  if (!have_device()) return BS_ENODEV;
+  bs::Diags A;
+  A.e = nullptr;
+  A.c = static_cast<const double*>(cda[0]);
+  A.d = static_cast<const double*>(cda[1]);
+  A.a = static_cast<const double*>(cda[2]);
+  A.b = nullptr;
+  return launched(bs::launch_mnpdm_lane(
+      n, batch, ld, A, kmax, outer_row, static_cast<const double*>(outer_e),
+      static_cast<const double*>(outer_b), static_cast<const double*>(rhs),
+      static_cast<double*>(x), info, static_cast<double*>(workspace),
+      static_cast<hipStream_t>(stream)));
+}
+
+int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
+                  const void* const diags[5], const void* factors,
+                  const void* rhs, void* x, double tol, int32_t max_iter,
+                  int32_t hb_s_L, int32_t hb_s_U, int32_t* iters,
+                  double* relres, int32_t* info, void* workspace,
+                  size_t ws_bytes, void* stream) {
+  if (dtype != BS_F64 || !shape_ok(n, batch, ld)) return BS_EINVAL;
+  if (!diags_ok(5, diags, dtype) || !array_ok(rhs, dtype) || !array_ok(x, dtype))
+    return BS_EINVAL;
+  if (iters == nullptr || !aligned(iters, 4) || !array_ok(relres, BS_F64) ||
+      info == nullptr || !aligned(info, 4))
+    return BS_EINVAL;
+  if (!(tol > 0.0) || max_iter < 0) return BS_EINVAL;
+  auto s_ok = [n](int32_t s) {
+    if (s < 0 || s <= 6) return true;
+    return s < 62 && (int64_t(1) << s) >= n;
+  };
+  if (!s_ok(hb_s_L) || !s_ok(hb_s_U)) return BS_EINVAL;
+  if (factors != nullptr && !array_ok(factors, dtype)) return BS_EINVAL;
+  const size_t need = bs_workspace_bytes(BS_OP_SIP, 5, dtype, n, batch);
+  if (ws_bytes < need) return BS_EWORKSPACE;
+  if (!array_ok(workspace, dtype)) return BS_EINVAL;
+  if (!have_device()) return BS_ENODEV;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const bs::Diags A = as_diags(5, diags);
+  double* ws = static_cast<double*>(workspace);
+  const int64_t lw = bs::ws_ld(batch);
+  const double* F = static_cast<const double*>(factors);
+  int64_t fld = ld;  // pitch of caller-provided factors (band_factor output)
+  if (F == nullptr) {
+    // ILU(0) into the first 4 workspace planes (pitch lw), then the plane for
+    // the forward-pass result
+    double* Fw = ws;
+    ws = ws + 4 * n * lw;
+    fld = lw;
+    if (bs::launch_factor_lane(5, n, batch, ld, A, Fw, fld, info, st) != hipSuccess)
+      return BS_ELAUNCH;
+    F = Fw;
+  }
+  return launched(bs::launch_sip_lane(n, batch, ld, A, F, fld,
+                                      static_cast<const double*>(rhs),
+                                      static_cast<double*>(x), tol, max_iter,
+                                      hb_s_L, hb_s_U, iters, relres, info, ws, st));
+}
+
+}  // extern "C"

@@ -1,0 +1,43 @@
+"""Helpers for the GPU parity tests (layout conversion only)."""
+import sys
+
+import numpy as np
+import torch
+
+from paper_1804_09666_amd import workloads as wl
+
+KEYS = ("e", "c", "d", "a", "b", "y")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_device(ws, batch, ld=None, corner_nan=False, pad_fill=0.0, dtype=torch.float64):
+    """System-contiguous numpy batch -> dict of [n, ld] device tensors."""
+    n = ws["d"].shape[1]
+    out = {}
+    for k in KEYS:
+        arr = np.array(ws[k], dtype=np.float64, copy=True)
+        if corner_nan and k in ("e", "c", "a", "b"):
+            me, mc, ma, mb = wl.corner_mask(n)
+            mask = dict(e=me, c=mc, a=ma, b=mb)[k]
+            arr[:, ~mask] = np.nan
+        out[k] = torch.from_numpy(wl.interleave(arr, ld, fill=pad_fill)).to("cuda", dtype)
+    return out
+
+
+def diags_of(t, kind=5):
+    if kind == 5:
+        return [t["e"], t["c"], t["d"], t["a"], t["b"]]
+    return [None, t["c"], t["d"], t["a"], None]
+
+
+def host(t, batch):
+    return wl.deinterleave(t.cpu().numpy().astype(np.float64), batch)
+
+
+def rel_err(x, ref):
+    """Per-system ||x - ref||_inf / ||ref||_inf."""
+    return np.abs(x - ref).max(axis=1) / np.maximum(np.abs(ref).max(axis=1), 1e-300)

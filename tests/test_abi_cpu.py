@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/bandsolve.h declares, sizes workspaces, and rejects bad
+arguments before it touches the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bandsolve.h")
+
+
+@pytest.fixture(scope="module")
+def bs():
+    from paper_1804_09666_amd import bandsolve
+    if not os.path.exists(bandsolve.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return bandsolve
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(bs):
+    lib = bs.load()
+    names = header_functions()
+    assert set(names) == set(bs.EXPORTED), names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings_and_version(bs):
+    assert bs.status_str(0) == "BS_OK"
+    assert "invalid" in bs.status_str(1)
+    assert "unknown" in bs.status_str(99)
+    assert bs.load().bs_version() >= 100
+
+
+def test_workspace_query(bs):
+    n, batch = 1000, 100
+    lw = 128
+    assert bs.workspace_bytes(bs.OP_FACTOR, 5, n, batch) == 0
+    assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 3, n, batch) == 0
+    assert bs.workspace_bytes(bs.OP_SIP, 5, n, batch) == 5 * n * lw * 8
+    assert bs.workspace_bytes(bs.OP_MNPDM, 5, n, batch) == 2 * n * lw * 8
+    assert bs.workspace_bytes(bs.OP_SOLVE, 5, n, batch) in (0, 2 * n * lw * 8)
+    assert bs.workspace_bytes(bs.OP_SOLVE, 3, n, batch) in (0, n * lw * 8)
+    lib = bs.load()
+    bad = ctypes.c_size_t(-1).value
+    assert lib.bs_workspace_bytes(bs.OP_SOLVE, 4, 0, n, batch) == bad
+    assert lib.bs_workspace_bytes(bs.OP_SOLVE, 5, 0, 0, batch) == bad
+    assert lib.bs_workspace_bytes(99, 5, 0, n, batch) == bad
+
+
+def _fake(k):
+    return ctypes.c_void_p(0x10000 * (k + 1))
+
+
+def test_invalid_arguments_rejected_on_host(bs):
+    lib = bs.load()
+    d5 = lib.VP5(*[_fake(k) for k in range(5)])
+    x, y, info, ws = _fake(7), _fake(8), _fake(9), _fake(10)
+    n, batch, ld = 16, 8, 8
+    big = ctypes.c_size_t(1 << 40)
+    E = bs.BS_EINVAL
+    # band_solve
+    assert lib.band_solve(4, 0, n, batch, ld, d5, None, y, x, info, ws, big, None) == E
+    assert lib.band_solve(5, 2, n, batch, ld, d5, None, y, x, info, ws, big, None) == E
+    assert lib.band_solve(5, 0, 0, batch, ld, d5, None, y, x, info, ws, big, None) == E
+    assert lib.band_solve(5, 0, n, 0, ld, d5, None, y, x, info, ws, big, None) == E
+    assert lib.band_solve(5, 0, n, batch, batch - 1, d5, None, y, x, info, ws, big, None) == E
+    assert lib.band_solve(5, 0, n, batch, ld, d5, None, None, x, info, ws, big, None) == E
+    assert lib.band_solve(5, 0, n, batch, ld, d5, None, y, None, info, ws, big, None) == E
+    assert lib.band_solve(5, 0, n, batch, ld, d5, None, y, x, None, ws, big, None) == E
+    mis = ctypes.c_void_p(0x10004)
+    assert lib.band_solve(5, 0, n, batch, ld, d5, None, mis, x, info, ws, big, None) == E
+    nulle = lib.VP5(None, _fake(1), _fake(2), _fake(3), None)
+    assert lib.band_solve(5, 0, n, batch, ld, nulle, None, y, x, info, ws, big, None) == E
+    need = bs.workspace_bytes(bs.OP_SOLVE, 5, n, batch)
+    if need:
+        assert lib.band_solve(5, 0, n, batch, ld, d5, None, y, x, info, ws, need - 1,
+                              None) == bs.BS_EWORKSPACE
+    # band_factor
+    assert lib.band_factor(5, 0, n, batch, ld, d5, None, info, None) == E
+    assert lib.band_factor(6, 0, n, batch, ld, d5, x, info, None) == E
+    # band_solve_mnpdm
+    d3 = lib.VP3(_fake(1), _fake(2), _fake(3))
+    assert lib.band_solve_mnpdm(0, n, batch, ld, d3, -1, None, None, None, y, x, info, ws,
+                                big, None) == E
+    assert lib.band_solve_mnpdm(0, n, batch, ld, d3, 2, None, None, None, y, x, info, ws,
+                                big, None) == E
+    assert lib.band_solve_mnpdm(0, n, batch, ld, d3, 0, None, None, None, y, x, info, ws,
+                                0, None) == bs.BS_EWORKSPACE
+    # sip_solve
+    it, rr = _fake(11), _fake(12)
+    assert lib.sip_solve(0, n, batch, ld, d5, None, y, x, 0.0, 10, 1, 1, it, rr, info, ws,
+                         big, None) == E
+    assert lib.sip_solve(0, n, batch, ld, d5, None, y, x, 1e-10, -1, 1, 1, it, rr, info, ws,
+                         big, None) == E
+    assert lib.sip_solve(0, 1000, batch, ld, d5, None, y, x, 1e-10, 5, 7, 1, it, rr, info,
+                         ws, big, None) == E           # 2^7 < 1000 and s > 6
+    assert lib.sip_solve(0, n, batch, ld, d5, None, y, x, 1e-10, 5, 1, 1, it, rr, info, ws,
+                         0, None) == bs.BS_EWORKSPACE
+
+
+@pytest.mark.skipif(__import__("torch").cuda.is_available(), reason="needs a machine without GPU")
+def test_valid_call_without_device_reports_enodev(bs):
+    lib = bs.load()
+    d5 = lib.VP5(*[_fake(k) for k in range(5)])
+    st = lib.band_factor(5, 0, 16, 8, 8, d5, _fake(7), _fake(9), None)
+    assert st == bs.BS_ENODEV
