@@ -47,6 +47,8 @@
  *            1e3 * max(1, relative residual of x0))
  *    -3      MNPDM: the outer-entry list of the system is not strictly
  *            ascending or names a row outside 0..n-1
+ *    -4      split-row band_solve: the blocks that share the system did not
+ *            all arrive within about a second (x unspecified)
  */
 #ifndef BANDSOLVE_H
 #define BANDSOLVE_H
@@ -82,11 +84,34 @@ const char* bs_status_str(int32_t status);
 /* Library ABI version (major*100 + minor). */
 int32_t bs_version(void);
 
-/* Bytes of device workspace the call `op` needs for (kind, dtype, n, batch);
- * 0 when it needs none.  Returns (size_t)-1 for arguments the call would
- * reject.  Host-only, never touches the GPU. */
+/* Bytes of device workspace the call `op` needs for (kind, dtype, n, batch,
+ * ld) under the current options; 0 when it needs none.  Returns (size_t)-1
+ * for arguments the call would reject.  Host-only, never touches the GPU. */
 size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
-                          int64_t batch);
+                          int64_t batch, int64_t ld);
+
+/* Process-wide tuning options (not per-call state; read at every call).
+ *   BS_OPT_DIRECT_PATH     fused band_solve kernel: 0 auto (default), 1 one
+ *                          lane per system, 2 rows of a system split over
+ *                          lanes where the variant supports n (else 1)
+ *   BS_OPT_PART_PD_VARIANT index of the split-row PD kernel variant
+ *   BS_OPT_PART_TD_VARIANT index of the split-row TD kernel variant
+ * bs_set_option returns BS_EINVAL for an unknown key or a value out of range;
+ * bs_get_option returns -1 for an unknown key. */
+enum bs_option_code {
+  BS_OPT_DIRECT_PATH = 0,
+  BS_OPT_PART_PD_VARIANT = 1,
+  BS_OPT_PART_TD_VARIANT = 2
+};
+int32_t bs_set_option(int32_t key, int64_t value);
+int64_t bs_get_option(int32_t key);
+
+/* Shape of split-row variant `index` of `kind`: shape[0] = rows per lane M,
+ * shape[1] = lanes per system in a block PW (a tile of M*PW rows),
+ * shape[2] = systems per block G, shape[3] = most tiles per system TMAX (the
+ * variant handles 8 <= n <= M*PW*TMAX).  BS_EINVAL if there is no such
+ * variant. */
+int32_t bs_part_variant(int32_t kind, int32_t index, int32_t shape[4]);
 
 /* ILU(0) of every system: the band Doolittle factorization A = L U with L
  * unit lower (l2, l1 on diagonals -2, -1) and U upper (u0, u1, u2 on 0, +1,
@@ -115,7 +140,12 @@ int32_t band_factor(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
  * factors != NULL: substitution with the factors of band_factor (same kind
  *   and layout): L z = rhs, U x = z.  info[s] is set to 0.
  * workspace / ws_bytes: as bs_workspace_bytes(BS_OP_SOLVE or
- *   BS_OP_SOLVE_FACTORED, ...); may be NULL / 0 when that is 0. */
+ *   BS_OP_SOLVE_FACTORED, ...); may be NULL / 0 when that is 0.  When the
+ *   rows of a system span several blocks, the blocks meet at counters in the
+ *   workspace: its contents must be zero before its first use with
+ *   band_solve, and every completed call leaves them zero again (after an
+ *   info of -4 -- blocks of a system that failed to meet -- zero it again).
+ *   Calls that share one workspace must not run concurrently. */
 int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
                    int64_t ld, const void* const diags[5], const void* factors,
                    const void* rhs, void* x, int32_t* info, void* workspace,

@@ -24,8 +24,11 @@ BS_OK, BS_EINVAL, BS_ELAUNCH, BS_EWORKSPACE, BS_ENODEV = range(5)
 BS_F64, BS_F32 = 0, 1
 OP_FACTOR, OP_SOLVE, OP_SOLVE_FACTORED, OP_MNPDM, OP_SIP = range(5)
 
-EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "band_factor",
-            "band_solve", "band_solve_mnpdm", "sip_solve")
+EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "bs_set_option",
+            "bs_get_option", "bs_part_variant", "band_factor", "band_solve",
+            "band_solve_mnpdm", "sip_solve")
+OPT_DIRECT_PATH, OPT_PART_PD_VARIANT, OPT_PART_TD_VARIANT = range(3)
+PATH_AUTO, PATH_LANE, PATH_PART = range(3)
 
 
 class BandSolveError(RuntimeError):
@@ -51,7 +54,10 @@ def load():
     sig = {
         "bs_status_str": (ctypes.c_char_p, [i32]),
         "bs_version": (i32, []),
-        "bs_workspace_bytes": (sz, [i32, i32, i32, i64, i64]),
+        "bs_workspace_bytes": (sz, [i32, i32, i32, i64, i64, i64]),
+        "bs_set_option": (i32, [i32, i64]),
+        "bs_get_option": (i64, [i32]),
+        "bs_part_variant": (i32, [i32, i32, ctypes.POINTER(i32)]),
         "band_factor": (i32, [i32, i32, i64, i64, i64, vp5, vp, vp, vp]),
         "band_solve": (i32, [i32, i32, i64, i64, i64, vp5, vp, vp, vp, vp, vp, sz, vp]),
         "band_solve_mnpdm": (i32, [i32, i64, i64, i64, vp3, i32, vp, vp, vp, vp, vp,
@@ -73,8 +79,28 @@ def status_str(status):
     return load().bs_status_str(int(status)).decode()
 
 
-def workspace_bytes(op, kind, n, batch, dtype=BS_F64):
-    v = load().bs_workspace_bytes(op, kind, dtype, n, batch)
+def set_option(key, value):
+    st = load().bs_set_option(int(key), int(value))
+    if st != BS_OK:
+        raise BandSolveError(st, f"bs_set_option({key}, {value})")
+
+
+def get_option(key):
+    return int(load().bs_get_option(int(key)))
+
+
+def part_variants(kind):
+    """[(M, PW, G, TMAX), ...] of the compiled split-row variants of `kind`."""
+    out = []
+    shape = (ctypes.c_int32 * 4)()
+    while load().bs_part_variant(kind, len(out), shape) == BS_OK:
+        out.append(tuple(shape))
+    return out
+
+
+def workspace_bytes(op, kind, n, batch, dtype=BS_F64, ld=None):
+    ld = batch if ld is None else ld
+    v = load().bs_workspace_bytes(op, kind, dtype, n, batch, ld)
     if v == ctypes.c_size_t(-1).value:
         raise BandSolveError(BS_EINVAL, "bs_workspace_bytes")
     return v
@@ -123,9 +149,11 @@ def _prep(diags, rhs, kind, batch):
 
 
 def _ws(nbytes, device):
+    """Workspace for one call; zero-filled (the split-row solver's counters
+    must start at zero)."""
     if nbytes == 0:
         return None
-    return torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device)
+    return torch.zeros((nbytes + 7) // 8, dtype=torch.float64, device=device)
 
 
 def _raise(st, what):
@@ -159,7 +187,7 @@ def solve(diags, rhs, x=None, *, kind=None, batch=None, factors=None, info=None,
     _check2d(x, "x", n, dtype)
     info = torch.empty(batch, dtype=torch.int32, device=dev) if info is None else info
     op = OP_SOLVE if factors is None else OP_SOLVE_FACTORED
-    nbytes = workspace_bytes(op, kind, n, batch, _dtype_code(dtype))
+    nbytes = workspace_bytes(op, kind, n, batch, _dtype_code(dtype), ld)
     if workspace is None:
         workspace = _ws(nbytes, dev)
     st = lib.band_solve(kind, _dtype_code(dtype), n, batch, ld,
@@ -191,7 +219,7 @@ def solve_mnpdm(cda, outer_row, outer_e, outer_b, rhs, x=None, *, batch=None,
     dev = rhs.device
     x = torch.empty_like(rhs) if x is None else x
     info = torch.empty(batch, dtype=torch.int32, device=dev) if info is None else info
-    nbytes = workspace_bytes(OP_MNPDM, 5, n, batch)
+    nbytes = workspace_bytes(OP_MNPDM, 5, n, batch, ld=ld)
     workspace = _ws(nbytes, dev) if workspace is None else workspace
     st = lib.band_solve_mnpdm(BS_F64, n, batch, ld, lib.VP3(*[_ptr(t) for t in cda]), kmax,
                               _ptr(outer_row) if kmax else None,
@@ -217,7 +245,7 @@ def sip(diags, rhs, x0=None, *, tol, max_iter, s_L=-1, s_U=-1, factors=None,
     iters = torch.empty(batch, dtype=torch.int32, device=dev)
     relres = torch.empty(batch, dtype=torch.float64, device=dev)
     info = torch.empty(batch, dtype=torch.int32, device=dev)
-    nbytes = workspace_bytes(OP_SIP, 5, n, batch)
+    nbytes = workspace_bytes(OP_SIP, 5, n, batch, ld=ld)
     workspace = _ws(nbytes, dev) if workspace is None else workspace
     st = lib.sip_solve(BS_F64, n, batch, ld, lib.VP5(*[_ptr(t) for t in diags]),
                        _ptr(factors), _ptr(rhs), _ptr(x), float(tol), int(max_iter),

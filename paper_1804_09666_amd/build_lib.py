@@ -5,6 +5,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libbandsolve.so")
 ARCH = "gfx950"
 
@@ -27,12 +28,12 @@ def sources():
 def build(force: bool = True, verbose: bool = False) -> str:
     srcs = sources()
     deps = srcs + glob.glob(os.path.join(CSRC, "*.h")) + \
-        [os.path.join(HERE, "..", "include", "bandsolve.h")]
+        [os.path.join(INCLUDE, "bandsolve.h")]
     if not force and os.path.exists(LIB) and \
             os.path.getmtime(LIB) >= max(os.path.getmtime(p) for p in deps):
         return LIB
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, *srcs, "-o", tmp]
+    cmd = ["hipcc", *HIPCC_FLAGS, f"-I{INCLUDE}", *srcs, "-o", tmp]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -8,7 +8,9 @@
 #include <stdint.h>
 #include <string.h>
 
-#include "../../include/bandsolve.h"
+#include <atomic>
+
+#include "bandsolve.h"
 #include "bs_internal.h"
 
 namespace {
@@ -54,10 +56,22 @@ bs::Diags as_diags(int32_t kind, const void* const diags[5]) {
   return A;
 }
 
-// Scratch arrays of n * ws_ld(batch) elements each a variant streams through.
-int64_t solve_ws_planes(int32_t kind, int64_t n, int64_t batch) {
-  if (bs::part_supported(kind, n, batch)) return 0;
-  return kind == 5 ? 2 : 1;  // alpha (+ beta); z is kept in x
+// Tuning options (process-wide).
+std::atomic<int64_t> g_direct_path{0};
+std::atomic<int64_t> g_pd_variant{0}, g_td_variant{0};
+
+int part_idx(int32_t kind) { return (int)(kind == 5 ? g_pd_variant.load() : g_td_variant.load()); }
+
+bool use_part(int32_t kind, int64_t n, int64_t batch, int64_t ld) {
+  if (g_direct_path.load() == 1) return false;
+  return bs::part_supported(kind, part_idx(kind), n, batch, ld);
+}
+
+size_t solve_ws_bytes(int32_t kind, int64_t n, int64_t batch, int64_t ld) {
+  if (use_part(kind, n, batch, ld))
+    return bs::part_workspace_bytes(kind, part_idx(kind), n, batch);
+  const int64_t planes = kind == 5 ? 2 : 1;  // alpha (+ beta); z is kept in x
+  return (size_t)(planes * n * bs::ws_ld(batch)) * 8;
 }
 
 int32_t launched(hipError_t e) { return e == hipSuccess ? BS_OK : BS_ELAUNCH; }
@@ -84,17 +98,52 @@ const char* bs_status_str(int32_t status) {
 
 int32_t bs_version(void) { return 100; }
 
+int32_t bs_set_option(int32_t key, int64_t value) {
+  switch (key) {
+    case BS_OPT_DIRECT_PATH:
+      if (value < 0 || value > 2) return BS_EINVAL;
+      g_direct_path = value;
+      return BS_OK;
+    case BS_OPT_PART_PD_VARIANT:
+    case BS_OPT_PART_TD_VARIANT: {
+      const int kind = key == BS_OPT_PART_PD_VARIANT ? 5 : 3;
+      if (value < 0 || value >= bs::part_variant_count(kind)) return BS_EINVAL;
+      (kind == 5 ? g_pd_variant : g_td_variant) = value;
+      return BS_OK;
+    }
+    default:
+      return BS_EINVAL;
+  }
+}
+
+int64_t bs_get_option(int32_t key) {
+  switch (key) {
+    case BS_OPT_DIRECT_PATH: return g_direct_path.load();
+    case BS_OPT_PART_PD_VARIANT: return g_pd_variant.load();
+    case BS_OPT_PART_TD_VARIANT: return g_td_variant.load();
+    default: return -1;
+  }
+}
+
+int32_t bs_part_variant(int32_t kind, int32_t index, int32_t shape[4]) {
+  if (!kind_ok(kind) || shape == nullptr) return BS_EINVAL;
+  int out[4];
+  if (!bs::part_variant_shape(kind, index, out)) return BS_EINVAL;
+  for (int q = 0; q < 4; ++q) shape[q] = out[q];
+  return BS_OK;
+}
+
 size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
-                          int64_t batch) {
+                          int64_t batch, int64_t ld) {
   const size_t bad = (size_t)-1;
-  if (!shape_ok(n, batch, batch)) return bad;
+  if (!shape_ok(n, batch, ld)) return bad;
   if (dtype != BS_F64) return bad;
   const int64_t plane = n * bs::ws_ld(batch);
   switch (op) {
     case BS_OP_FACTOR:
       return kind_ok(kind) ? 0 : bad;
     case BS_OP_SOLVE:
-      return kind_ok(kind) ? (size_t)(solve_ws_planes(kind, n, batch) * plane) * 8 : bad;
+      return kind_ok(kind) ? solve_ws_bytes(kind, n, batch, ld) : bad;
     case BS_OP_SOLVE_FACTORED:
       return kind_ok(kind) ? 0 : bad;
     case BS_OP_MNPDM:
@@ -139,14 +188,15 @@ int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
                                           static_cast<const double*>(rhs),
                                           static_cast<double*>(x), info, st));
   }
-  const size_t need = bs_workspace_bytes(BS_OP_SOLVE, kind, dtype, n, batch);
+  const size_t need = bs_workspace_bytes(BS_OP_SOLVE, kind, dtype, n, batch, ld);
   if (ws_bytes < need) return BS_EWORKSPACE;
   if (need > 0 && !array_ok(workspace, dtype)) return BS_EINVAL;
   if (!have_device()) return BS_ENODEV;
-  if (bs::part_supported(kind, n, batch))
-    return launched(bs::launch_part(kind, n, batch, ld, A,
+  if (use_part(kind, n, batch, ld))
+    return launched(bs::launch_part(kind, part_idx(kind), n, batch, ld, A,
                                     static_cast<const double*>(rhs),
-                                    static_cast<double*>(x), info, st));
+                                    static_cast<double*>(x), info,
+                                    static_cast<double*>(workspace), st));
   double* ws = static_cast<double*>(workspace);
   if (kind == 5)
     return launched(bs::launch_npdm_lane(n, batch, ld, A,
@@ -171,7 +221,7 @@ int32_t band_solve_mnpdm(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
   if (kmax > 0 && (outer_row == nullptr || !aligned(outer_row, 4) ||
                    !array_ok(outer_e, dtype) || !array_ok(outer_b, dtype)))
     return BS_EINVAL;
-  const size_t need = bs_workspace_bytes(BS_OP_MNPDM, 5, dtype, n, batch);
+  const size_t need = bs_workspace_bytes(BS_OP_MNPDM, 5, dtype, n, batch, ld);
   if (ws_bytes < need) return BS_EWORKSPACE;
   if (!array_ok(workspace, dtype)) return BS_EINVAL;
   if (!have_device()) return BS_ENODEV;
@@ -207,7 +257,7 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
   };
   if (!s_ok(hb_s_L) || !s_ok(hb_s_U)) return BS_EINVAL;
   if (factors != nullptr && !array_ok(factors, dtype)) return BS_EINVAL;
-  const size_t need = bs_workspace_bytes(BS_OP_SIP, 5, dtype, n, batch);
+  const size_t need = bs_workspace_bytes(BS_OP_SIP, 5, dtype, n, batch, ld);
   if (ws_bytes < need) return BS_EWORKSPACE;
   if (!array_ok(workspace, dtype)) return BS_EINVAL;
   if (!have_device()) return BS_ENODEV;

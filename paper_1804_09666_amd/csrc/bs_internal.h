@@ -40,11 +40,15 @@ hipError_t launch_subst_lane(int kind, int64_t n, int64_t batch, int64_t ld,
                              double* x, int32_t* info, hipStream_t st);
 
 // ---- direct solvers, rows of a system split over lanes (direct_part.hip) --
-// Returns true when the partitioned kernel handles (kind, n, batch).
-bool part_supported(int kind, int64_t n, int64_t batch);
-hipError_t launch_part(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
-                       const double* y, double* x, int32_t* info,
-                       hipStream_t st);
+// Variant idx of a kind: M rows per lane, PW lanes per system in a block
+// (one tile of M*PW rows), G systems per block, up to TMAX tiles per system.
+int part_variant_count(int kind);
+bool part_variant_shape(int kind, int idx, int out[4]);
+bool part_supported(int kind, int idx, int64_t n, int64_t batch, int64_t ld);
+size_t part_workspace_bytes(int kind, int idx, int64_t n, int64_t batch);
+hipError_t launch_part(int kind, int idx, int64_t n, int64_t batch, int64_t ld,
+                       Diags A, const double* y, double* x, int32_t* info,
+                       double* ws, hipStream_t st);
 
 // ---- SIP (sip_lane.hip) --------------------------------------------------
 hipError_t launch_sip_lane(int64_t n, int64_t batch, int64_t ld, Diags A,

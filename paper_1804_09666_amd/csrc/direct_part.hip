@@ -1,12 +1,648 @@
-// direct_part.hip -- partitioned (multi-lane per system) direct solvers.
+// direct_part.hip -- NPDM / NTDM with the rows of each system split over many
+// lanes, for batches too small to fill the GPU with one lane per system.
+//
+// Method (partitioned elimination).  System s is cut into P chunks of M rows;
+// lane (s, j) owns chunk j.  Rows past n are identity rows, which leave the
+// solution of the real rows unchanged.
+//   1. The lane loads its M rows of e, c, d, a, b, y into registers (one
+//      coalesced segment per row and group of G systems) and runs the NPDM
+//      recurrences (the LU of Sec. 1 of Veneva & Ayriyan, arXiv:1804.09666)
+//      on its chunk alone.  The couplings to the two rows before the chunk
+//      (x_L) and the two rows after it (x_R) are carried as extra right-hand
+//      sides, so after the back substitution every row of the chunk reads
+//          x_r = p_r - V_r x_L - W_r x_R.
+//      Rows 0, 1 and M-2, M-1 of (p, V, W) form the chunk's affine map from
+//      (x_L, x_R) to its top pair T and bottom pair B.
+//   2. Neighbouring maps are merged pairwise up a binary tree in LDS: merging
+//      eliminates the interface pair (bottom of the left part, top of the
+//      right part) with one NB x NB solve, and the node keeps the
+//      affine expressions of that interface in terms of the outer x_L, x_R.
+//      The root has no outer couplings (x_L = x_R = 0 at the system ends);
+//      walking back down the tree hands every chunk its own x_L, x_R.
+//   3. Each lane writes x_r = p_r - V_r x_L - W_r x_R for its rows.
+// Inputs are read once and x written once: nothing goes through global
+// scratch.  NB = 2 for pentadiagonal, 1 for tridiagonal systems.
+//
+// Block -> system-group mapping is XCD-aware: consecutive system groups
+// (which share 128-byte lines of every row) go to the same XCD, so the line
+// is fetched from HBM once and served from that XCD's L2 to its neighbours.
+#include <climits>
+
 #include "bs_internal.h"
 
 namespace bs {
+namespace {
 
-bool part_supported(int, int64_t, int64_t) { return false; }
+template <int NB>
+struct Map {  // T = pt - Vt xL - Wt xR,  B = pb - Vb xL - Wb xR
+  double pt[NB], pb[NB];
+  double Vt[NB][NB], Vb[NB][NB], Wt[NB][NB], Wb[NB][NB];
+};
 
-hipError_t launch_part(int, int64_t, int64_t, int64_t, Diags, const double*,
-                       double*, int32_t*, hipStream_t) {
+template <int NB>
+struct Node {  // interface: B_A = g0 + G1 xL + G2 xR,  T_B = h0 + H1 xL + H2 xR
+  double g0[NB], h0[NB];
+  double G1[NB][NB], G2[NB][NB], H1[NB][NB], H2[NB][NB];
+};
+
+template <int NB>
+constexpr int kRecSz = 2 * NB + 4 * NB * NB;  // doubles per Map or Node
+
+template <int NB>
+__device__ inline void mm(const double (&A)[NB][NB], const double (&B)[NB][NB],
+                          double (&C)[NB][NB]) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) acc = fma(A[i][k], B[k][j], acc);
+      C[i][j] = acc;
+    }
+}
+
+template <int NB>
+__device__ inline void mv(const double (&A)[NB][NB], const double (&x)[NB],
+                          double (&y)[NB]) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) acc = fma(A[i][k], x[k], acc);
+    y[i] = acc;
+  }
+}
+
+// Inverse of a 1x1 or 2x2 block; false if singular or not finite.
+__device__ inline bool inv(const double (&M)[1][1], double (&R)[1][1]) {
+  R[0][0] = 1.0 / M[0][0];
+  return M[0][0] != 0.0 && isfinite(R[0][0]);
+}
+__device__ inline bool inv(const double (&M)[2][2], double (&R)[2][2]) {
+  const double det = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+  const double r = 1.0 / det;
+  R[0][0] = M[1][1] * r;
+  R[0][1] = -M[0][1] * r;
+  R[1][0] = -M[1][0] * r;
+  R[1][1] = M[0][0] * r;
+  return det != 0.0 && isfinite(r);
+}
+
+// Merge left part A with right part B (B's x_L is A's bottom pair, A's x_R
+// is B's top pair).  Returns false if the interface block is singular.
+template <int NB>
+__device__ bool merge(const Map<NB>& A, const Map<NB>& B, Map<NB>& AB, Node<NB>& nd) {
+  double Mx[NB][NB], S[NB][NB], T1[NB][NB], t[NB];
+  mm<NB>(A.Wb, B.Vt, Mx);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) Mx[i][j] = (i == j ? 1.0 : 0.0) - Mx[i][j];
+  const bool ok = inv(Mx, S);
+  mv<NB>(A.Wb, B.pt, t);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) t[i] = A.pb[i] - t[i];
+  mv<NB>(S, t, nd.g0);
+  mm<NB>(S, A.Vb, nd.G1);
+  mm<NB>(A.Wb, B.Wt, T1);
+  mm<NB>(S, T1, nd.G2);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) nd.G1[i][j] = -nd.G1[i][j];
+  mv<NB>(B.Vt, nd.g0, t);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) nd.h0[i] = B.pt[i] - t[i];
+  mm<NB>(B.Vt, nd.G1, nd.H1);
+  mm<NB>(B.Vt, nd.G2, nd.H2);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      nd.H1[i][j] = -nd.H1[i][j];
+      nd.H2[i][j] = -(nd.H2[i][j] + B.Wt[i][j]);
+    }
+  Map<NB> R;
+  mv<NB>(A.Wt, nd.h0, t);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) R.pt[i] = A.pt[i] - t[i];
+  mm<NB>(A.Wt, nd.H1, T1);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) R.Vt[i][j] = A.Vt[i][j] + T1[i][j];
+  mm<NB>(A.Wt, nd.H2, R.Wt);
+  mv<NB>(B.Vb, nd.g0, t);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) R.pb[i] = B.pb[i] - t[i];
+  mm<NB>(B.Vb, nd.G1, R.Vb);
+  mm<NB>(B.Vb, nd.G2, T1);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) R.Wb[i][j] = T1[i][j] + B.Wb[i][j];
+  AB = R;
+  return ok;
+}
+
+template <typename R>
+__device__ inline void store_rec(const R& r, double* dst) {
+  const double* src = reinterpret_cast<const double*>(&r);
+#pragma unroll
+  for (int q = 0; q < (int)(sizeof(R) / sizeof(double)); ++q) dst[q] = src[q];
+}
+template <typename R>
+__device__ inline void load_rec(R& r, const double* src) {
+  double* dst = reinterpret_cast<double*>(&r);
+#pragma unroll
+  for (int q = 0; q < (int)(sizeof(R) / sizeof(double)); ++q) dst[q] = src[q];
+}
+
+__device__ inline bool bad_pivot(double m) { return !(m != 0.0) || !isfinite(m); }
+
+__device__ inline double ldg(const double* __restrict__ base, uint32_t byte_off) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+__device__ inline void stg(double* __restrict__ base, uint32_t byte_off, double v) {
+  *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+
+// Chunk of a pentadiagonal system: local NPDM with the couplings to
+// x_L = (x_{-2}, x_{-1}) (entries e_0, c_0 of row 0 and e_1 of row 1) and to
+// x_R = (x_M, x_{M+1}) (b_{M-2} of row M-2, a_{M-1} and b_{M-1} of row M-1)
+// as right-hand sides.  On return p, v0, v1, w0, w1 hold U^{-1} L^{-1} of
+// y and of the coupling columns; `bad` is the first local row with a bad
+// pivot (M if none).
+template <int M>
+__device__ inline void chunk_pd(const double (&e)[M], const double (&c)[M],
+                                const double (&d)[M], const double (&a)[M],
+                                const double (&b)[M], const double (&y)[M],
+                                double (&p)[M], double (&v0)[M], double (&v1)[M],
+                                double (&w0)[M], double (&w1)[M], int& bad) {
+  double al[M], be[M];
+  double fm2 = 0.0;  // L^{-1} of the x_M column at row M-2
+  bad = M;
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    double ga, mu;
+    if (r == 0) {
+      ga = 0.0;
+      mu = d[0];
+    } else if (r == 1) {
+      ga = c[1];
+      mu = fma(-al[0], ga, d[1]);
+    } else {
+      ga = fma(-al[r - 2], e[r], c[r]);
+      mu = fma(-al[r - 1], ga, fma(-be[r - 2], e[r], d[r]));
+    }
+    if (bad == M && bad_pivot(mu)) bad = r;
+    const double rc = 1.0 / mu;
+    if (r == 0)
+      al[0] = a[0] * rc;
+    else if (r <= M - 2)
+      al[r] = fma(-be[r - 1], ga, a[r]) * rc;
+    else
+      al[r] = 0.0;
+    be[r] = (r <= M - 3) ? b[r] * rc : 0.0;
+    if (r == 0) {
+      p[0] = y[0] * rc;
+      v0[0] = e[0] * rc;
+      v1[0] = c[0] * rc;
+    } else if (r == 1) {
+      p[1] = fma(-ga, p[0], y[1]) * rc;
+      v0[1] = (-ga * v0[0]) * rc;
+      v1[1] = fma(-ga, v1[0], e[1]) * rc;
+    } else {
+      p[r] = fma(-ga, p[r - 1], fma(-e[r], p[r - 2], y[r])) * rc;
+      v0[r] = fma(-ga, v0[r - 1], -e[r] * v0[r - 2]) * rc;
+      v1[r] = fma(-ga, v1[r - 1], -e[r] * v1[r - 2]) * rc;
+    }
+    if (r == M - 2) fm2 = b[M - 2] * rc;
+    if (r == M - 1) {
+      w0[M - 1] = fma(-ga, fm2, a[M - 1]) * rc;
+      w1[M - 1] = b[M - 1] * rc;
+    }
+  }
+  w0[M - 2] = fma(-al[M - 2], w0[M - 1], fm2);
+  w1[M - 2] = -al[M - 2] * w1[M - 1];
+  p[M - 2] = fma(-al[M - 2], p[M - 1], p[M - 2]);
+  v0[M - 2] = fma(-al[M - 2], v0[M - 1], v0[M - 2]);
+  v1[M - 2] = fma(-al[M - 2], v1[M - 1], v1[M - 2]);
+#pragma unroll
+  for (int r = M - 3; r >= 0; --r) {
+    p[r] = fma(-be[r], p[r + 2], fma(-al[r], p[r + 1], p[r]));
+    v0[r] = fma(-be[r], v0[r + 2], fma(-al[r], v0[r + 1], v0[r]));
+    v1[r] = fma(-be[r], v1[r + 2], fma(-al[r], v1[r + 1], v1[r]));
+    w0[r] = fma(-be[r], w0[r + 2], -al[r] * w0[r + 1]);
+    w1[r] = fma(-be[r], w1[r + 2], -al[r] * w1[r + 1]);
+  }
+}
+
+// Chunk of a tridiagonal system: local Thomas with the couplings to x_{-1}
+// (c_0 of row 0) and x_M (a_{M-1} of row M-1) as right-hand sides.
+template <int M>
+__device__ inline void chunk_td(const double (&c)[M], const double (&d)[M],
+                                const double (&a)[M], const double (&y)[M],
+                                double (&p)[M], double (&v0)[M], double (&w0)[M],
+                                int& bad) {
+  double al[M];
+  bad = M;
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    const double mu = (r == 0) ? d[0] : fma(-al[r - 1], c[r], d[r]);
+    if (bad == M && bad_pivot(mu)) bad = r;
+    const double rc = 1.0 / mu;
+    al[r] = (r <= M - 2) ? a[r] * rc : 0.0;
+    if (r == 0) {
+      p[0] = y[0] * rc;
+      v0[0] = c[0] * rc;
+    } else {
+      p[r] = fma(-c[r], p[r - 1], y[r]) * rc;
+      v0[r] = (-c[r] * v0[r - 1]) * rc;
+    }
+    if (r == M - 1) w0[M - 1] = a[M - 1] * rc;
+  }
+#pragma unroll
+  for (int r = M - 2; r >= 0; --r) {
+    p[r] = fma(-al[r], p[r + 1], p[r]);
+    v0[r] = fma(-al[r], v0[r + 1], v0[r]);
+    w0[r] = -al[r] * w0[r + 1];
+  }
+}
+
+// Binary tree over NL leaf maps held by lanes (leaf, g), leaf in [0, NL);
+// lanes with leaf >= NL only take part in the barriers.  Each internal node
+// owns one record slot in s_node: the right child parks its map there, the
+// left child merges and overwrites it with the node record, and on the way
+// down the left child replaces the record with the right child's outer pairs.
+// leaf_rows: rows per leaf, row0: first row of leaf 0 (for breakdown rows).
+template <int NB, int NL, int G>
+__device__ inline void tree_up(Map<NB>& mp, int leaf, int g, double* s_node,
+                               int* s_bad, int64_t leaf_rows, int64_t row0, int64_t n) {
+  constexpr int RS = kRecSz<NB>;
+  constexpr int L = __builtin_ctz(NL);
+  const bool active = leaf < NL;
+  int node_off = 0;
+#pragma unroll
+  for (int lvl = 1; lvl <= L; ++lvl) {
+    const int stride = 1 << lvl, half = stride >> 1;
+    const int k = leaf >> lvl;
+    double* slot = s_node + ((node_off + k) * G + g) * RS;
+    if (active && (leaf & (stride - 1)) == half) store_rec(mp, slot);
+    __syncthreads();
+    if (active && (leaf & (stride - 1)) == 0) {
+      Map<NB> rb;
+      load_rec(rb, slot);
+      Node<NB> nd;
+      if (!merge<NB>(mp, rb, mp, nd)) {
+        const int64_t row = row0 + (int64_t)(leaf + half) * leaf_rows - NB;
+        if (row < n) atomicMin(&s_bad[g], (int)(row + 1));
+      }
+      store_rec(nd, slot);
+    }
+    node_off += NL >> lvl;
+  }
+}
+
+// Walk back down: on entry the lanes with leaf == 0 hold the outer pairs of
+// the whole range; on exit every lane with leaf < NL holds its leaf's pairs.
+// The caller puts a barrier between tree_up and tree_down.
+template <int NB, int NL, int G>
+__device__ inline void tree_down(double (&xl)[NB], double (&xr)[NB], int leaf, int g,
+                                 double* s_node) {
+  constexpr int RS = kRecSz<NB>;
+  constexpr int L = __builtin_ctz(NL);
+  const bool active = leaf < NL;
+  int node_off = NL - 1;
+#pragma unroll
+  for (int lvl = L; lvl >= 1; --lvl) {
+    const int stride = 1 << lvl, half = stride >> 1;
+    const int k = leaf >> lvl;
+    node_off -= NL >> lvl;
+    double* slot = s_node + ((node_off + k) * G + g) * RS;
+    if (active && (leaf & (stride - 1)) == 0) {
+      Node<NB> nd;
+      load_rec(nd, slot);
+      double ba[NB], tb[NB], t1[NB], t2[NB];
+      mv<NB>(nd.G1, xl, t1);
+      mv<NB>(nd.G2, xr, t2);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) ba[q] = nd.g0[q] + t1[q] + t2[q];
+      mv<NB>(nd.H1, xl, t1);
+      mv<NB>(nd.H2, xr, t2);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) tb[q] = nd.h0[q] + t1[q] + t2[q];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        slot[q] = ba[q];        // right part: x_L = B_A, x_R unchanged
+        slot[NB + q] = xr[q];
+        xr[q] = tb[q];          // left part: x_R = T_B
+      }
+    }
+    __syncthreads();
+    if (active && (leaf & (stride - 1)) == half) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        xl[q] = slot[q];
+        xr[q] = slot[NB + q];
+      }
+    }
+  }
+}
+
+__device__ inline unsigned ld_counter(unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Device-coherent (write-through / cache-bypassing) accesses for data that
+// blocks on other XCDs read.
+__device__ inline void st_coherent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_coherent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+constexpr int kWaitVmem = 0x0F70;  // s_waitcnt vmcnt(0): this wave's memory ops done
+
+constexpr int kBadNone = INT_MAX;
+constexpr int kTimeout = -4;
+constexpr uint64_t kWaitTicks = 100000000;  // 1 s of the 100 MHz real-time counter
+
+// One block = G systems x PW chunks of M rows = one tile of RT = M*PW rows of
+// G systems.  T <= TMAX tiles (consecutive blocks on one XCD) cover a system;
+// they exchange their tile maps through `xch` and meet at the counter pair
+// cnt[2*grp], cnt[2*grp+1] (arrivals, departures; reset by the last tile to
+// leave, so the counters are zero again after every completed call).
+template <int KIND, int M, int PW, int G, int TMAX>
+__global__ __launch_bounds__(G * PW) void part_kernel(
+    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
+    const double* __restrict__ C, const double* __restrict__ D,
+    const double* __restrict__ A, const double* __restrict__ B,
+    const double* __restrict__ Y, double* __restrict__ X,
+    int32_t* __restrict__ info, double* __restrict__ xch,
+    unsigned* __restrict__ cnt, int T) {
+  constexpr int NB = KIND == 5 ? 2 : 1;
+  constexpr int RS = kRecSz<NB>;
+  constexpr int RT = M * PW;
+  static_assert((PW & (PW - 1)) == 0 && (TMAX & (TMAX - 1)) == 0 && M >= 4, "shape");
+  __shared__ double s_node[(PW - 1) * G * RS];
+  __shared__ double s_gnode[(TMAX > 1 ? TMAX - 1 : 1) * G * RS];
+  __shared__ double s_bnd[G * 2 * NB];
+  __shared__ int s_bad[G];
+  __shared__ int s_timeout;
+
+  const int tid = threadIdx.x;
+  const int g = tid % G;
+  const int j = tid / G;
+  // block -> (system group, tile); the T tiles of a group sit on one XCD
+  int64_t grp, tile;
+  {
+    const int64_t b = blockIdx.x, nblk = gridDim.x;
+    if (nblk % (8 * T) == 0) {
+      const int64_t k = b / 8, per_xcd = nblk / 8 / T;
+      grp = (b % 8) * per_xcd + k / T;
+      tile = k % T;
+    } else {
+      grp = b / T;
+      tile = b % T;
+    }
+  }
+  const int64_t s = grp * G + g;
+  const bool live = s < batch;
+  const int64_t r0 = (tile * PW + j) * M;
+  if (tid < G) s_bad[tid] = kBadNone;
+  if (tid == 0) s_timeout = 0;
+
+  // ---- 1. load the chunk and eliminate it locally -------------------------
+  // Byte offsets fit in 32 bits (checked on the host), so every load is an
+  // SGPR base plus one per-row VGPR offset shared by the six arrays.
+  double c[M], d[M], a[M], y[M], e[M], b[M];
+  const uint32_t row_bytes = (uint32_t)(ld * 8);
+  const uint32_t off0 = (uint32_t)((r0 * ld + s) * 8);
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    const int64_t i = r0 + r;
+    const uint32_t o = off0 + (uint32_t)r * row_bytes;
+    const bool in = live && i < n;
+    d[r] = in ? ldg(D, o) : 1.0;
+    y[r] = in ? ldg(Y, o) : 0.0;
+    c[r] = (in && i >= 1) ? ldg(C, o) : 0.0;
+    a[r] = (in && i <= n - 2) ? ldg(A, o) : 0.0;
+    if (KIND == 5) {
+      e[r] = (in && i >= 2) ? ldg(E, o) : 0.0;
+      b[r] = (in && i <= n - 3) ? ldg(B, o) : 0.0;
+    } else {
+      e[r] = 0.0;
+      b[r] = 0.0;
+    }
+  }
+  double p[M], v[NB][M], w[NB][M];
+  int bad;
+  if constexpr (KIND == 5)
+    chunk_pd<M>(e, c, d, a, b, y, p, v[0], v[1], w[0], w[1], bad);
+  else
+    chunk_td<M>(c, d, a, y, p, v[0], w[0], bad);
+
+  Map<NB> mp;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    mp.pt[q] = p[q];
+    mp.pb[q] = p[M - NB + q];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      mp.Vt[q][k] = v[k][q];
+      mp.Wt[q][k] = w[k][q];
+      mp.Vb[q][k] = v[k][M - NB + q];
+      mp.Wb[q][k] = w[k][M - NB + q];
+    }
+  }
+  __syncthreads();  // s_bad initialised
+  if (bad < M && r0 + bad < n) atomicMin(&s_bad[g], (int)(r0 + bad + 1));
+
+  // ---- 2. merge the chunks of this tile ----------------------------------
+  tree_up<NB, PW, G>(mp, j, g, s_node, s_bad, M, tile * RT, n);
+
+  double xl[NB], xr[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) xl[q] = xr[q] = 0.0;  // no coupling at the ends
+  if (T > 1) {
+    // ---- 2b. exchange tile maps with the other tiles of the system ------
+    // The maps go through the device-coherent level with write-through
+    // stores and cache-bypassing loads, so no cache-wide write-back or
+    // invalidate is needed; the arrival count is bumped only after this
+    // wave's map stores have completed.
+    constexpr int XS = RS + 1;  // map + first bad row of the tile
+    if (tid < 64) {  // wave 0 holds the tile maps (lanes j == 0, tid < G)
+      if (j == 0) {
+        double* dst = xch + ((grp * T + tile) * G + g) * XS;
+        const double* src = reinterpret_cast<const double*>(&mp);
+#pragma unroll
+        for (int q = 0; q < RS; ++q) st_coherent(dst + q, src[q]);
+        st_coherent(dst + RS, (double)s_bad[g]);
+      }
+      __builtin_amdgcn_s_waitcnt(kWaitVmem);
+      if (tid == 0) {
+        atomicAdd(&cnt[2 * grp], 1u);
+        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+        while (ld_counter(&cnt[2 * grp]) < (unsigned)T) {
+          __builtin_amdgcn_s_sleep(2);
+          if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
+            s_timeout = 1;
+            break;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    Map<NB> gm;
+    if (j < TMAX) {
+      if (j < T) {
+        const double* src = xch + ((grp * T + j) * G + g) * XS;
+        double* dst = reinterpret_cast<double*>(&gm);
+#pragma unroll
+        for (int q = 0; q < RS; ++q) dst[q] = ld_coherent(src + q);
+        const double tb = ld_coherent(src + RS);
+        if (tb < (double)kBadNone) atomicMin(&s_bad[g], (int)tb);
+      } else {  // tiles past the last one: all identity rows
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          gm.pt[q] = gm.pb[q] = 0.0;
+#pragma unroll
+          for (int k = 0; k < NB; ++k) gm.Vt[q][k] = gm.Vb[q][k] = gm.Wt[q][k] = gm.Wb[q][k] = 0.0;
+        }
+      }
+    }
+    __syncthreads();  // every tile map read: this tile may leave
+    if (tid == 0) {
+      const unsigned gone = atomicAdd(&cnt[2 * grp + 1], 1u);
+      if (gone == (unsigned)T - 1) {  // last one out resets the meeting point
+        __hip_atomic_store(&cnt[2 * grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&cnt[2 * grp + 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    if constexpr (TMAX > 1) {
+      tree_up<NB, TMAX, G>(gm, j, g, s_gnode, s_bad, RT, 0, n);
+      double gl[NB], gr[NB];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) gl[q] = gr[q] = 0.0;
+      __syncthreads();
+      tree_down<NB, TMAX, G>(gl, gr, j, g, s_gnode);
+      if (j == tile) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          s_bnd[g * 2 * NB + q] = gl[q];
+          s_bnd[g * 2 * NB + NB + q] = gr[q];
+        }
+      }
+      __syncthreads();
+      if (j == 0) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          xl[q] = s_bnd[g * 2 * NB + q];
+          xr[q] = s_bnd[g * 2 * NB + NB + q];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 3. back down the tile's tree, then x = p - V x_L - W x_R ---------
+  tree_down<NB, PW, G>(xl, xr, j, g, s_node);
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    const int64_t i = r0 + r;
+    double xv = p[r];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) xv = fma(-v[k][r], xl[k], fma(-w[k][r], xr[k], xv));
+    if (live && i < n) stg(X, off0 + (uint32_t)r * row_bytes, xv);
+  }
+  if (j == 0 && tile == 0 && live) {
+    const int b0 = s_bad[g];
+    info[s] = s_timeout ? kTimeout : ((b0 == kBadNone) ? 0 : b0);
+  }
+}
+
+struct Variant {
+  int kind, M, PW, G, TMAX;
+};
+
+// Compiled variants; index 0 of each kind is the default.
+constexpr Variant kVariants[] = {
+    {5, 32, 16, 16, 4}, {5, 16, 16, 16, 8}, {5, 8, 32, 16, 8}, {5, 16, 32, 16, 4},
+    {3, 16, 32, 16, 4}, {3, 8, 64, 16, 4}, {3, 32, 16, 16, 4}, {3, 16, 16, 16, 8},
+};
+
+template <int KIND, int M, int PW, int G, int TMAX>
+hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, Diags A, const double* y,
+                      double* x, int32_t* info, double* ws, hipStream_t st) {
+  constexpr int RT = M * PW;
+  const int T = (int)((n + RT - 1) / RT);
+  const int64_t groups = (batch + G - 1) / G;
+  unsigned* cnt = (T > 1) ? reinterpret_cast<unsigned*>(ws) : nullptr;
+  double* xch = (T > 1) ? ws + (2 * groups + 1) / 2 + 1 : nullptr;
+  hipLaunchKernelGGL((part_kernel<KIND, M, PW, G, TMAX>), dim3((unsigned)(groups * T)),
+                     dim3(G * PW), 0, st, n, batch, ld, A.e, A.c, A.d, A.a, A.b, y, x,
+                     info, xch, cnt, T);
+  return hipGetLastError();
+}
+
+const Variant* find_variant(int kind, int idx) {
+  int k = 0;
+  for (const Variant& v : kVariants)
+    if (v.kind == kind && k++ == idx) return &v;
+  return nullptr;
+}
+
+}  // namespace
+
+int part_variant_count(int kind) {
+  int k = 0;
+  for (const Variant& v : kVariants) k += v.kind == kind;
+  return k;
+}
+
+bool part_variant_shape(int kind, int idx, int out[4]) {
+  const Variant* v = find_variant(kind, idx);
+  if (!v) return false;
+  out[0] = v->M;
+  out[1] = v->PW;
+  out[2] = v->G;
+  out[3] = v->TMAX;
+  return true;
+}
+
+bool part_supported(int kind, int idx, int64_t n, int64_t batch, int64_t ld) {
+  (void)batch;
+  const Variant* v = find_variant(kind, idx);
+  if (!v) return false;
+  if (n < 8 || n > (int64_t)v->M * v->PW * v->TMAX) return false;
+  // per-lane byte offsets are 32-bit
+  if ((n + 1) * ld * 8 >= (int64_t(1) << 32)) return false;
+  return true;
+}
+
+size_t part_workspace_bytes(int kind, int idx, int64_t n, int64_t batch) {
+  const Variant* v = find_variant(kind, idx);
+  if (!v) return 0;
+  const int64_t RT = (int64_t)v->M * v->PW;
+  const int64_t T = (n + RT - 1) / RT;
+  const int64_t groups = (batch + v->G - 1) / v->G;
+  const int64_t rs = (kind == 5 ? 20 : 6) + 1;
+  if (T <= 1) return 0;
+  return (size_t)(((2 * groups + 1) / 2 + 1) + groups * T * v->G * rs) * 8;
+}
+
+hipError_t launch_part(int kind, int idx, int64_t n, int64_t batch, int64_t ld,
+                       Diags A, const double* y, double* x, int32_t* info,
+                       double* ws, hipStream_t st) {
+  const Variant* v = find_variant(kind, idx);
+  if (!v) return hipErrorInvalidValue;
+#define BS_PV(K, MM, PP, GG, TT)                                                    \
+  if (v->kind == K && v->M == MM && v->PW == PP && v->G == GG && v->TMAX == TT)      \
+    return launch_cfg<K, MM, PP, GG, TT>(n, batch, ld, A, y, x, info, ws, st);
+  BS_PV(5, 32, 16, 16, 4) BS_PV(5, 16, 16, 16, 8) BS_PV(5, 8, 32, 16, 8) BS_PV(5, 16, 32, 16, 4)
+  BS_PV(3, 16, 32, 16, 4) BS_PV(3, 8, 64, 16, 4) BS_PV(3, 32, 16, 16, 4) BS_PV(3, 16, 16, 16, 8)
+#undef BS_PV
   return hipErrorInvalidValue;
 }
 

@@ -48,13 +48,50 @@ def test_workspace_query(bs):
     assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 3, n, batch) == 0
     assert bs.workspace_bytes(bs.OP_SIP, 5, n, batch) == 5 * n * lw * 8
     assert bs.workspace_bytes(bs.OP_MNPDM, 5, n, batch) == 2 * n * lw * 8
-    assert bs.workspace_bytes(bs.OP_SOLVE, 5, n, batch) in (0, 2 * n * lw * 8)
-    assert bs.workspace_bytes(bs.OP_SOLVE, 3, n, batch) in (0, n * lw * 8)
     lib = bs.load()
     bad = ctypes.c_size_t(-1).value
-    assert lib.bs_workspace_bytes(bs.OP_SOLVE, 4, 0, n, batch) == bad
-    assert lib.bs_workspace_bytes(bs.OP_SOLVE, 5, 0, 0, batch) == bad
-    assert lib.bs_workspace_bytes(99, 5, 0, n, batch) == bad
+    assert lib.bs_workspace_bytes(bs.OP_SOLVE, 4, 0, n, batch, batch) == bad
+    assert lib.bs_workspace_bytes(bs.OP_SOLVE, 5, 0, 0, batch, batch) == bad
+    assert lib.bs_workspace_bytes(bs.OP_SOLVE, 5, 0, n, batch, batch - 1) == bad
+    assert lib.bs_workspace_bytes(99, 5, 0, n, batch, batch) == bad
+    # the split kernel needs no workspace; one lane per system needs alpha, beta
+    bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_LANE)
+    try:
+        assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch) == 2 * 2048 * lw * 8
+        assert bs.workspace_bytes(bs.OP_SOLVE, 3, 2048, batch) == 2048 * lw * 8
+    finally:
+        bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_AUTO)
+    # split rows: small exchange area (counters + tile maps) only
+    M, PW, G, TMAX = bs.part_variants(5)[0]
+    T = -(-2048 // (M * PW))
+    groups = -(-batch // G)
+    assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch) == \
+        ((2 * groups + 1) // 2 + 1 + groups * T * G * 21) * 8
+    assert bs.workspace_bytes(bs.OP_SOLVE, 5, M * PW, batch) == 0
+    assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2 * M * PW * TMAX, batch) == \
+        2 * 2 * M * PW * TMAX * lw * 8
+
+
+def test_options(bs):
+    assert bs.get_option(bs.OPT_DIRECT_PATH) == bs.PATH_AUTO
+    with pytest.raises(bs.BandSolveError):
+        bs.set_option(bs.OPT_DIRECT_PATH, 3)
+    with pytest.raises(bs.BandSolveError):
+        bs.set_option(bs.OPT_PART_PD_VARIANT, 99)
+    with pytest.raises(bs.BandSolveError):
+        bs.set_option(bs.OPT_PART_TD_VARIANT, -1)
+    with pytest.raises(bs.BandSolveError):
+        bs.set_option(99, 1)
+    assert bs.get_option(99) == -1
+    for kind in (5, 3):
+        vs = bs.part_variants(kind)
+        assert len(vs) >= 2
+        for M, PW, G, TMAX in vs:
+            assert M >= 4 and PW & (PW - 1) == 0 and TMAX & (TMAX - 1) == 0 and G >= 1
+            assert M * PW * TMAX >= 2048
+    bs.set_option(bs.OPT_PART_PD_VARIANT, 1)
+    assert bs.get_option(bs.OPT_PART_PD_VARIANT) == 1
+    bs.set_option(bs.OPT_PART_PD_VARIANT, 0)
 
 
 def _fake(k):
@@ -81,7 +118,7 @@ def test_invalid_arguments_rejected_on_host(bs):
     assert lib.band_solve(5, 0, n, batch, ld, d5, None, mis, x, info, ws, big, None) == E
     nulle = lib.VP5(None, _fake(1), _fake(2), _fake(3), None)
     assert lib.band_solve(5, 0, n, batch, ld, nulle, None, y, x, info, ws, big, None) == E
-    need = bs.workspace_bytes(bs.OP_SOLVE, 5, n, batch)
+    need = bs.workspace_bytes(bs.OP_SOLVE, 5, n, batch, ld=ld)
     if need:
         assert lib.band_solve(5, 0, n, batch, ld, d5, None, y, x, info, ws, need - 1,
                               None) == bs.BS_EWORKSPACE

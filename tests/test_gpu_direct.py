@@ -13,6 +13,15 @@ pytestmark = pytest.mark.gpu
 
 TOL = 1e-12   # relative parity bar per system, FP64
 
+PATHS = {"lane": bs.PATH_LANE, "part": bs.PATH_PART}
+@pytest.fixture(params=["lane", "part"])
+def path(request):
+    """Run the test once with one lane per system and once with the rows of a
+    system split over lanes (where the shape allows it)."""
+    bs.set_option(bs.OPT_DIRECT_PATH, PATHS[request.param])
+    yield request.param
+    bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_AUTO)
+
 
 def oracle_direct(ws, kind):
     if kind == 5:
@@ -21,10 +30,10 @@ def oracle_direct(ws, kind):
 
 
 @pytest.mark.parametrize("kind", [5, 3])
-def test_config0_parity(kind):
+def test_config0_parity(kind, path):
     ws = wl.config0(kind)
     batch = 64
-    say(f"config0 kind={kind} n=1024 batch=64")
+    say(f"config0 kind={kind} n=1024 batch=64 path={path}")
     t = to_device(ws, batch)
     x, info = bs.solve(diags_of(t, kind), t["y"], kind=kind, batch=batch)
     torch.cuda.synchronize()
@@ -38,10 +47,11 @@ def test_config0_parity(kind):
 
 @pytest.mark.parametrize("kind", [5, 3])
 @pytest.mark.parametrize("n,batch,ld", [(1, 5, 64), (2, 3, 3), (3, 70, 128), (4, 64, 64),
-                                        (37, 1, 1), (129, 67, 80), (1000, 200, 256)])
-def test_shapes_ragged_and_tiny(kind, n, batch, ld):
+                                        (8, 9, 9), (37, 1, 1), (129, 67, 80), (1000, 200, 256),
+                                        (2047, 33, 64), (2048, 5, 5)])
+def test_shapes_ragged_and_tiny(kind, n, batch, ld, path):
     ws = wl.dominant_batch(batch, n, kind=kind, seed=1000 + n + batch)
-    say(f"shape kind={kind} n={n} batch={batch} ld={ld}")
+    say(f"shape kind={kind} n={n} batch={batch} ld={ld} path={path}")
     t = to_device(ws, batch, ld=ld, corner_nan=True, pad_fill=np.nan)
     x0 = torch.full((n, ld), 7.0, dtype=torch.float64, device="cuda")
     x, info = bs.solve(diags_of(t, kind), t["y"], x0, kind=kind, batch=batch)
@@ -53,12 +63,12 @@ def test_shapes_ragged_and_tiny(kind, n, batch, ld):
         assert (x[:, batch:] == 7.0).all()
 
 
-def test_config1_full_size_pd_and_td():
+def test_config1_full_size_pd_and_td(path):
     """2048 x 2048 ADI sweep (r = 4): every system of both batches."""
     pd, td, _ = wl.config1()
     batch = 2048
     for kind, ws in ((5, pd), (3, td)):
-        say(f"config1 kind={kind} n=2048 batch=2048")
+        say(f"config1 kind={kind} n=2048 batch=2048 path={path}")
         t = to_device(ws, batch)
         x, info = bs.solve(diags_of(t, kind), t["y"], kind=kind, batch=batch)
         torch.cuda.synchronize()
@@ -67,6 +77,69 @@ def test_config1_full_size_pd_and_td():
         err = rel_err(host(x, batch), xr)
         say(f"  max rel err {err.max():.3e}")
         assert err.max() <= TOL
+
+
+@pytest.mark.parametrize("kind", [5, 3])
+def test_every_split_variant(kind):
+    """Each compiled split-row variant, on a ragged batch whose rows span
+    several tiles and on a second-order PDE batch."""
+    ws = wl.dominant_batch(45, 1999, kind=kind, seed=17)
+    pd, td, _ = wl.config1(N=512, seed=23)
+    pde = pd if kind == 5 else td
+    xr, _ = oracle_direct(ws, kind)
+    xp, _ = oracle_direct(pde, kind)
+    bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_PART)
+    key = bs.OPT_PART_PD_VARIANT if kind == 5 else bs.OPT_PART_TD_VARIANT
+    try:
+        for idx, shape in enumerate(bs.part_variants(kind)):
+            bs.set_option(key, idx)
+            say(f"variant kind={kind} (M, PW, G, TMAX)={shape}")
+            for rep in range(2):   # the workspace is reused: counters reset
+                t = to_device(ws, 45, ld=64, corner_nan=True)
+                x, info = bs.solve(diags_of(t, kind), t["y"], kind=kind, batch=45)
+                t2 = to_device(pde, 512)
+                x2, info2 = bs.solve(diags_of(t2, kind), t2["y"], kind=kind, batch=512)
+                torch.cuda.synchronize()
+                assert (info.cpu().numpy() == 0).all() and (info2.cpu().numpy() == 0).all()
+                assert rel_err(host(x, 45), xr).max() <= TOL
+                assert rel_err(host(x2, 512), xp).max() <= TOL
+    finally:
+        bs.set_option(key, 0)
+        bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_AUTO)
+
+
+def test_split_workspace_reuse_and_graph_replay():
+    """One persistent workspace, many calls and graph replays: the meeting
+    counters return to zero after every call."""
+    pd, _, _ = wl.config1(N=1024, seed=29)
+    batch = 1024
+    t = to_device(pd, batch)
+    xr, _ = oracle_direct(pd, 5)
+    nbytes = bs.workspace_bytes(bs.OP_SOLVE, 5, 1024, batch)
+    assert nbytes > 0
+    wsb = torch.zeros((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
+    x = torch.empty_like(t["y"])
+    info = torch.empty(batch, dtype=torch.int32, device="cuda")
+    for _ in range(5):
+        bs.solve(diags_of(t), t["y"], x, batch=batch, info=info, workspace=wsb)
+    torch.cuda.synchronize()
+    assert (info.cpu() == 0).all() and rel_err(host(x, batch), xr).max() <= TOL
+    M, PW, G, TMAX = bs.part_variants(5)[0]
+    groups = -(-batch // G)
+    assert (wsb[:groups].view(torch.int32)[: 2 * groups] == 0).all()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            bs.solve(diags_of(t), t["y"], x, batch=batch, info=info, workspace=wsb, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(4):
+        x.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert (info.cpu() == 0).all(), rep
+        assert rel_err(host(x, batch), xr).max() <= TOL, rep
 
 
 def test_in_place_and_deterministic():
@@ -80,7 +153,7 @@ def test_in_place_and_deterministic():
     assert torch.equal(x1[:, :100], x2[:, :100]) and torch.equal(x1[:, :100], x3[:, :100])
 
 
-def test_zero_and_nonfinite_pivots_reported():
+def test_zero_and_nonfinite_pivots_reported(path):
     ws = wl.dominant_batch(4, 50, kind=5, seed=6)
     ws["d"][0, 0] = 0.0            # system 0: mu_0 = 0
     ws["d"][1, 10] = np.inf        # system 1: non-finite pivot at row 10
