@@ -1,0 +1,351 @@
+"""Benchmark: batched pentadiagonal NPDM solves of one ADI sweep (n = 2048,
+2048 systems, FP64) on one MI355X, plus the other hot-path rows.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A timed step is one band_solve of the 2048 pentadiagonal systems (n = 2048)
+of the first y-sweep of u_t = (k(u)u_x)_x + (k(u)u_y)_y, k = 1 + u^2, on a
+2048 x 2048 grid (r = tau/h^2 = 4), inputs resident in HBM.  Steps rotate over
+four copies of the inputs (4 x 235 MB, more than the 256 MB Infinity Cache)
+so each step streams its operands from HBM.  Prints ONE JSON line.
+
+Outside the timed region the run also measures the other rows of the hot
+path on the same sweep (tridiagonal NTDM batch, MNPDM, band ILU(0), SIP with
+Hotelling-Bodewig steps) and times the FP64 CPU oracle on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1804_09666_amd import bandsolve as bs  # noqa: E402
+from paper_1804_09666_amd import workloads as wl  # noqa: E402
+
+N_ROWS = 2048
+BATCH = 2048
+R_ADI = 4.0
+PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
+PD_BYTES_PER_ROW = 56            # e, c, d, a, b, y read + x written (FP64)
+TD_BYTES_PER_ROW = 40            # c, d, a, y read + x written
+ROTATE = 4
+COPY_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_npdm_split_pd_n2048_b2048.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1804_09666_amd", "csrc", "direct_part.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def to_dev(ws, keys=("e", "c", "d", "a", "b", "y")):
+    return {k: torch.from_numpy(wl.interleave(ws[k])).cuda() for k in keys}
+
+
+def diags_of(t, kind):
+    if kind == 5:
+        return [t["e"], t["c"], t["d"], t["a"], t["b"]]
+    return [None, t["c"], t["d"], t["a"], None]
+
+
+def timed_solves(sets, kind, steps, warmup, ws_buf, xs, info):
+    """Warm up, then time `steps` solves: per-launch events plus the whole
+    region, all on the current stream (the one the library launches on)."""
+    stream = torch.cuda.current_stream()
+    for w in range(warmup):
+        t = sets[w % len(sets)]
+        bs.solve(diags_of(t, kind), t["y"], xs[w % len(xs)], kind=kind, batch=BATCH,
+                 info=info, workspace=ws_buf)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t_all0 = torch.cuda.Event(enable_timing=True)
+    t_all1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_all0.record(stream)
+    for k in range(steps):
+        t = sets[k % len(sets)]
+        ev[k][0].record(stream)
+        bs.solve(diags_of(t, kind), t["y"], xs[k % len(xs)], kind=kind, batch=BATCH,
+                 info=info, workspace=ws_buf)
+        ev[k][1].record(stream)
+    t_all1.record(stream)
+    torch.cuda.synchronize()
+    per = np.array([a.elapsed_time(b) for a, b in ev])   # ms
+    return t_all0.elapsed_time(t_all1), per
+
+
+def traffic_from_profile():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    if kv.get("kernel_source_sha256_16") != src_hash:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(pd):
+    """The FP64 oracle (serial NPDM per system, OpenMP over systems) on the
+    host cores, on the full sweep batch, repeated to ~10 s of CPU work."""
+    import oracle
+    args = [np.ascontiguousarray(pd[k]) for k in ("e", "c", "d", "a", "b", "y")]
+    nthreads = oracle.max_threads()
+    oracle.npdm_batch(*args, nthreads=nthreads)          # warm-up
+    t0 = time.perf_counter()
+    oracle.npdm_batch(*args, nthreads=nthreads)
+    one = time.perf_counter() - t0
+    reps = int(max(1, min(200, 10.0 / max(one * nthreads, 1e-6))))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        oracle.npdm_batch(*args, nthreads=nthreads)
+    wall = time.perf_counter() - t0
+    # one core, a bounded sample of 128 systems, for the per-row figure
+    sub = [a[:128] for a in args]
+    t0 = time.perf_counter()
+    oracle.npdm_batch(*sub, nthreads=1)
+    one_core = time.perf_counter() - t0
+    return {
+        "value": BATCH * reps / wall,
+        "unit": "PD systems/s",
+        "cores": nthreads,
+        "kind": "oracle",
+        "sample": f"full sweep batch ({BATCH} systems, n={N_ROWS}) x {reps} repetitions, "
+                  f"system-contiguous copy (layout conversion not timed)",
+        "ns_per_row_1core": one_core / (128 * N_ROWS) * 1e9,
+    }
+
+
+def other_rows(pd, td):
+    """Hot-path rows other than the timed PD solve, on the same sweep."""
+    out = {}
+
+    def t_ms(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    # NTDM on the tridiagonal (first-order) batch of the same sweep
+    tds = [to_dev(td, ("c", "d", "a", "y")) for _ in range(ROTATE)]
+    x = torch.empty_like(tds[0]["y"])
+    info = torch.empty(BATCH, dtype=torch.int32, device="cuda")
+    nb = bs.workspace_bytes(bs.OP_SOLVE, 3, N_ROWS, BATCH)
+    wsb = torch.zeros(max(nb, 8) // 8, dtype=torch.float64, device="cuda")
+    k = [0]
+
+    def td_solve():
+        t = tds[k[0] % ROTATE]
+        k[0] += 1
+        bs.solve(diags_of(t, 3), t["y"], x, kind=3, batch=BATCH, info=info, workspace=wsb)
+    ms = t_ms(td_solve, reps=20)
+    out["ntdm_td"] = {"us": ms * 1e3, "systems_per_s": BATCH / ms * 1e3,
+                      "algorithmic_GBps": TD_BYTES_PER_ROW * N_ROWS * BATCH / ms / 1e6,
+                      "info_ok": bool((info == 0).all())}
+    del tds
+
+    t = to_dev(pd)
+    # MNPDM: outer diagonals given as the two entries per system (rows 0, n-1)
+    rows = np.full((2, BATCH), -1, dtype=np.int32)
+    oe = np.zeros((2, BATCH))
+    ob = np.zeros((2, BATCH))
+    rows[0], ob[0] = 0, pd["b"][:, 0]
+    rows[1], oe[1] = N_ROWS - 1, pd["e"][:, N_ROWS - 1]
+    dv = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (rows, oe, ob)]
+    ms = t_ms(lambda: bs.solve_mnpdm([t["c"], t["d"], t["a"]], *dv, t["y"], x, batch=BATCH,
+                                     info=info), reps=3)
+    out["mnpdm_pd"] = {"us": ms * 1e3, "systems_per_s": BATCH / ms * 1e3,
+                       "algorithmic_GBps": 40 * N_ROWS * BATCH / ms / 1e6,
+                       "info_ok": bool((info == 0).all())}
+    # ILU(0) = band Doolittle
+    f = torch.empty((4, N_ROWS, BATCH), dtype=torch.float64, device="cuda")
+    ms = t_ms(lambda: bs.factor(diags_of(t, 5), batch=BATCH, out=f, info=info), reps=3)
+    out["ilu0_pd"] = {"us": ms * 1e3, "algorithmic_GBps": 72 * N_ROWS * BATCH / ms / 1e6}
+    # SIP with HB steps (s_L, s_U) = (3, 4) from zero start to 1e-10
+    res = {}
+
+    def sip():
+        xs, it, rr, si = bs.sip(diags_of(t, 5), t["y"], tol=1e-10, max_iter=200, s_L=3, s_U=4,
+                                factors=f, batch=BATCH)
+        res.update(it=it, rr=rr, si=si)
+    ms = t_ms(sip, reps=1)
+    its = res["it"].float()
+    out["sip_hb_pd"] = {"us": ms * 1e3, "hb_s": [3, 4], "tol": 1e-10,
+                        "iters_mean": float(its.mean()), "iters_max": int(res["it"].max()),
+                        "us_per_iteration": ms * 1e3 / max(float(its.max()), 1.0),
+                        "converged": int((res["si"] == 0).sum())}
+    return out
+
+
+def pmc_run():
+    """Workload for the rocprofv3 counter passes: 5 PD solves of the sweep
+    batch (rotating inputs) and one plain 1 GiB device copy whose HBM bytes
+    are known, to scale FETCH_SIZE / WRITE_SIZE."""
+    pd, _, _ = wl.config1(r=R_ADI, N=N_ROWS)
+    sets = [to_dev(pd) for _ in range(ROTATE)]
+    x = torch.empty_like(sets[0]["y"])
+    info = torch.empty(BATCH, dtype=torch.int32, device="cuda")
+    nb = bs.workspace_bytes(bs.OP_SOLVE, 5, N_ROWS, BATCH)
+    ws_buf = torch.zeros(max(nb, 8) // 8, dtype=torch.float64, device="cuda")
+    for k in range(5):
+        t = sets[k % ROTATE]
+        bs.solve(diags_of(t, 5), t["y"], x, batch=BATCH, info=info, workspace=ws_buf)
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log("pmc run done")
+
+
+def summarize_pmc(fetch_dir, write_dir, out_path=TRAFFIC_FILE):
+    """Turn the two counter passes into HBM bytes per launch of the split PD
+    kernel, each counter scaled by its reading for the 1 GiB copy."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") == counter:
+                    rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+        return rows
+
+    res = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = read(d, counter)
+        kern = [v for k, v in rows if "part_kernel<5" in k]
+        copy = [v for k, v in rows if "copybuffer" in k.lower()]
+        if not kern or not copy:
+            raise SystemExit(f"{counter}: kernel or copy dispatch not found in {d}")
+        res[counter] = (float(np.mean(kern)), float(max(copy)))
+    fetch_k, fetch_c = res["FETCH_SIZE"]
+    write_k, write_c = res["WRITE_SIZE"]
+    f_scale = COPY_BYTES / (fetch_c * 1024.0)
+    w_scale = COPY_BYTES / (write_c * 1024.0)
+    hbm = fetch_k * 1024.0 * f_scale + write_k * 1024.0 * w_scale
+    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    alg = PD_BYTES_PER_ROW * N_ROWS * BATCH
+    with open(out_path, "w") as fh:
+        fh.write("# HBM traffic per launch of the split-row NPDM kernel on the n=2048 x 2048\n"
+                 "# ADI pentadiagonal batch, from two rocprofv3 counter passes:\n"
+                 "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -- python3 bench.py --pmc-run\n"
+                 "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -- python3 bench.py --pmc-run\n"
+                 "# Each counter (KiB per dispatch) is scaled by what it reads for a plain\n"
+                 "# 1 GiB device copy (read 1 GiB, write 1 GiB) in the same run.\n")
+        fh.write(f"kernel_source_sha256_16: {src_hash}\n")
+        fh.write(f"fetch_kib_per_launch_raw: {fetch_k:.1f}\n")
+        fh.write(f"write_kib_per_launch_raw: {write_k:.1f}\n")
+        fh.write(f"copy_fetch_kib_raw: {fetch_c:.1f}\n")
+        fh.write(f"copy_write_kib_raw: {write_c:.1f}\n")
+        fh.write(f"fetch_scale: {f_scale:.4f}\n")
+        fh.write(f"write_scale: {w_scale:.4f}\n")
+        fh.write(f"hbm_bytes_per_launch: {hbm:.0f}\n")
+        fh.write(f"algorithmic_bytes_per_launch: {alg}\n")
+        fh.write(f"traffic_over_algorithmic: {hbm / alg:.4f}\n")
+    print(open(out_path).read())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-rows", action="store_true", help="skip the other hot-path rows")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="only run the workload of the rocprofv3 counter passes")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the HBM traffic summary from two counter passes")
+    args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
+    if args.pmc_run:
+        pmc_run()
+        return
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(systems of a sweep would be sharded across GPUs; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.init()
+    log(f"device: {torch.cuda.get_device_name(0)}")
+    pd, td, _ = wl.config1(r=R_ADI, N=N_ROWS)
+    sets = [to_dev(pd) for _ in range(ROTATE)]
+    xs = [torch.empty_like(sets[0]["y"]) for _ in range(ROTATE)]
+    info = torch.empty(BATCH, dtype=torch.int32, device="cuda")
+    nb = bs.workspace_bytes(bs.OP_SOLVE, 5, N_ROWS, BATCH)
+    ws_buf = torch.zeros(max(nb, 8) // 8, dtype=torch.float64, device="cuda")
+    log(f"timing {args.steps} steps after {args.warmup} warm-up steps")
+    total_ms, per = timed_solves(sets, 5, args.steps, args.warmup, ws_buf, xs, info)
+    ok = bool((info == 0).all())
+    # parity spot check of the last step against the oracle (untimed)
+    import oracle
+    idx = np.arange(0, BATCH, 97)
+    xr, _ = oracle.npdm_batch(*[pd[k][idx] for k in ("e", "c", "d", "a", "b", "y")])
+    xg = wl.deinterleave(xs[(args.steps - 1) % ROTATE].cpu().numpy(), BATCH)[idx]
+    rel = float((np.abs(xg - xr).max(axis=1) / np.abs(xr).max(axis=1)).max())
+    ms_step = total_ms / args.steps
+    kern_ms = float(per.mean())
+    alg_bytes = PD_BYTES_PER_ROW * N_ROWS * BATCH
+    achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
+    line = {
+        "metric": "PD systems/sec + HBM GB/s at n=2048; FP32+IR and warm-start vs FP64 at 1e-10",
+        "value": BATCH / (ms_step * 1e-3),
+        "unit": "PD systems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "adi_sweep_pd_n2048_b2048", "n": N_ROWS, "batch": BATCH,
+                   "r": R_ADI, "method": "NPDM (split-row band_solve)",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic_from_profile()},
+        "hbm_GBps_algorithmic": alg_bytes / (ms_step * 1e-3) / 1e9,
+        "kernel_us_mean": kern_ms * 1e3,
+        "kernel_us_p10_p90": [float(np.percentile(per, 10) * 1e3),
+                              float(np.percentile(per, 90) * 1e3)],
+        "parity_max_rel_err_sampled": rel,
+        "info_ok": ok,
+    }
+    if not args.no_rows:
+        log("measuring the other hot-path rows")
+        line["rows"] = other_rows(pd, td)
+    if not args.no_cpu:
+        log("timing the CPU oracle")
+        line["cpu_baseline"] = cpu_baseline(pd)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
