@@ -79,9 +79,18 @@ __device__ inline bool inv(const double (&M)[1][1], double (&R)[1][1]) {
   R[0][0] = 1.0 / M[0][0];
   return M[0][0] != 0.0 && isfinite(R[0][0]);
 }
+// 1/x from the hardware reciprocal estimate and two Newton steps (full
+// double precision up to an ulp; the interface blocks are far from the
+// subnormal range).
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
 __device__ inline bool inv(const double (&M)[2][2], double (&R)[2][2]) {
-  const double det = M[0][0] * M[1][1] - M[0][1] * M[1][0];
-  const double r = 1.0 / det;
+  const double det = fma(M[0][0], M[1][1], -M[0][1] * M[1][0]);
+  const double r = recip(det);
   R[0][0] = M[1][1] * r;
   R[0][1] = -M[0][1] * r;
   R[1][0] = -M[1][0] * r;
@@ -161,11 +170,14 @@ __device__ inline void load_rec(R& r, const double* src) {
 
 __device__ inline bool bad_pivot(double m) { return !(m != 0.0) || !isfinite(m); }
 
+// Streaming accesses: every input element is read once and every x element
+// written once, so they carry the non-temporal hint.
 __device__ inline double ldg(const double* __restrict__ base, uint32_t byte_off) {
-  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+  return __builtin_nontemporal_load(
+      reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off));
 }
 __device__ inline void stg(double* __restrict__ base, uint32_t byte_off, double v) {
-  *reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off) = v;
+  __builtin_nontemporal_store(v, reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off));
 }
 
 // Chunk of a pentadiagonal system: local NPDM with the couplings to
@@ -373,8 +385,8 @@ constexpr uint64_t kWaitTicks = 100000000;  // 1 s of the 100 MHz real-time coun
 // they exchange their tile maps through `xch` and meet at the counter pair
 // cnt[2*grp], cnt[2*grp+1] (arrivals, departures; reset by the last tile to
 // leave, so the counters are zero again after every completed call).
-template <int KIND, int M, int PW, int G, int TMAX>
-__global__ __launch_bounds__(G * PW) void part_kernel(
+template <int KIND, int M, int PW, int G, int TMAX, int WPE>
+__global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void part_kernel(
     int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
     const double* __restrict__ C, const double* __restrict__ D,
     const double* __restrict__ A, const double* __restrict__ B,
@@ -563,16 +575,16 @@ __global__ __launch_bounds__(G * PW) void part_kernel(
 }
 
 struct Variant {
-  int kind, M, PW, G, TMAX;
+  int kind, M, PW, G, TMAX, WPE;  // WPE: waves per SIMD the register budget targets
 };
 
 // Compiled variants; index 0 of each kind is the default.
 constexpr Variant kVariants[] = {
-    {5, 32, 16, 16, 4}, {5, 16, 16, 16, 8}, {5, 8, 32, 16, 8}, {5, 16, 32, 16, 4},
-    {3, 16, 32, 16, 4}, {3, 8, 64, 16, 4}, {3, 32, 16, 16, 4}, {3, 16, 16, 16, 8},
+    {5, 32, 16, 16, 4, 1}, {5, 16, 16, 16, 8, 2}, {5, 16, 16, 16, 8, 1}, {5, 8, 32, 16, 8, 1},
+    {3, 32, 16, 16, 4, 1}, {3, 16, 16, 16, 8, 2}, {3, 16, 32, 16, 4, 2}, {3, 8, 64, 16, 4, 4},
 };
 
-template <int KIND, int M, int PW, int G, int TMAX>
+template <int KIND, int M, int PW, int G, int TMAX, int WPE>
 hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, Diags A, const double* y,
                       double* x, int32_t* info, double* ws, hipStream_t st) {
   constexpr int RT = M * PW;
@@ -580,7 +592,7 @@ hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, Diags A, const doubl
   const int64_t groups = (batch + G - 1) / G;
   unsigned* cnt = (T > 1) ? reinterpret_cast<unsigned*>(ws) : nullptr;
   double* xch = (T > 1) ? ws + (2 * groups + 1) / 2 + 1 : nullptr;
-  hipLaunchKernelGGL((part_kernel<KIND, M, PW, G, TMAX>), dim3((unsigned)(groups * T)),
+  hipLaunchKernelGGL((part_kernel<KIND, M, PW, G, TMAX, WPE>), dim3((unsigned)(groups * T)),
                      dim3(G * PW), 0, st, n, batch, ld, A.e, A.c, A.d, A.a, A.b, y, x,
                      info, xch, cnt, T);
   return hipGetLastError();
@@ -637,11 +649,13 @@ hipError_t launch_part(int kind, int idx, int64_t n, int64_t batch, int64_t ld,
                        double* ws, hipStream_t st) {
   const Variant* v = find_variant(kind, idx);
   if (!v) return hipErrorInvalidValue;
-#define BS_PV(K, MM, PP, GG, TT)                                                    \
-  if (v->kind == K && v->M == MM && v->PW == PP && v->G == GG && v->TMAX == TT)      \
-    return launch_cfg<K, MM, PP, GG, TT>(n, batch, ld, A, y, x, info, ws, st);
-  BS_PV(5, 32, 16, 16, 4) BS_PV(5, 16, 16, 16, 8) BS_PV(5, 8, 32, 16, 8) BS_PV(5, 16, 32, 16, 4)
-  BS_PV(3, 16, 32, 16, 4) BS_PV(3, 8, 64, 16, 4) BS_PV(3, 32, 16, 16, 4) BS_PV(3, 16, 16, 16, 8)
+#define BS_PV(K, MM, PP, GG, TT, WW)                                                  \
+  if (v->kind == K && v->M == MM && v->PW == PP && v->G == GG && v->TMAX == TT &&        \
+      v->WPE == WW)                                                                      \
+    return launch_cfg<K, MM, PP, GG, TT, WW>(n, batch, ld, A, y, x, info, ws, st);
+  BS_PV(5, 32, 16, 16, 4, 1) BS_PV(5, 16, 16, 16, 8, 2) BS_PV(5, 16, 16, 16, 8, 1)
+  BS_PV(5, 8, 32, 16, 8, 1) BS_PV(3, 32, 16, 16, 4, 1) BS_PV(3, 16, 16, 16, 8, 2)
+  BS_PV(3, 16, 32, 16, 4, 2) BS_PV(3, 8, 64, 16, 4, 4)
 #undef BS_PV
   return hipErrorInvalidValue;
 }
