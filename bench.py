@@ -101,9 +101,11 @@ def traffic_from_profile():
         return None
 
 
-def cpu_baseline(pd):
-    """The FP64 oracle (serial NPDM per system, OpenMP over systems) on the
-    host cores, on the full sweep batch, repeated to ~10 s of CPU work."""
+def cpu_baseline(pd, samples):
+    """The CPU leg: the FP64 oracle (serial NPDM per system, OpenMP over
+    systems) timed on the host cores on the full sweep batch, repeated to
+    ~10 s of CPU work; it also solves the sampled systems (`samples`: name ->
+    system-contiguous batch) whose GPU results are compared with it."""
     import oracle
     args = [np.ascontiguousarray(pd[k]) for k in ("e", "c", "d", "a", "b", "y")]
     nthreads = oracle.max_threads()
@@ -121,6 +123,12 @@ def cpu_baseline(pd):
     t0 = time.perf_counter()
     oracle.npdm_batch(*sub, nthreads=1)
     one_core = time.perf_counter() - t0
+    refs = {}
+    for name, ws in samples.items():
+        if "e" in ws:
+            refs[name] = oracle.npdm_batch(*[ws[k] for k in ("e", "c", "d", "a", "b", "y")])[0]
+        else:
+            refs[name] = oracle.ntdm_batch(*[ws[k] for k in ("c", "d", "a", "y")])[0]
     return {
         "value": BATCH * reps / wall,
         "unit": "PD systems/s",
@@ -129,23 +137,101 @@ def cpu_baseline(pd):
         "sample": f"full sweep batch ({BATCH} systems, n={N_ROWS}) x {reps} repetitions, "
                   f"system-contiguous copy (layout conversion not timed)",
         "ns_per_row_1core": one_core / (128 * N_ROWS) * 1e9,
-    }
+    }, refs
+
+
+def t_ms(fn, reps=5):
+    """Mean wall time of fn() on the current stream (after one untimed call)."""
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def precision_rows():
+    """FP32 storage + FP64 refinement to 1e-10 against the FP64 solve, on the
+    sweep batch (2048 x 2048) and on 256 pentadiagonal lines of length 1e6
+    (r = 4), all inputs resident in HBM.  Returns (rows, sampled GPU results,
+    sampled host batches) -- the errors against the oracle are filled in by
+    the caller once the CPU leg has solved the samples."""
+    KEYS = ("e", "c", "d", "a", "b", "y")
+    out, got, samples = {}, {}, {}
+    cases = []
+    pd, _, _ = wl.config1(r=R_ADI, N=N_ROWS)
+    c1 = {k: torch.from_numpy(wl.interleave(pd[k], BATCH)).cuda() for k in KEYS}
+    idx = [0, 97, 1024, 2047]
+    cases.append(("adi_sweep_pd_n2048_b2048", c1, BATCH, N_ROWS,
+                  {k: pd[k][idx] for k in KEYS}, idx))
+    nsys, n = 256, 1_000_000
+    v = wl.smooth_lines(nsys, n, wl.BASE_SEED + 3)
+    vt = torch.from_numpy(np.ascontiguousarray(v.T)).cuda()
+    c3 = wl.sweep_lines_interleaved(vt, R_ADI, 2)
+    del vt
+    idx3 = [0, 128, 255]
+    cases.append(("pd_lines_n1e6_b256", c3, nsys, n, wl.sweep_lines(v[idx3], R_ADI, 2), idx3))
+    del v
+    for name, dev, batch, n, host_ws, idx in cases:
+        log(f"precision rows: {name}")
+        info = torch.empty(batch, dtype=torch.int32, device="cuda")
+        rows = n * batch
+        # FP64 direct solve
+        x64 = torch.empty_like(dev["y"])
+        w64 = torch.zeros(max(bs.workspace_bytes(bs.OP_SOLVE, 5, n, batch), 8) // 8,
+                          dtype=torch.float64, device="cuda")
+        ms64 = t_ms(lambda: bs.solve(diags_of(dev, 5), dev["y"], x64, batch=batch, info=info,
+                                     workspace=w64))
+        ok64 = bool((info == 0).all())
+        # FP32 storage solve alone (the matrix already held in FP32)
+        d32 = {k: dev[k].float() for k in KEYS}
+        x32 = torch.empty_like(d32["y"])
+        w32 = torch.zeros(max(bs.workspace_bytes(bs.OP_SOLVE, 5, n, batch, bs.BS_F32), 8) // 8,
+                          dtype=torch.float64, device="cuda")
+        ms32 = t_ms(lambda: bs.solve(diags_of(d32, 5), d32["y"], x32, batch=batch, info=info,
+                                     workspace=w32))
+        ok32 = bool((info == 0).all())
+        del d32
+        # FP32 solves + FP64 refinement to 1e-10 on the FP64 data
+        xir = torch.empty_like(dev["y"])
+        wir = torch.zeros(bs.workspace_bytes(bs.OP_REFINE, 5, n, batch) // 8 + 1,
+                          dtype=torch.float64, device="cuda")
+        res = {}
+
+        def ir():
+            _, st, rr, inf = bs.refine(diags_of(dev, 5), dev["y"], xir, batch=batch, tol=1e-10,
+                                       max_steps=8, workspace=wir)
+            res.update(st=st, rr=rr, inf=inf)
+        msir = t_ms(ir)
+        steps = res["st"].cpu().numpy()
+        out[name] = {
+            "n": n, "batch": batch,
+            "fp64_solve_us": ms64 * 1e3,
+            "fp64_algorithmic_GBps": PD_BYTES_PER_ROW * rows / ms64 / 1e6,
+            "fp32_storage_solve_us": ms32 * 1e3,
+            "fp32_algorithmic_GBps": 28 * rows / ms32 / 1e6,
+            "fp32_ir_to_1e-10_us": msir * 1e3,
+            "fp32_ir_over_fp64_time": msir / ms64,
+            "ir_steps_hist": np.bincount(steps).tolist(),
+            "ir_relres_max": float(res["rr"].max()),
+            "ir_converged": int((res["inf"] == 0).sum()),
+            "info_ok": ok64 and ok32,
+        }
+        got[name] = {"fp64": x64[:, idx].cpu().numpy().T, "fp32": x32[:, idx].double().cpu().numpy().T,
+                     "fp32_ir": xir[:, idx].cpu().numpy().T}
+        samples["prec_" + name] = host_ws
+        del x64, x32, xir, w64, w32, wir
+    del c1, c3
+    torch.cuda.empty_cache()
+    return out, got, samples
 
 
 def other_rows(pd, td):
     """Hot-path rows other than the timed PD solve, on the same sweep."""
     out = {}
-
-    def t_ms(fn, reps=5):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
 
     # NTDM on the tridiagonal (first-order) batch of the same sweep
     tds = [to_dev(td, ("c", "d", "a", "y")) for _ in range(ROTATE)]
@@ -302,12 +388,8 @@ def main():
     log(f"timing {args.steps} steps after {args.warmup} warm-up steps")
     total_ms, per = timed_solves(sets, 5, args.steps, args.warmup, ws_buf, xs, info)
     ok = bool((info == 0).all())
-    # parity spot check of the last step against the oracle (untimed)
-    import oracle
     idx = np.arange(0, BATCH, 97)
-    xr, _ = oracle.npdm_batch(*[pd[k][idx] for k in ("e", "c", "d", "a", "b", "y")])
-    xg = wl.deinterleave(xs[(args.steps - 1) % ROTATE].cpu().numpy(), BATCH)[idx]
-    rel = float((np.abs(xg - xr).max(axis=1) / np.abs(xr).max(axis=1)).max())
+    x_last = wl.deinterleave(xs[(args.steps - 1) % ROTATE].cpu().numpy(), BATCH)[idx]
     ms_step = total_ms / args.steps
     kern_ms = float(per.mean())
     alg_bytes = PD_BYTES_PER_ROW * N_ROWS * BATCH
@@ -335,15 +417,29 @@ def main():
         "kernel_us_mean": kern_ms * 1e3,
         "kernel_us_p10_p90": [float(np.percentile(per, 10) * 1e3),
                               float(np.percentile(per, 90) * 1e3)],
-        "parity_max_rel_err_sampled": rel,
         "info_ok": ok,
     }
+    samples = {"timed": {k: pd[k][idx] for k in ("e", "c", "d", "a", "b", "y")}}
     if not args.no_rows:
         log("measuring the other hot-path rows")
         line["rows"] = other_rows(pd, td)
+        del sets, xs
+        torch.cuda.empty_cache()
+        prec, prec_x, prec_samples = precision_rows()
+        line["fp32_ir"] = prec
+        samples.update(prec_samples)
     if not args.no_cpu:
         log("timing the CPU oracle")
-        line["cpu_baseline"] = cpu_baseline(pd)
+        line["cpu_baseline"], refs = cpu_baseline(pd, samples)
+
+        def rel(x, ref):
+            return float((np.abs(x - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
+        line["parity_max_rel_err_sampled"] = rel(x_last, refs["timed"])
+        if not args.no_rows:
+            for name, xsamp in prec_x.items():
+                ref = refs["prec_" + name]
+                for key, xv in xsamp.items():
+                    line["fp32_ir"][name][f"{key}_err_vs_oracle"] = rel(xv, ref)
     print(json.dumps(line), flush=True)
 
 

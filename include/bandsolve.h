@@ -28,8 +28,12 @@
  * a_{n-1}, b_{n-2}, b_{n-1} are never read (they may hold anything, NaN
  * included).  Inputs are never written.  x may alias rhs.
  *
- * PRECISION.  dtype BS_F64: every array is double.  dtype BS_F32 (band_solve
- * only): diags, rhs and x are float; pivots and recurrences run in FP32.
+ * PRECISION.  dtype BS_F64: every array is double.  dtype BS_F32 (fused
+ * band_solve only, n >= 8): diags, rhs and x are stored as float, and every
+ * arithmetic step (pivots and recurrences included) runs in FP64 on the
+ * values read; only the storage rounding differs from FP64.
+ * band_solve_refine takes FP64 arrays, solves with FP32 storage and restores
+ * FP64 accuracy by iterative refinement.
  *
  * STREAMS.  `stream` is a hipStream_t passed as void* (NULL = the default
  * stream).  Every call only enqueues work on it and returns; results, info,
@@ -49,6 +53,8 @@
  *            ascending or names a row outside 0..n-1
  *    -4      split-row band_solve: the blocks that share the system did not
  *            all arrive within about a second (x unspecified)
+ *    -1, -2  band_solve_refine: not converged within max_steps / residual not
+ *            finite (as for SIP)
  */
 #ifndef BANDSOLVE_H
 #define BANDSOLVE_H
@@ -75,7 +81,8 @@ enum bs_op_code {
   BS_OP_SOLVE = 1,        /* band_solve with factors == NULL (fused)       */
   BS_OP_SOLVE_FACTORED = 2, /* band_solve with factors from band_factor    */
   BS_OP_MNPDM = 3,        /* band_solve_mnpdm                              */
-  BS_OP_SIP = 4           /* sip_solve                                     */
+  BS_OP_SIP = 4,          /* sip_solve                                     */
+  BS_OP_REFINE = 5        /* band_solve_refine (dtype BS_F64)              */
 };
 
 /* Human-readable name of a status code (static string). */
@@ -91,9 +98,9 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
                           int64_t batch, int64_t ld);
 
 /* Process-wide tuning options (not per-call state; read at every call).
- *   BS_OPT_DIRECT_PATH     fused band_solve kernel: 0 auto (default), 1 one
- *                          lane per system, 2 rows of a system split over
- *                          lanes where the variant supports n (else 1)
+ *   BS_OPT_DIRECT_PATH     fused band_solve kernel: 0 and 2 rows of a
+ *                          system split over lanes (default; one lane per
+ *                          system for n < 8), 1 one lane per system (FP64)
  *   BS_OPT_PART_PD_VARIANT index of the split-row PD kernel variant
  *   BS_OPT_PART_TD_VARIANT index of the split-row TD kernel variant
  * bs_set_option returns BS_EINVAL for an unknown key or a value out of range;
@@ -131,12 +138,15 @@ int32_t band_factor(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
 /* Solve A x = rhs for every system.
  * factors == NULL: fused factor + solve, NPDM (kind 5) or NTDM (kind 3)
  *   (Sec. 1): LU without pivoting, L = (e, gamma, mu), U unit upper
- *   (alpha, beta); info[s] reports the first bad pivot.  For large enough
- *   batches each system is one lane and the arithmetic is that of the
- *   sequential recurrence; for few, long systems the rows of a system are
- *   split over several lanes (partitioned elimination with a reduced
- *   interface system), which changes the rounding but not the result beyond
- *   it (info then reports the first bad pivot of the elimination performed).
+ *   (alpha, beta); info[s] reports the first bad pivot.  With one lane per
+ *   system (option BS_OPT_DIRECT_PATH = 1) the arithmetic is that of the
+ *   sequential recurrence.  By default the rows of a system are split over
+ *   many lanes (partitioned elimination with a reduced interface system),
+ *   which changes the rounding but not the result beyond it (info then
+ *   reports the first bad pivot of the elimination performed): one launch for
+ *   n up to M*PW*TMAX of the configured variant, three launches (tile maps,
+ *   per-system reduction, finish) for longer systems.  dtype BS_F32 needs
+ *   this split path (n >= 8).
  * factors != NULL: substitution with the factors of band_factor (same kind
  *   and layout): L z = rhs, U x = z.  info[s] is set to 0.
  * workspace / ws_bytes: as bs_workspace_bytes(BS_OP_SOLVE or
@@ -150,6 +160,32 @@ int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
                    int64_t ld, const void* const diags[5], const void* factors,
                    const void* rhs, void* x, int32_t* info, void* workspace,
                    size_t ws_bytes, void* stream);
+
+/* Mixed-precision NPDM / NTDM with iterative refinement.  The matrix and rhs
+ * are FP64; the elimination reads an FP32 copy of them (half the bytes per
+ * sweep), and FP64 residuals on the original matrix correct the result:
+ *     A32 = fl32(A); x = 0; r = rhs
+ *     repeat: solve A32 d = fl32(r) (fused band_solve, BS_F32); x += d;
+ *             r = rhs - A x (FP64)
+ *     until ||r||_inf < tol ||rhs||_inf, per system, or max_steps solves.
+ * Refinement of this kind converges when cond(A) times the FP32 rounding
+ * unit is well below 1 (diagonally dominant ADI sweeps: a few steps to
+ * 1e-12).  Systems that have converged are frozen; once all have, the
+ * remaining launches return at once (no host synchronisation, so the call
+ * can be captured in a graph).
+ * diags (FP64, kind 3 needs c, d, a), rhs, x: batch-interleaved, n*ld each;
+ * x is output only and must not alias rhs.  n >= 8.
+ * steps[s]: FP32 solves the system took; relres[s]: final
+ * ||r||_inf / ||rhs||_inf (0 for rhs = 0); info[s]: 0, -1 (not converged
+ * within max_steps), -2 (residual not finite), i+1 (bad pivot of the FP32
+ * elimination at row i) or -4 (as band_solve).
+ * workspace: bs_workspace_bytes(BS_OP_REFINE, kind, BS_F64, ...) bytes,
+ * 256-byte aligned, zero before its first use (as for band_solve; the call
+ * leaves its counters at zero again). */
+int32_t band_solve_refine(int32_t kind, int64_t n, int64_t batch, int64_t ld,
+                          const double* const diags[5], const double* rhs, double* x,
+                          double tol, int32_t max_steps, int32_t* steps, double* relres,
+                          int32_t* info, void* workspace, size_t ws_bytes, void* stream);
 
 /* MNPDM (Sec. 1): pentadiagonal solve in which the outer diagonals e and b
  * are given sparsely.  cda = {c, d, a} (batch-interleaved, n*ld each).

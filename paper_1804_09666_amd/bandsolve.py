@@ -22,11 +22,11 @@ LIB_PATH = os.path.join(HERE, "libbandsolve.so")
 
 BS_OK, BS_EINVAL, BS_ELAUNCH, BS_EWORKSPACE, BS_ENODEV = range(5)
 BS_F64, BS_F32 = 0, 1
-OP_FACTOR, OP_SOLVE, OP_SOLVE_FACTORED, OP_MNPDM, OP_SIP = range(5)
+OP_FACTOR, OP_SOLVE, OP_SOLVE_FACTORED, OP_MNPDM, OP_SIP, OP_REFINE = range(6)
 
 EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "bs_set_option",
             "bs_get_option", "bs_part_variant", "band_factor", "band_solve",
-            "band_solve_mnpdm", "sip_solve")
+            "band_solve_refine", "band_solve_mnpdm", "sip_solve")
 OPT_DIRECT_PATH, OPT_PART_PD_VARIANT, OPT_PART_TD_VARIANT = range(3)
 PATH_AUTO, PATH_LANE, PATH_PART = range(3)
 
@@ -60,6 +60,8 @@ def load():
         "bs_part_variant": (i32, [i32, i32, ctypes.POINTER(i32)]),
         "band_factor": (i32, [i32, i32, i64, i64, i64, vp5, vp, vp, vp]),
         "band_solve": (i32, [i32, i32, i64, i64, i64, vp5, vp, vp, vp, vp, vp, sz, vp]),
+        "band_solve_refine": (i32, [i32, i64, i64, i64, vp5, vp, vp, ctypes.c_double, i32,
+                                    vp, vp, vp, vp, sz, vp]),
         "band_solve_mnpdm": (i32, [i32, i64, i64, i64, vp3, i32, vp, vp, vp, vp, vp,
                                    vp, vp, sz, vp]),
         "sip_solve": (i32, [i32, i64, i64, i64, vp5, vp, vp, vp, ctypes.c_double, i32,
@@ -197,6 +199,30 @@ def solve(diags, rhs, x=None, *, kind=None, batch=None, factors=None, info=None,
                         _stream(stream))
     _raise(st, "band_solve")
     return x, info
+
+
+def refine(diags, rhs, x=None, *, tol=1e-12, max_steps=8, kind=None, batch=None,
+           workspace=None, stream=None):
+    """FP32-storage NPDM / NTDM with FP64 iterative refinement on FP64 data
+    -> (x, steps, relres, info).  x must not alias rhs."""
+    lib = load()
+    kind, n, ld, batch, dtype = _prep(diags, rhs, kind, batch)
+    if dtype != torch.float64:
+        raise ValueError("refine takes float64 diagonals and right-hand side")
+    dev = rhs.device
+    x = torch.empty_like(rhs) if x is None else x
+    _check2d(x, "x", n, dtype)
+    steps = torch.empty(batch, dtype=torch.int32, device=dev)
+    relres = torch.empty(batch, dtype=torch.float64, device=dev)
+    info = torch.empty(batch, dtype=torch.int32, device=dev)
+    nbytes = workspace_bytes(OP_REFINE, kind, n, batch, BS_F64, ld)
+    workspace = _ws(nbytes, dev) if workspace is None else workspace
+    st = lib.band_solve_refine(kind, n, batch, ld, lib.VP5(*[_ptr(t) for t in diags]),
+                               _ptr(rhs), _ptr(x), float(tol), int(max_steps), _ptr(steps),
+                               _ptr(relres), _ptr(info), _ptr(workspace),
+                               workspace.numel() * workspace.element_size(), _stream(stream))
+    _raise(st, "band_solve_refine")
+    return x, steps, relres, info
 
 
 def solve_mnpdm(cda, outer_row, outer_e, outer_b, rhs, x=None, *, batch=None,

@@ -23,7 +23,7 @@ bool aligned(const void* p, size_t a) {
 
 bool shape_ok(int64_t n, int64_t batch, int64_t ld) {
   if (n < 1 || batch < 1 || ld < batch) return false;
-  if (n > (int64_t(1) << 31) || batch > (int64_t(1) << 31)) return false;
+  if (n >= (int64_t(1) << 31) - 1 || batch >= (int64_t(1) << 31)) return false;
   if (ld > kMaxElems / n) return false;
   return true;
 }
@@ -62,17 +62,68 @@ std::atomic<int64_t> g_pd_variant{0}, g_td_variant{0};
 
 int part_idx(int32_t kind) { return (int)(kind == 5 ? g_pd_variant.load() : g_td_variant.load()); }
 
-bool use_part(int32_t kind, int64_t n, int64_t batch, int64_t ld) {
-  if (g_direct_path.load() == 1) return false;
-  return bs::part_supported(kind, part_idx(kind), n, batch, ld);
+}  // namespace
+
+namespace bs {
+namespace {
+
+// Which fused kernel solves (kind, dtype, n, ld) under the current options.
+enum class Route { kLane, kPart, kLong, kNone };
+
+Route route(int kind, int dtype, int64_t n, int64_t ld, int* idx) {
+  *idx = -1;
+  if (g_direct_path.load() != 1) {
+    *idx = part_pick(kind, part_idx(kind), n, ld, dtype);
+    if (*idx >= 0) return Route::kPart;
+    if (long_supported(n, ld, dtype)) return Route::kLong;
+  }
+  return dtype == BS_F64 ? Route::kLane : Route::kNone;
 }
 
-size_t solve_ws_bytes(int32_t kind, int64_t n, int64_t batch, int64_t ld) {
-  if (use_part(kind, n, batch, ld))
-    return bs::part_workspace_bytes(kind, part_idx(kind), n, batch);
-  const int64_t planes = kind == 5 ? 2 : 1;  // alpha (+ beta); z is kept in x
-  return (size_t)(planes * n * bs::ws_ld(batch)) * 8;
+}  // namespace
+
+bool direct_supported(int kind, int dtype, int64_t n, int64_t ld) {
+  int idx;
+  return route(kind, dtype, n, ld, &idx) != Route::kNone;
 }
+
+size_t direct_ws_bytes(int kind, int dtype, int64_t n, int64_t batch, int64_t ld) {
+  int idx;
+  switch (route(kind, dtype, n, ld, &idx)) {
+    case Route::kPart: return part_workspace_bytes(kind, idx, n, batch);
+    case Route::kLong: return long_workspace_bytes(kind, n, batch);
+    case Route::kLane: return (size_t)((kind == 5 ? 2 : 1) * n * ws_ld(batch)) * 8;
+    default: return 0;
+  }
+}
+
+hipError_t launch_direct(int kind, int dtype, int64_t n, int64_t batch, int64_t ld,
+                         const void* const dg[5], const void* y, void* x, int32_t* info,
+                         void* ws, hipStream_t st, const int32_t* skip) {
+  int idx;
+  double* w = static_cast<double*>(ws);
+  switch (route(kind, dtype, n, ld, &idx)) {
+    case Route::kPart:
+      return launch_part(kind, idx, dtype, n, batch, ld, dg, y, x, info, w, st, skip);
+    case Route::kLong:
+      return launch_long_path(kind, dtype, n, batch, ld, dg, y, x, info, w, st, skip);
+    case Route::kLane: {
+      if (skip != nullptr) return hipErrorInvalidValue;  // lane kernels take no skip flag
+      Diags A = as_diags(kind, dg);
+      if (kind == 5)
+        return launch_npdm_lane(n, batch, ld, A, static_cast<const double*>(y),
+                                static_cast<double*>(x), info, w, st);
+      return launch_ntdm_lane(n, batch, ld, A, static_cast<const double*>(y),
+                              static_cast<double*>(x), info, w, st);
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace bs
+
+namespace {
 
 int32_t launched(hipError_t e) { return e == hipSuccess ? BS_OK : BS_ELAUNCH; }
 
@@ -137,13 +188,15 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
                           int64_t batch, int64_t ld) {
   const size_t bad = (size_t)-1;
   if (!shape_ok(n, batch, ld)) return bad;
-  if (dtype != BS_F64) return bad;
+  if (dtype != BS_F64 && dtype != BS_F32) return bad;
   const int64_t plane = n * bs::ws_ld(batch);
+  if (dtype == BS_F32 && op != BS_OP_SOLVE) return bad;
   switch (op) {
     case BS_OP_FACTOR:
       return kind_ok(kind) ? 0 : bad;
     case BS_OP_SOLVE:
-      return kind_ok(kind) ? solve_ws_bytes(kind, n, batch, ld) : bad;
+      if (!kind_ok(kind) || !bs::direct_supported(kind, dtype, n, ld)) return bad;
+      return bs::direct_ws_bytes(kind, dtype, n, batch, ld);
     case BS_OP_SOLVE_FACTORED:
       return kind_ok(kind) ? 0 : bad;
     case BS_OP_MNPDM:
@@ -152,6 +205,9 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
       // ILU(0) factors (4 planes, batch-interleaved with ld = ws_ld) + 1 plane
       // for the forward pass result
       return (size_t)(5 * plane) * 8;
+    case BS_OP_REFINE:
+      if (!kind_ok(kind) || !bs::direct_supported(kind, BS_F32, n, ld)) return bad;
+      return bs::refine_workspace_bytes(kind, n, batch, ld);
     default:
       return bad;
   }
@@ -174,37 +230,51 @@ int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
                    int64_t ld, const void* const diags[5], const void* factors,
                    const void* rhs, void* x, int32_t* info, void* workspace,
                    size_t ws_bytes, void* stream) {
-  if (!kind_ok(kind) || dtype != BS_F64 || !shape_ok(n, batch, ld)) return BS_EINVAL;
+  if (!kind_ok(kind) || (dtype != BS_F64 && dtype != BS_F32) || !shape_ok(n, batch, ld))
+    return BS_EINVAL;
   if (!diags_ok(kind, diags, dtype) || !array_ok(rhs, dtype) ||
       !array_ok(x, dtype) || info == nullptr || !aligned(info, 4))
     return BS_EINVAL;
-  if (factors != nullptr && !array_ok(factors, dtype)) return BS_EINVAL;
   const hipStream_t st = static_cast<hipStream_t>(stream);
-  const bs::Diags A = as_diags(kind, diags);
   if (factors != nullptr) {
+    if (dtype != BS_F64 || !array_ok(factors, dtype)) return BS_EINVAL;
     if (!have_device()) return BS_ENODEV;
-    return launched(bs::launch_subst_lane(kind, n, batch, ld, A,
+    return launched(bs::launch_subst_lane(kind, n, batch, ld, as_diags(kind, diags),
                                           static_cast<const double*>(factors),
                                           static_cast<const double*>(rhs),
                                           static_cast<double*>(x), info, st));
   }
   const size_t need = bs_workspace_bytes(BS_OP_SOLVE, kind, dtype, n, batch, ld);
+  if (need == (size_t)-1) return BS_EINVAL;  // no kernel for this dtype and shape
   if (ws_bytes < need) return BS_EWORKSPACE;
-  if (need > 0 && !array_ok(workspace, dtype)) return BS_EINVAL;
+  if (need > 0 && (workspace == nullptr || !aligned(workspace, 8))) return BS_EINVAL;
   if (!have_device()) return BS_ENODEV;
-  if (use_part(kind, n, batch, ld))
-    return launched(bs::launch_part(kind, part_idx(kind), n, batch, ld, A,
-                                    static_cast<const double*>(rhs),
-                                    static_cast<double*>(x), info,
-                                    static_cast<double*>(workspace), st));
-  double* ws = static_cast<double*>(workspace);
-  if (kind == 5)
-    return launched(bs::launch_npdm_lane(n, batch, ld, A,
-                                         static_cast<const double*>(rhs),
-                                         static_cast<double*>(x), info, ws, st));
-  return launched(bs::launch_ntdm_lane(n, batch, ld, A,
-                                       static_cast<const double*>(rhs),
-                                       static_cast<double*>(x), info, ws, st));
+  return launched(bs::launch_direct(kind, dtype, n, batch, ld, diags, rhs, x, info,
+                                    workspace, st));
+}
+
+int32_t band_solve_refine(int32_t kind, int64_t n, int64_t batch, int64_t ld,
+                          const double* const diags[5], const double* rhs, double* x,
+                          double tol, int32_t max_steps, int32_t* steps, double* relres,
+                          int32_t* info, void* workspace, size_t ws_bytes, void* stream) {
+  if (!kind_ok(kind) || !shape_ok(n, batch, ld)) return BS_EINVAL;
+  const void* dv[5];
+  for (int k = 0; k < 5; ++k) dv[k] = diags ? diags[k] : nullptr;
+  if (diags == nullptr || !diags_ok(kind, dv, BS_F64) || !array_ok(rhs, BS_F64) ||
+      !array_ok(x, BS_F64))
+    return BS_EINVAL;
+  if (steps == nullptr || !aligned(steps, 4) || !array_ok(relres, BS_F64) ||
+      info == nullptr || !aligned(info, 4))
+    return BS_EINVAL;
+  if (!(tol > 0.0) || max_steps < 1) return BS_EINVAL;
+  if ((const void*)x == (const void*)rhs) return BS_EINVAL;  // rhs is re-read every step
+  const size_t need = bs_workspace_bytes(BS_OP_REFINE, kind, BS_F64, n, batch, ld);
+  if (need == (size_t)-1) return BS_EINVAL;
+  if (ws_bytes < need) return BS_EWORKSPACE;
+  if (workspace == nullptr || !aligned(workspace, 256)) return BS_EINVAL;
+  if (!have_device()) return BS_ENODEV;
+  return launched(bs::launch_refine(kind, n, batch, ld, diags, rhs, x, tol, max_steps, steps,
+                                    relres, info, workspace, static_cast<hipStream_t>(stream)));
 }
 
 int32_t band_solve_mnpdm(int32_t dtype, int64_t n, int64_t batch, int64_t ld,

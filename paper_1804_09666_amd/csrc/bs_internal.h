@@ -41,14 +41,42 @@ hipError_t launch_subst_lane(int kind, int64_t n, int64_t batch, int64_t ld,
 
 // ---- direct solvers, rows of a system split over lanes (direct_part.hip) --
 // Variant idx of a kind: M rows per lane, PW lanes per system in a block
-// (one tile of M*PW rows), G systems per block, up to TMAX tiles per system.
+// (one tile of M*PW rows), G systems per block, up to TMAX tiles per system,
+// all in one launch.  dtype 0: FP64 storage, 1: FP32 storage; arithmetic is
+// FP64 in both.
 int part_variant_count(int kind);
 bool part_variant_shape(int kind, int idx, int out[4]);
-bool part_supported(int kind, int idx, int64_t n, int64_t batch, int64_t ld);
+// The configured variant if it handles (n, ld, dtype), else the first one
+// that does; -1 if none.
+int part_pick(int kind, int idx, int64_t n, int64_t ld, int dtype);
 size_t part_workspace_bytes(int kind, int idx, int64_t n, int64_t batch);
-hipError_t launch_part(int kind, int idx, int64_t n, int64_t batch, int64_t ld,
-                       Diags A, const double* y, double* x, int32_t* info,
-                       double* ws, hipStream_t st);
+// skip (nullable device flag): when *skip != 0 at launch the kernels return
+// at once (a refinement loop that has converged).
+hipError_t launch_part(int kind, int idx, int dtype, int64_t n, int64_t batch, int64_t ld,
+                       const void* const dg[5], const void* y, void* x, int32_t* info,
+                       double* ws, hipStream_t st, const int32_t* skip = nullptr);
+// Any length: three launches (tile maps, per-system reduction, finish).
+bool long_supported(int64_t n, int64_t ld, int dtype);
+size_t long_workspace_bytes(int kind, int64_t n, int64_t batch);
+hipError_t launch_long_path(int kind, int dtype, int64_t n, int64_t batch, int64_t ld,
+                            const void* const dg[5], const void* y, void* x, int32_t* info,
+                            double* ws, hipStream_t st, const int32_t* skip = nullptr);
+
+// ---- mixed-precision refinement (refine.hip) ------------------------------
+size_t refine_workspace_bytes(int kind, int64_t n, int64_t batch, int64_t ld);
+hipError_t launch_refine(int kind, int64_t n, int64_t batch, int64_t ld, const double* const dg[5],
+                         const double* rhs, double* x, double tol, int32_t max_steps,
+                         int32_t* steps, double* relres, int32_t* info, void* ws,
+                         hipStream_t st);
+
+// Fused FP32/FP64 direct solve selection shared by band_solve and refinement:
+// bytes of workspace and the launch for (kind, dtype, n, batch, ld).
+size_t direct_ws_bytes(int kind, int dtype, int64_t n, int64_t batch, int64_t ld);
+hipError_t launch_direct(int kind, int dtype, int64_t n, int64_t batch, int64_t ld,
+                         const void* const dg[5], const void* y, void* x, int32_t* info,
+                         void* ws, hipStream_t st, const int32_t* skip = nullptr);
+// false if no kernel handles this (FP32 storage needs the split or long path).
+bool direct_supported(int kind, int dtype, int64_t n, int64_t ld);
 
 // ---- SIP (sip_lane.hip) --------------------------------------------------
 hipError_t launch_sip_lane(int64_t n, int64_t batch, int64_t ld, Diags A,

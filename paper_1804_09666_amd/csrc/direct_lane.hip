@@ -20,7 +20,6 @@ namespace {
 constexpr int kLaneBlock = 64;  // one wave per block: spreads few systems over many CUs
 
 __device__ inline bool bad_pivot(double m) { return !(m != 0.0) || !isfinite(m); }
-__device__ inline bool bad_pivot(float m) { return !(m != 0.0f) || !isfinite(m); }
 
 // NPDM: gamma_i = c_i - alpha_{i-2} e_i;  mu_i = (d_i - beta_{i-2} e_i) -
 // alpha_{i-1} gamma_i;  alpha_i = (a_i - beta_{i-1} gamma_i) / mu_i;

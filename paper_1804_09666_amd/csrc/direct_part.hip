@@ -48,6 +48,17 @@ struct Node {  // interface: B_A = g0 + G1 xL + G2 xR,  T_B = h0 + H1 xL + H2 xR
 template <int NB>
 constexpr int kRecSz = 2 * NB + 4 * NB * NB;  // doubles per Map or Node
 
+// The map of a range of identity rows (no couplings, zero solution).
+template <int NB>
+__device__ inline void zero_map(Map<NB>& m) {
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    m.pt[q] = m.pb[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) m.Vt[q][k] = m.Vb[q][k] = m.Wt[q][k] = m.Wb[q][k] = 0.0;
+  }
+}
+
 template <int NB>
 __device__ inline void mm(const double (&A)[NB][NB], const double (&B)[NB][NB],
                           double (&C)[NB][NB]) {
@@ -171,13 +182,16 @@ __device__ inline void load_rec(R& r, const double* src) {
 __device__ inline bool bad_pivot(double m) { return !(m != 0.0) || !isfinite(m); }
 
 // Streaming accesses: every input element is read once and every x element
-// written once, so they carry the non-temporal hint.
-__device__ inline double ldg(const double* __restrict__ base, uint32_t byte_off) {
+// written once, so they carry the non-temporal hint.  Storage may be FP64 or
+// FP32 (TIO); arithmetic is always FP64.
+template <typename TIO>
+__device__ inline TIO ldg(const TIO* __restrict__ base, uint32_t byte_off) {
   return __builtin_nontemporal_load(
-      reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off));
+      reinterpret_cast<const TIO*>(reinterpret_cast<const char*>(base) + byte_off));
 }
-__device__ inline void stg(double* __restrict__ base, uint32_t byte_off, double v) {
-  __builtin_nontemporal_store(v, reinterpret_cast<double*>(reinterpret_cast<char*>(base) + byte_off));
+template <typename TIO>
+__device__ inline void stg(TIO* __restrict__ base, uint32_t byte_off, double v) {
+  __builtin_nontemporal_store((TIO)v, reinterpret_cast<TIO*>(reinterpret_cast<char*>(base) + byte_off));
 }
 
 // Chunk of a pentadiagonal system: local NPDM with the couplings to
@@ -380,23 +394,142 @@ constexpr int kBadNone = INT_MAX;
 constexpr int kTimeout = -4;
 constexpr uint64_t kWaitTicks = 100000000;  // 1 s of the 100 MHz real-time counter
 
+// Loads the M rows of a chunk (first row r0) of system s into registers:
+// identity rows past n, zero couplings outside the matrix.  Byte offsets fit
+// in 32 bits (checked on the host), so every load is an SGPR base plus one
+// per-row VGPR offset shared by the six arrays.
+template <int KIND, int M, typename TIO>
+__device__ inline void load_chunk(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
+                                  int64_t row_base,
+                                  const TIO* __restrict__ E, const TIO* __restrict__ C,
+                                  const TIO* __restrict__ D, const TIO* __restrict__ A,
+                                  const TIO* __restrict__ B, const TIO* __restrict__ Y,
+                                  double (&e)[M], double (&c)[M], double (&d)[M],
+                                  double (&a)[M], double (&b)[M], double (&y)[M]) {
+  const uint32_t row_bytes = (uint32_t)(ld * sizeof(TIO));
+  const uint32_t off0 = (uint32_t)((r0 * ld + s) * (int64_t)sizeof(TIO));
+  if constexpr (sizeof(TIO) == 8) {
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      const int64_t i = row_base + r0 + r;  // global row
+      const uint32_t o = off0 + (uint32_t)r * row_bytes;
+      const bool in = live && i < n;
+      d[r] = in ? ldg(D, o) : 1.0;
+      y[r] = in ? ldg(Y, o) : 0.0;
+      c[r] = (in && i >= 1) ? ldg(C, o) : 0.0;
+      a[r] = (in && i <= n - 2) ? ldg(A, o) : 0.0;
+      if (KIND == 5) {
+        e[r] = (in && i >= 2) ? ldg(E, o) : 0.0;
+        b[r] = (in && i <= n - 3) ? ldg(B, o) : 0.0;
+      } else {
+        e[r] = 0.0;
+        b[r] = 0.0;
+      }
+    }
+  } else {
+    // FP32 storage: unconditional loads (slots outside the matrix read the
+    // array's first element instead, and are replaced afterwards), all
+    // issued before the first widening to FP64 waits for its operand.
+    // Conditional loads would each sit in a branch with their widening, and
+    // the chunk's loads would then complete one at a time.
+    TIO re[M], rc[M], rd[M], ra[M], rb[M], ry[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      const int64_t i = row_base + r0 + r;
+      const uint32_t o = off0 + (uint32_t)r * row_bytes;
+      const bool in = live && i < n;
+      rd[r] = ldg(D, in ? o : 0u);
+      ry[r] = ldg(Y, in ? o : 0u);
+      rc[r] = ldg(C, (in && i >= 1) ? o : 0u);
+      ra[r] = ldg(A, (in && i <= n - 2) ? o : 0u);
+      if (KIND == 5) {
+        re[r] = ldg(E, (in && i >= 2) ? o : 0u);
+        rb[r] = ldg(B, (in && i <= n - 3) ? o : 0u);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      const int64_t i = row_base + r0 + r;
+      const bool in = live && i < n;
+      d[r] = in ? (double)rd[r] : 1.0;
+      y[r] = in ? (double)ry[r] : 0.0;
+      c[r] = (in && i >= 1) ? (double)rc[r] : 0.0;
+      a[r] = (in && i <= n - 2) ? (double)ra[r] : 0.0;
+      e[r] = (KIND == 5 && in && i >= 2) ? (double)re[r] : 0.0;
+      b[r] = (KIND == 5 && in && i <= n - 3) ? (double)rb[r] : 0.0;
+    }
+  }
+}
+
+// The chunk's affine map: tip rows of p, V, W.
+template <int NB, int M>
+__device__ inline Map<NB> chunk_map(const double (&p)[M], const double (&v)[NB][M],
+                                    const double (&w)[NB][M]) {
+  Map<NB> mp;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    mp.pt[q] = p[q];
+    mp.pb[q] = p[M - NB + q];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      mp.Vt[q][k] = v[k][q];
+      mp.Wt[q][k] = w[k][q];
+      mp.Vb[q][k] = v[k][M - NB + q];
+      mp.Wb[q][k] = w[k][M - NB + q];
+    }
+  }
+  return mp;
+}
+
+template <int KIND, int M>
+__device__ inline void eliminate_chunk(const double (&e)[M], const double (&c)[M],
+                                       const double (&d)[M], const double (&a)[M],
+                                       const double (&b)[M], const double (&y)[M],
+                                       double (&p)[M], double (&v)[KIND == 5 ? 2 : 1][M],
+                                       double (&w)[KIND == 5 ? 2 : 1][M], int& bad) {
+  if constexpr (KIND == 5)
+    chunk_pd<M>(e, c, d, a, b, y, p, v[0], v[1], w[0], w[1], bad);
+  else
+    chunk_td<M>(c, d, a, y, p, v[0], w[0], bad);
+}
+
+template <int NB, int M, typename TIO>
+__device__ inline void write_chunk(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
+                                   int64_t row_base,
+                                   const double (&p)[M], const double (&v)[NB][M],
+                                   const double (&w)[NB][M], const double (&xl)[NB],
+                                   const double (&xr)[NB], TIO* __restrict__ X) {
+  const uint32_t row_bytes = (uint32_t)(ld * sizeof(TIO));
+  const uint32_t off0 = (uint32_t)((r0 * ld + s) * (int64_t)sizeof(TIO));
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    const int64_t i = row_base + r0 + r;
+    double xv = p[r];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) xv = fma(-v[k][r], xl[k], fma(-w[k][r], xr[k], xv));
+    if (live && i < n) stg(X, off0 + (uint32_t)r * row_bytes, xv);
+  }
+}
+
 // One block = G systems x PW chunks of M rows = one tile of RT = M*PW rows of
 // G systems.  T <= TMAX tiles (consecutive blocks on one XCD) cover a system;
 // they exchange their tile maps through `xch` and meet at the counter pair
 // cnt[2*grp], cnt[2*grp+1] (arrivals, departures; reset by the last tile to
 // leave, so the counters are zero again after every completed call).
-template <int KIND, int M, int PW, int G, int TMAX, int WPE>
+template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE>
 __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void part_kernel(
-    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
-    const double* __restrict__ C, const double* __restrict__ D,
-    const double* __restrict__ A, const double* __restrict__ B,
-    const double* __restrict__ Y, double* __restrict__ X,
+    int64_t n, int64_t batch, int64_t ld, const TIO* __restrict__ E,
+    const TIO* __restrict__ C, const TIO* __restrict__ D,
+    const TIO* __restrict__ A, const TIO* __restrict__ B,
+    const TIO* __restrict__ Y, TIO* __restrict__ X,
     int32_t* __restrict__ info, double* __restrict__ xch,
-    unsigned* __restrict__ cnt, int T) {
+    unsigned* __restrict__ cnt, int T, const int32_t* __restrict__ skip) {
   constexpr int NB = KIND == 5 ? 2 : 1;
   constexpr int RS = kRecSz<NB>;
   constexpr int RT = M * PW;
   static_assert((PW & (PW - 1)) == 0 && (TMAX & (TMAX - 1)) == 0 && M >= 4, "shape");
+  if (skip != nullptr && *skip) return;  // uniform: a refinement loop has finished
   __shared__ double s_node[(PW - 1) * G * RS];
   __shared__ double s_gnode[(TMAX > 1 ? TMAX - 1 : 1) * G * RS];
   __shared__ double s_bnd[G * 2 * NB];
@@ -426,48 +559,12 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
   if (tid == 0) s_timeout = 0;
 
   // ---- 1. load the chunk and eliminate it locally -------------------------
-  // Byte offsets fit in 32 bits (checked on the host), so every load is an
-  // SGPR base plus one per-row VGPR offset shared by the six arrays.
   double c[M], d[M], a[M], y[M], e[M], b[M];
-  const uint32_t row_bytes = (uint32_t)(ld * 8);
-  const uint32_t off0 = (uint32_t)((r0 * ld + s) * 8);
-#pragma unroll
-  for (int r = 0; r < M; ++r) {
-    const int64_t i = r0 + r;
-    const uint32_t o = off0 + (uint32_t)r * row_bytes;
-    const bool in = live && i < n;
-    d[r] = in ? ldg(D, o) : 1.0;
-    y[r] = in ? ldg(Y, o) : 0.0;
-    c[r] = (in && i >= 1) ? ldg(C, o) : 0.0;
-    a[r] = (in && i <= n - 2) ? ldg(A, o) : 0.0;
-    if (KIND == 5) {
-      e[r] = (in && i >= 2) ? ldg(E, o) : 0.0;
-      b[r] = (in && i <= n - 3) ? ldg(B, o) : 0.0;
-    } else {
-      e[r] = 0.0;
-      b[r] = 0.0;
-    }
-  }
+  load_chunk<KIND, M>(n, ld, s, live, r0, 0, E, C, D, A, B, Y, e, c, d, a, b, y);
   double p[M], v[NB][M], w[NB][M];
   int bad;
-  if constexpr (KIND == 5)
-    chunk_pd<M>(e, c, d, a, b, y, p, v[0], v[1], w[0], w[1], bad);
-  else
-    chunk_td<M>(c, d, a, y, p, v[0], w[0], bad);
-
-  Map<NB> mp;
-#pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    mp.pt[q] = p[q];
-    mp.pb[q] = p[M - NB + q];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) {
-      mp.Vt[q][k] = v[k][q];
-      mp.Wt[q][k] = w[k][q];
-      mp.Vb[q][k] = v[k][M - NB + q];
-      mp.Wb[q][k] = w[k][M - NB + q];
-    }
-  }
+  eliminate_chunk<KIND, M>(e, c, d, a, b, y, p, v, w, bad);
+  Map<NB> mp = chunk_map<NB, M>(p, v, w);
   __syncthreads();  // s_bad initialised
   if (bad < M && r0 + bad < n) atomicMin(&s_bad[g], (int)(r0 + bad + 1));
 
@@ -516,12 +613,7 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
         const double tb = ld_coherent(src + RS);
         if (tb < (double)kBadNone) atomicMin(&s_bad[g], (int)tb);
       } else {  // tiles past the last one: all identity rows
-#pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          gm.pt[q] = gm.pb[q] = 0.0;
-#pragma unroll
-          for (int k = 0; k < NB; ++k) gm.Vt[q][k] = gm.Vb[q][k] = gm.Wt[q][k] = gm.Wb[q][k] = 0.0;
-        }
+        zero_map(gm);
       }
     }
     __syncthreads();  // every tile map read: this tile may leave
@@ -560,17 +652,171 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
 
   // ---- 3. back down the tile's tree, then x = p - V x_L - W x_R ---------
   tree_down<NB, PW, G>(xl, xr, j, g, s_node);
-#pragma unroll
-  for (int r = 0; r < M; ++r) {
-    const int64_t i = r0 + r;
-    double xv = p[r];
-#pragma unroll
-    for (int k = 0; k < NB; ++k) xv = fma(-v[k][r], xl[k], fma(-w[k][r], xr[k], xv));
-    if (live && i < n) stg(X, off0 + (uint32_t)r * row_bytes, xv);
-  }
+  write_chunk<NB, M>(n, ld, s, live, r0, 0, p, v, w, xl, xr, X);
   if (j == 0 && tile == 0 && live) {
     const int b0 = s_bad[g];
     info[s] = s_timeout ? kTimeout : ((b0 == kBadNone) ? 0 : b0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Long systems (more tiles than one group of blocks can exchange at once):
+// three launches.
+//   long_tile_kernel<FINISH=false>: every tile's local eliminations and tree,
+//     tile map (and first bad row) to `maps`;
+//   long_reduce_kernel: per system, the tile maps are folded left to right
+//     within each lane's run of tiles, then merged up a tree across the lanes
+//     of one wave; walking back down gives every tile its outer pairs
+//     (`bounds`) and the system its info;
+//   long_tile_kernel<FINISH=true>: every tile reloads its rows, repeats the
+//     same local eliminations and tree (bitwise the same maps), walks down
+//     from its outer pairs and writes x.
+// Inputs are read twice; no per-row state goes through memory.
+// ---------------------------------------------------------------------------
+template <bool FINISH, typename TIO, int KIND, int M, int PW, int G>
+__global__ __launch_bounds__(G * PW) void long_tile_kernel(
+    int64_t n, int64_t batch, int64_t ld, const TIO* __restrict__ E,
+    const TIO* __restrict__ C, const TIO* __restrict__ D,
+    const TIO* __restrict__ A, const TIO* __restrict__ B,
+    const TIO* __restrict__ Y, TIO* __restrict__ X, double* __restrict__ maps,
+    const double* __restrict__ bounds, int64_t T, const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  constexpr int NB = KIND == 5 ? 2 : 1;
+  constexpr int RS = kRecSz<NB>;
+  constexpr int XS = RS + 1;
+  constexpr int RT = M * PW;
+  __shared__ double s_node[(PW - 1) * G * RS];
+  __shared__ int s_bad[G];
+  const int tid = threadIdx.x;
+  const int g = tid % G;
+  const int j = tid / G;
+  const int64_t grp = blockIdx.x / T, tile = blockIdx.x % T;
+  const int64_t s = grp * G + g;
+  const bool live = s < batch;
+  const int64_t row_base = tile * RT;  // pointers rebased to the tile: 32-bit offsets inside it
+  const int64_t shift = row_base * ld;
+  const int64_t r0 = (int64_t)j * M;
+  if (tid < G) s_bad[tid] = kBadNone;
+  double c[M], d[M], a[M], y[M], e[M], b[M];
+  load_chunk<KIND, M>(n, ld, s, live, r0, row_base, KIND == 5 ? E + shift : E, C + shift,
+                      D + shift, A + shift, KIND == 5 ? B + shift : B, Y + shift, e, c, d, a,
+                      b, y);
+  double p[M], v[NB][M], w[NB][M];
+  int bad;
+  eliminate_chunk<KIND, M>(e, c, d, a, b, y, p, v, w, bad);
+  Map<NB> mp = chunk_map<NB, M>(p, v, w);
+  __syncthreads();
+  if (!FINISH && bad < M && row_base + r0 + bad < n)
+    atomicMin(&s_bad[g], (int)(row_base + r0 + bad + 1));
+  tree_up<NB, PW, G>(mp, j, g, s_node, s_bad, M, row_base, n);
+  const int64_t rec = (grp * T + tile) * G + g;
+  if constexpr (!FINISH) {
+    if (j == 0) {
+      double* dst = maps + rec * XS;
+      store_rec(mp, dst);
+      dst[RS] = (double)s_bad[g];
+    }
+  } else {
+    double xl[NB] = {}, xr[NB] = {};
+    if (j == 0) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        xl[q] = bounds[rec * 2 * NB + q];
+        xr[q] = bounds[rec * 2 * NB + NB + q];
+      }
+    }
+    __syncthreads();
+    tree_down<NB, PW, G>(xl, xr, j, g, s_node);
+    write_chunk<NB, M>(n, ld, s, live, r0, row_base, p, v, w, xl, xr, X + shift);
+  }
+}
+
+// One wave per system: lane l folds tiles [l*R, (l+1)*R) left to right
+// (node records to `nodes`), then the 64 lane maps merge up a tree in LDS.
+template <int KIND, int G>
+__global__ __launch_bounds__(256) void long_reduce_kernel(
+    int64_t n, int64_t batch, int64_t T, int64_t rows_per_tile,
+    const double* __restrict__ maps, double* __restrict__ nodes,
+    double* __restrict__ bounds, int32_t* __restrict__ info, const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  constexpr int NB = KIND == 5 ? 2 : 1;
+  constexpr int RS = kRecSz<NB>;
+  constexpr int XS = RS + 1;
+  constexpr int WPB = 4;  // systems (waves) per block
+  __shared__ double s_node[WPB * 63 * RS];
+  __shared__ int s_bad[WPB];
+  const int lane = threadIdx.x % 64;
+  const int wv = threadIdx.x / 64;
+  const int64_t s = (int64_t)blockIdx.x * WPB + wv;
+  const bool live = s < batch;
+  const int64_t grp = s / G, g = s % G;
+  const int64_t R = (T + 63) / 64;
+  const int64_t t0 = lane * R, t1 = (t0 + R < T) ? t0 + R : T;
+  if (lane == 0) s_bad[wv] = kBadNone;
+  __syncthreads();
+  Map<NB> acc;
+  zero_map(acc);
+  int bad = kBadNone;
+  if (live) {
+    for (int64_t t = t0; t < t1; ++t) {
+      const double* src = maps + ((grp * T + t) * G + g) * XS;
+      Map<NB> m;
+      load_rec(m, src);
+      const double tb = src[RS];
+      if (tb < (double)bad) bad = (int)tb;
+      if (t == t0) {
+        acc = m;
+      } else {
+        Node<NB> nd;
+        if (!merge<NB>(acc, m, acc, nd)) {
+          const int64_t row = t * rows_per_tile - NB;
+          if (row < n && row + 1 < bad) bad = (int)(row + 1);
+        }
+        store_rec(nd, nodes + (s * T + t) * RS);
+      }
+    }
+  }
+  if (bad != kBadNone) atomicMin(&s_bad[wv], bad);
+  // tree over the 64 runs of this wave (empty runs are zero maps)
+  tree_up<NB, 64, 1>(acc, lane, 0, s_node + wv * 63 * RS, s_bad + wv, R * rows_per_tile, 0, n);
+  double xl[NB], xr[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) xl[q] = xr[q] = 0.0;
+  __syncthreads();
+  tree_down<NB, 64, 1>(xl, xr, lane, 0, s_node + wv * 63 * RS);
+  // walk back through this lane's run
+  if (live && t0 < t1) {
+    for (int64_t t = t1 - 1; t > t0; --t) {
+      Node<NB> nd;
+      load_rec(nd, nodes + (s * T + t) * RS);
+      double ba[NB], tb[NB], u1[NB], u2[NB];
+      mv<NB>(nd.G1, xl, u1);
+      mv<NB>(nd.G2, xr, u2);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) ba[q] = nd.g0[q] + u1[q] + u2[q];
+      mv<NB>(nd.H1, xl, u1);
+      mv<NB>(nd.H2, xr, u2);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) tb[q] = nd.h0[q] + u1[q] + u2[q];
+      double* dst = bounds + ((grp * T + t) * G + g) * 2 * NB;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        dst[q] = ba[q];
+        dst[NB + q] = xr[q];
+        xr[q] = tb[q];
+      }
+    }
+    double* dst = bounds + ((grp * T + t0) * G + g) * 2 * NB;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      dst[q] = xl[q];
+      dst[NB + q] = xr[q];
+    }
+  }
+  __syncthreads();
+  if (lane == 0 && live) {
+    const int b0 = s_bad[wv];
+    info[s] = (b0 == kBadNone) ? 0 : b0;
   }
 }
 
@@ -578,23 +824,58 @@ struct Variant {
   int kind, M, PW, G, TMAX, WPE;  // WPE: waves per SIMD the register budget targets
 };
 
-// Compiled variants; index 0 of each kind is the default.
+// Compiled single-launch variants; index 0 of each kind is the default.
 constexpr Variant kVariants[] = {
-    {5, 32, 16, 16, 4, 1}, {5, 16, 16, 16, 8, 2}, {5, 16, 16, 16, 8, 1}, {5, 8, 32, 16, 8, 1},
-    {3, 32, 16, 16, 4, 1}, {3, 16, 16, 16, 8, 2}, {3, 16, 32, 16, 4, 2}, {3, 8, 64, 16, 4, 4},
+    {5, 32, 16, 16, 4, 1}, {5, 32, 16, 16, 8, 1}, {5, 16, 16, 16, 8, 1}, {5, 8, 32, 16, 8, 1},
+    {3, 32, 16, 16, 4, 1}, {3, 32, 16, 16, 8, 1}, {3, 16, 16, 16, 8, 2}, {3, 16, 32, 16, 4, 2},
 };
+// Shape of the long-system path (both kinds).
+constexpr int kLongM = 32, kLongPW = 16, kLongG = 16;
 
-template <int KIND, int M, int PW, int G, int TMAX, int WPE>
-hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, Diags A, const double* y,
-                      double* x, int32_t* info, double* ws, hipStream_t st) {
+template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE>
+hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, const void* const* dg,
+                      const void* y, void* x, int32_t* info, double* ws, hipStream_t st,
+                      const int32_t* skip) {
   constexpr int RT = M * PW;
   const int T = (int)((n + RT - 1) / RT);
   const int64_t groups = (batch + G - 1) / G;
   unsigned* cnt = (T > 1) ? reinterpret_cast<unsigned*>(ws) : nullptr;
   double* xch = (T > 1) ? ws + (2 * groups + 1) / 2 + 1 : nullptr;
-  hipLaunchKernelGGL((part_kernel<KIND, M, PW, G, TMAX, WPE>), dim3((unsigned)(groups * T)),
-                     dim3(G * PW), 0, st, n, batch, ld, A.e, A.c, A.d, A.a, A.b, y, x,
-                     info, xch, cnt, T);
+  hipLaunchKernelGGL((part_kernel<TIO, KIND, M, PW, G, TMAX, WPE>), dim3((unsigned)(groups * T)),
+                     dim3(G * PW), 0, st, n, batch, ld, (const TIO*)dg[0], (const TIO*)dg[1],
+                     (const TIO*)dg[2], (const TIO*)dg[3], (const TIO*)dg[4], (const TIO*)y,
+                     (TIO*)x, info, xch, cnt, T, skip);
+  return hipGetLastError();
+}
+
+template <typename TIO, int KIND>
+hipError_t launch_long(int64_t n, int64_t batch, int64_t ld, const void* const* dg,
+                       const void* y, void* x, int32_t* info, double* ws, hipStream_t st,
+                       const int32_t* skip) {
+  constexpr int M = kLongM, PW = kLongPW, G = kLongG;
+  constexpr int NB = KIND == 5 ? 2 : 1;
+  constexpr int RS = kRecSz<NB>;
+  const int64_t RT = (int64_t)M * PW;
+  const int64_t T = (n + RT - 1) / RT;
+  const int64_t groups = (batch + G - 1) / G;
+  const int64_t recs = groups * T * G;
+  double* maps = ws;
+  double* bounds = maps + recs * (RS + 1);
+  double* nodes = bounds + recs * 2 * NB;
+  const TIO* P[6] = {(const TIO*)dg[0], (const TIO*)dg[1], (const TIO*)dg[2],
+                     (const TIO*)dg[3], (const TIO*)dg[4], (const TIO*)y};
+  hipLaunchKernelGGL((long_tile_kernel<false, TIO, KIND, M, PW, G>), dim3((unsigned)(groups * T)),
+                     dim3(G * PW), 0, st, n, batch, ld, P[0], P[1], P[2], P[3], P[4], P[5],
+                     (TIO*)x, maps, bounds, T, skip);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((long_reduce_kernel<KIND, G>), dim3((unsigned)((batch + 3) / 4)), dim3(256),
+                     0, st, n, batch, T, RT, maps, nodes, bounds, info, skip);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((long_tile_kernel<true, TIO, KIND, M, PW, G>), dim3((unsigned)(groups * T)),
+                     dim3(G * PW), 0, st, n, batch, ld, P[0], P[1], P[2], P[3], P[4], P[5],
+                     (TIO*)x, maps, bounds, T, skip);
   return hipGetLastError();
 }
 
@@ -623,14 +904,26 @@ bool part_variant_shape(int kind, int idx, int out[4]) {
   return true;
 }
 
-bool part_supported(int kind, int idx, int64_t n, int64_t batch, int64_t ld) {
-  (void)batch;
-  const Variant* v = find_variant(kind, idx);
-  if (!v) return false;
+// FP32 storage is compiled for the first two variants of each kind.
+static bool has_f32(int kind, int idx) {
+  (void)kind;
+  return idx == 0 || idx == 1;
+}
+
+static bool covers(const Variant* v, int64_t n, int64_t ld, int dtype) {
+  const int64_t esz = dtype == 1 ? 4 : 8;
   if (n < 8 || n > (int64_t)v->M * v->PW * v->TMAX) return false;
-  // per-lane byte offsets are 32-bit
-  if ((n + 1) * ld * 8 >= (int64_t(1) << 32)) return false;
-  return true;
+  return (n + 1) * ld * esz < (int64_t(1) << 32);  // per-lane byte offsets are 32-bit
+}
+
+int part_pick(int kind, int idx, int64_t n, int64_t ld, int dtype) {
+  const Variant* v = find_variant(kind, idx);
+  if (v && covers(v, n, ld, dtype) && (dtype == 0 || has_f32(kind, idx))) return idx;
+  for (int k = 0; k < part_variant_count(kind); ++k) {
+    v = find_variant(kind, k);
+    if (covers(v, n, ld, dtype) && (dtype == 0 || has_f32(kind, k))) return k;
+  }
+  return -1;
 }
 
 size_t part_workspace_bytes(int kind, int idx, int64_t n, int64_t batch) {
@@ -644,20 +937,50 @@ size_t part_workspace_bytes(int kind, int idx, int64_t n, int64_t batch) {
   return (size_t)(((2 * groups + 1) / 2 + 1) + groups * T * v->G * rs) * 8;
 }
 
-hipError_t launch_part(int kind, int idx, int64_t n, int64_t batch, int64_t ld,
-                       Diags A, const double* y, double* x, int32_t* info,
-                       double* ws, hipStream_t st) {
+hipError_t launch_part(int kind, int idx, int dtype, int64_t n, int64_t batch, int64_t ld,
+                       const void* const dg[5], const void* y, void* x, int32_t* info,
+                       double* ws, hipStream_t st, const int32_t* skip) {
   const Variant* v = find_variant(kind, idx);
   if (!v) return hipErrorInvalidValue;
-#define BS_PV(K, MM, PP, GG, TT, WW)                                                  \
+#define BS_PV(TIO, K, MM, PP, GG, TT, WW)                                                \
   if (v->kind == K && v->M == MM && v->PW == PP && v->G == GG && v->TMAX == TT &&        \
       v->WPE == WW)                                                                      \
-    return launch_cfg<K, MM, PP, GG, TT, WW>(n, batch, ld, A, y, x, info, ws, st);
-  BS_PV(5, 32, 16, 16, 4, 1) BS_PV(5, 16, 16, 16, 8, 2) BS_PV(5, 16, 16, 16, 8, 1)
-  BS_PV(5, 8, 32, 16, 8, 1) BS_PV(3, 32, 16, 16, 4, 1) BS_PV(3, 16, 16, 16, 8, 2)
-  BS_PV(3, 16, 32, 16, 4, 2) BS_PV(3, 8, 64, 16, 4, 4)
+    return launch_cfg<TIO, K, MM, PP, GG, TT, WW>(n, batch, ld, dg, y, x, info, ws, st, skip);
+  if (dtype == 0) {
+    BS_PV(double, 5, 32, 16, 16, 4, 1) BS_PV(double, 5, 32, 16, 16, 8, 1)
+    BS_PV(double, 5, 16, 16, 16, 8, 1) BS_PV(double, 5, 8, 32, 16, 8, 1)
+    BS_PV(double, 3, 32, 16, 16, 4, 1) BS_PV(double, 3, 32, 16, 16, 8, 1)
+    BS_PV(double, 3, 16, 16, 16, 8, 2) BS_PV(double, 3, 16, 32, 16, 4, 2)
+  } else {
+    BS_PV(float, 5, 32, 16, 16, 4, 1) BS_PV(float, 5, 32, 16, 16, 8, 1)
+    BS_PV(float, 3, 32, 16, 16, 4, 1) BS_PV(float, 3, 32, 16, 16, 8, 1)
+  }
 #undef BS_PV
   return hipErrorInvalidValue;
+}
+
+bool long_supported(int64_t n, int64_t ld, int dtype) {
+  const int64_t esz = dtype == 1 ? 4 : 8;
+  return n >= 8 && (int64_t)(kLongM * kLongPW + 1) * ld * esz < (int64_t(1) << 32);
+}
+
+size_t long_workspace_bytes(int kind, int64_t n, int64_t batch) {
+  const int64_t NB = kind == 5 ? 2 : 1;
+  const int64_t RS = 2 * NB + 4 * NB * NB;
+  const int64_t RT = (int64_t)kLongM * kLongPW;
+  const int64_t T = (n + RT - 1) / RT;
+  const int64_t recs = (batch + kLongG - 1) / kLongG * T * kLongG;
+  return (size_t)(recs * (RS + 1) + recs * 2 * NB + (int64_t)batch * T * RS) * 8;
+}
+
+hipError_t launch_long_path(int kind, int dtype, int64_t n, int64_t batch, int64_t ld,
+                            const void* const dg[5], const void* y, void* x, int32_t* info,
+                            double* ws, hipStream_t st, const int32_t* skip) {
+  if (dtype == 0)
+    return kind == 5 ? launch_long<double, 5>(n, batch, ld, dg, y, x, info, ws, st, skip)
+                     : launch_long<double, 3>(n, batch, ld, dg, y, x, info, ws, st, skip);
+  return kind == 5 ? launch_long<float, 5>(n, batch, ld, dg, y, x, info, ws, st, skip)
+                   : launch_long<float, 3>(n, batch, ld, dg, y, x, info, ws, st, skip);
 }
 
 }  // namespace bs

@@ -129,6 +129,32 @@ def sweep_lines(v, r, order):
     return dict(e=e, c=c, d=d, a=a, b=b, y=y)
 
 
+def sweep_lines_interleaved(vt, r, order):
+    """sweep_lines for lines stored along the FIRST axis (vt[i, s] = node i of
+    line s, the batch-interleaved layout) on numpy arrays or torch tensors of
+    any device: the same elementwise operations in the same order, so the
+    coefficients are bitwise those of sweep_lines on vt.T (no fused
+    multiply-add: every product and sum is its own rounded operation)."""
+    n = vt.shape[0]
+    kv = 1.0 + vt * vt
+    kh = 0.5 * (kv[:-1] + kv[1:])               # k_{i+1/2}, i = 0..n-2
+    zeros = (lambda: vt * 0.0)
+    e, c, d, a, b, y = zeros(), zeros(), zeros(), zeros(), zeros(), zeros()
+    c[1:-1] = -r * kh[:-1]
+    a[1:-1] = -r * kh[1:]
+    d[1:-1] = 1.0 + r * (kh[:-1] + kh[1:])
+    y[1:-1] = vt[1:-1]
+    if order == 1:
+        d[0], a[0] = 1.0, -1.0
+        c[-1], d[-1] = -1.0, 1.0
+    elif order == 2:
+        d[0], a[0], b[0] = -3.0, 4.0, -1.0
+        e[-1], c[-1], d[-1] = 1.0, -4.0, 3.0
+    else:
+        raise ValueError("order must be 1 or 2")
+    return dict(e=e, c=c, d=d, a=a, b=b, y=y)
+
+
 def adi_sweep(u, r, order, axis):
     """Systems of one sweep of a 2-D field u[iy, ix]: axis='x' gives one
     system per grid row (lines along x), axis='y' one per grid column."""

@@ -68,8 +68,33 @@ def test_workspace_query(bs):
     assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch) == \
         ((2 * groups + 1) // 2 + 1 + groups * T * G * 21) * 8
     assert bs.workspace_bytes(bs.OP_SOLVE, 5, M * PW, batch) == 0
-    assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2 * M * PW * TMAX, batch) == \
-        2 * 2 * M * PW * TMAX * lw * 8
+    # n beyond every single-launch variant: the three-launch path keeps one
+    # record per tile (tile map + first bad row, outer pairs, fold node)
+    n_long = 40000
+    for kind, nb in ((5, 2), (3, 1)):
+        rs = 2 * nb + 4 * nb * nb
+        T = -(-n_long // (32 * 16))
+        recs = -(-batch // 16) * T * 16
+        assert bs.workspace_bytes(bs.OP_SOLVE, kind, n_long, batch) == \
+            (recs * (rs + 1) + recs * 2 * nb + batch * T * rs) * 8
+    # FP32 storage: the split kernels only (n >= 8), fused solve only
+    assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch, bs.BS_F32) == \
+        bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch)
+    assert lib.bs_workspace_bytes(bs.OP_SOLVE, 5, bs.BS_F32, 4, batch, batch) == bad
+    assert lib.bs_workspace_bytes(bs.OP_SIP, 5, bs.BS_F32, n, batch, batch) == bad
+    assert lib.bs_workspace_bytes(bs.OP_REFINE, 5, bs.BS_F32, n, batch, batch) == bad
+    # refinement: FP32 copy of A (5 or 3 planes), r, d, per-system flags, solver
+    for kind, planes in ((5, 5), (3, 3)):
+        got = bs.workspace_bytes(bs.OP_REFINE, kind, 2048, batch)
+        assert got >= (planes + 2) * 2048 * batch * 4 + \
+            bs.workspace_bytes(bs.OP_SOLVE, kind, 2048, batch, bs.BS_F32)
+        assert got % 256 == 0
+    assert lib.bs_workspace_bytes(bs.OP_REFINE, 5, 0, 4, batch, batch) == bad
+    bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_LANE)
+    try:   # one lane per system has no FP32 kernel
+        assert lib.bs_workspace_bytes(bs.OP_SOLVE, 5, bs.BS_F32, 2048, batch, batch) == bad
+    finally:
+        bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_AUTO)
 
 
 def test_options(bs):
@@ -122,6 +147,23 @@ def test_invalid_arguments_rejected_on_host(bs):
     if need:
         assert lib.band_solve(5, 0, n, batch, ld, d5, None, y, x, info, ws, need - 1,
                               None) == bs.BS_EWORKSPACE
+    # FP32 storage: fused solve only, n >= 8
+    assert lib.band_solve(5, 1, n, batch, ld, d5, _fake(6), y, x, info, ws, big, None) == E
+    assert lib.band_solve(5, 1, 4, batch, ld, d5, None, y, x, info, ws, big, None) == E
+    # band_solve_refine
+    st, rr = _fake(11), _fake(12)
+    ws256 = ctypes.c_void_p(0x100000)
+    R = lib.band_solve_refine
+    assert R(4, n, batch, ld, d5, y, x, 1e-12, 4, st, rr, info, ws256, big, None) == E
+    assert R(5, 4, batch, ld, d5, y, x, 1e-12, 4, st, rr, info, ws256, big, None) == E
+    assert R(5, n, batch, ld, d5, y, y, 1e-12, 4, st, rr, info, ws256, big, None) == E
+    assert R(5, n, batch, ld, d5, y, x, 0.0, 4, st, rr, info, ws256, big, None) == E
+    assert R(5, n, batch, ld, d5, y, x, 1e-12, 0, st, rr, info, ws256, big, None) == E
+    assert R(5, n, batch, ld, d5, y, x, 1e-12, 4, None, rr, info, ws256, big, None) == E
+    assert R(5, n, batch, ld, d5, y, x, 1e-12, 4, st, rr, info, ctypes.c_void_p(0x100008), big,
+             None) == E  # not 256-byte aligned
+    assert R(5, n, batch, ld, d5, y, x, 1e-12, 4, st, rr, info, ws256, 0, None) == \
+        bs.BS_EWORKSPACE
     # band_factor
     assert lib.band_factor(5, 0, n, batch, ld, d5, None, info, None) == E
     assert lib.band_factor(6, 0, n, batch, ld, d5, x, info, None) == E

@@ -48,7 +48,8 @@ def test_config0_parity(kind, path):
 @pytest.mark.parametrize("kind", [5, 3])
 @pytest.mark.parametrize("n,batch,ld", [(1, 5, 64), (2, 3, 3), (3, 70, 128), (4, 64, 64),
                                         (8, 9, 9), (37, 1, 1), (129, 67, 80), (1000, 200, 256),
-                                        (2047, 33, 64), (2048, 5, 5)])
+                                        (2047, 33, 64), (2048, 5, 5), (3000, 9, 16),
+                                        (4096, 20, 64)])
 def test_shapes_ragged_and_tiny(kind, n, batch, ld, path):
     ws = wl.dominant_batch(batch, n, kind=kind, seed=1000 + n + batch)
     say(f"shape kind={kind} n={n} batch={batch} ld={ld} path={path}")
