@@ -103,12 +103,16 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
  *                          system for n < 8), 1 one lane per system (FP64)
  *   BS_OPT_PART_PD_VARIANT index of the split-row PD kernel variant
  *   BS_OPT_PART_TD_VARIANT index of the split-row TD kernel variant
+ *   BS_OPT_SIP_PATH        sip_solve kernel: 0 and 2 rows of a system split
+ *                          over lanes where the HB steps allow it (default),
+ *                          1 one lane per system
  * bs_set_option returns BS_EINVAL for an unknown key or a value out of range;
  * bs_get_option returns -1 for an unknown key. */
 enum bs_option_code {
   BS_OPT_DIRECT_PATH = 0,
   BS_OPT_PART_PD_VARIANT = 1,
-  BS_OPT_PART_TD_VARIANT = 2
+  BS_OPT_PART_TD_VARIANT = 2,
+  BS_OPT_SIP_PATH = 3
 };
 int32_t bs_set_option(int32_t key, int64_t value);
 int64_t bs_get_option(int32_t key);
@@ -217,7 +221,15 @@ int32_t band_solve_mnpdm(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
  * Stop when ||b - A x||_inf < tol * ||b||_inf (relative form of the paper's
  *   errorMargin test, checked before every step) or after max_iter steps.
  * iters[s] (int32), relres[s] (double, final relative residual) and info[s]
- * (0, -1, -2 or a pivot row + 1) are written per system.  dtype BS_F64. */
+ * (0, -1, -2 or a pivot row + 1) are written per system.  dtype BS_F64.
+ * Kernels: with HB for both factors (s_L, s_U >= 0, 2^s < n, and
+ *   2^s_L + 2^s_U <= 96) the rows of a system are split over many lanes and
+ *   every step is one launch over all rows plus a one-block status launch:
+ *   max_iter + 1 step launches are enqueued, and those after the last system
+ *   has stopped return at once.  Otherwise (exact substitution, Algorithm 1
+ *   as written) one lane walks each system in one persistent launch.
+ * workspace: bs_workspace_bytes(BS_OP_SIP, ...) bytes, 256-byte aligned; its
+ *   contents need no initialisation.  x and rhs must not alias. */
 int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
                   const void* const diags[5], const void* factors,
                   const void* rhs, void* x, double tol, int32_t max_iter,

@@ -27,7 +27,7 @@ OP_FACTOR, OP_SOLVE, OP_SOLVE_FACTORED, OP_MNPDM, OP_SIP, OP_REFINE = range(6)
 EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "bs_set_option",
             "bs_get_option", "bs_part_variant", "band_factor", "band_solve",
             "band_solve_refine", "band_solve_mnpdm", "sip_solve")
-OPT_DIRECT_PATH, OPT_PART_PD_VARIANT, OPT_PART_TD_VARIANT = range(3)
+OPT_DIRECT_PATH, OPT_PART_PD_VARIANT, OPT_PART_TD_VARIANT, OPT_SIP_PATH = range(4)
 PATH_AUTO, PATH_LANE, PATH_PART = range(3)
 
 

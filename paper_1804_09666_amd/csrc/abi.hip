@@ -59,6 +59,7 @@ bs::Diags as_diags(int32_t kind, const void* const diags[5]) {
 // Tuning options (process-wide).
 std::atomic<int64_t> g_direct_path{0};
 std::atomic<int64_t> g_pd_variant{0}, g_td_variant{0};
+std::atomic<int64_t> g_sip_path{0};
 
 int part_idx(int32_t kind) { return (int)(kind == 5 ? g_pd_variant.load() : g_td_variant.load()); }
 
@@ -155,6 +156,10 @@ int32_t bs_set_option(int32_t key, int64_t value) {
       if (value < 0 || value > 2) return BS_EINVAL;
       g_direct_path = value;
       return BS_OK;
+    case BS_OPT_SIP_PATH:
+      if (value < 0 || value > 2) return BS_EINVAL;
+      g_sip_path = value;
+      return BS_OK;
     case BS_OPT_PART_PD_VARIANT:
     case BS_OPT_PART_TD_VARIANT: {
       const int kind = key == BS_OPT_PART_PD_VARIANT ? 5 : 3;
@@ -172,6 +177,7 @@ int64_t bs_get_option(int32_t key) {
     case BS_OPT_DIRECT_PATH: return g_direct_path.load();
     case BS_OPT_PART_PD_VARIANT: return g_pd_variant.load();
     case BS_OPT_PART_TD_VARIANT: return g_td_variant.load();
+    case BS_OPT_SIP_PATH: return g_sip_path.load();
     default: return -1;
   }
 }
@@ -201,10 +207,14 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
       return kind_ok(kind) ? 0 : bad;
     case BS_OP_MNPDM:
       return (size_t)(2 * plane) * 8;
-    case BS_OP_SIP:
-      // ILU(0) factors (4 planes, batch-interleaved with ld = ws_ld) + 1 plane
-      // for the forward pass result
-      return (size_t)(5 * plane) * 8;
+    case BS_OP_SIP: {
+      // ILU(0) factors (4 planes, batch-interleaved with pitch ws_ld), then
+      // either one plane for the forward pass (one lane per system) or the
+      // second x buffer and per-system state (rows split over lanes)
+      const size_t lane = (size_t)plane * 8;
+      const size_t tile = bs::sip_tile_workspace_bytes(n, batch, ld);
+      return (size_t)(4 * plane) * 8 + (lane > tile ? lane : tile);
+    }
     case BS_OP_REFINE:
       if (!kind_ok(kind) || !bs::direct_supported(kind, BS_F32, n, ld)) return bad;
       return bs::refine_workspace_bytes(kind, n, batch, ld);
@@ -337,20 +347,24 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
   const int64_t lw = bs::ws_ld(batch);
   const double* F = static_cast<const double*>(factors);
   int64_t fld = ld;  // pitch of caller-provided factors (band_factor output)
-  if (F == nullptr) {
-    // ILU(0) into the first 4 workspace planes (pitch lw), then the plane for
-    // the forward-pass result
-    double* Fw = ws;
-    ws = ws + 4 * n * lw;
+  const bool own = F == nullptr;
+  if (own) {
+    // ILU(0) into the first 4 workspace planes (pitch lw)
     fld = lw;
-    if (bs::launch_factor_lane(5, n, batch, ld, A, Fw, fld, info, st) != hipSuccess)
+    if (bs::launch_factor_lane(5, n, batch, ld, A, ws, fld, info, st) != hipSuccess)
       return BS_ELAUNCH;
-    F = Fw;
+    F = ws;
   }
+  double* rest = ws + 4 * n * lw;  // 256-byte aligned: lw is a multiple of 64
+  if (g_sip_path.load() != 1 && bs::sip_tile_supported(n, hb_s_L, hb_s_U))
+    return launched(bs::launch_sip_tile(n, batch, ld, A, F, fld, own,
+                                        static_cast<const double*>(rhs),
+                                        static_cast<double*>(x), tol, max_iter, hb_s_L,
+                                        hb_s_U, iters, relres, info, rest, st));
   return launched(bs::launch_sip_lane(n, batch, ld, A, F, fld,
                                       static_cast<const double*>(rhs),
                                       static_cast<double*>(x), tol, max_iter,
-                                      hb_s_L, hb_s_U, iters, relres, info, ws, st));
+                                      hb_s_L, hb_s_U, iters, relres, info, rest, st));
 }
 
 }  // extern "C"

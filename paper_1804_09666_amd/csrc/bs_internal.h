@@ -86,4 +86,16 @@ hipError_t launch_sip_lane(int64_t n, int64_t batch, int64_t ld, Diags A,
                            int32_t sU, int32_t* iters, double* relres,
                            int32_t* info, double* v_ws, hipStream_t st);
 
+// ---- SIP with HB steps, rows split over lanes (sip_tile.hip) -------------
+// Both s_L, s_U >= 0, HB not exact (2^s <= n) and halos that leave a tile
+// core of at least 64 rows.
+bool sip_tile_supported(int64_t n, int32_t sL, int32_t sU);
+size_t sip_tile_workspace_bytes(int64_t n, int64_t batch, int64_t ld);
+// own_factors: the factors were just computed by launch_factor_lane, whose
+// info marks systems that cannot step.
+hipError_t launch_sip_tile(int64_t n, int64_t batch, int64_t ld, Diags A, const double* factors,
+                           int64_t fld, bool own_factors, const double* y, double* x, double tol,
+                           int32_t max_iter, int32_t sL, int32_t sU, int32_t* iters,
+                           double* relres, int32_t* info, void* ws, hipStream_t st);
+
 }  // namespace bs

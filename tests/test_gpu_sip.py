@@ -11,6 +11,17 @@ from gpu_util import diags_of, host, rel_err, say, to_device
 
 pytestmark = pytest.mark.gpu
 
+SIP_PATHS = {"lane": 1, "tile": 2}
+
+
+@pytest.fixture(params=["lane", "tile"])
+def sip_path(request):
+    """Run the test with one lane per system and with the rows of a system
+    split over lanes (the latter only where both factors take HB steps)."""
+    bs.set_option(bs.OPT_SIP_PATH, SIP_PATHS[request.param])
+    yield request.param
+    bs.set_option(bs.OPT_SIP_PATH, 0)
+
 
 def run_both(ws, batch, tol, max_iter, sL, sU, x0=None, ld=None):
     t = to_device(ws, batch, ld=ld)
@@ -27,9 +38,9 @@ def run_both(ws, batch, tol, max_iter, sL, sU, x0=None, ld=None):
 
 
 @pytest.mark.parametrize("sL,sU", [(-1, -1), (-1, 2), (1, 1), (2, 3), (3, 3), (5, 6), (11, 11)])
-def test_config0_sip_parity(sL, sU):
+def test_config0_sip_parity(sL, sU, sip_path):
     ws = wl.config0(5)
-    say(f"config0 SIP sL={sL} sU={sU}")
+    say(f"config0 SIP sL={sL} sU={sU} path={sip_path}")
     x, it, rr, info, xo, ito, rro, sto = run_both(ws, 64, 1e-12, 200, sL, sU)
     say(f"  iters gpu {it.min()}..{it.max()} oracle {ito.min()}..{ito.max()}")
     assert (sto == 0).all() and (info == 0).all()
@@ -40,7 +51,7 @@ def test_config0_sip_parity(sL, sU):
     assert rel_err(x, xo).max() <= 1e-10
 
 
-def test_pde_lines_warm_start_and_status_codes():
+def test_pde_lines_warm_start_and_status_codes(sip_path):
     sw = wl.sweep_lines(wl.smooth_lines(64, 512, seed=21), r=4.0, order=2)
     say("PDE lines SIP sL=3 sU=4 zero and warm start")
     x, it, rr, info, xo, ito, rro, sto = run_both(sw, 64, 1e-10, 300, 3, 4)
@@ -54,7 +65,7 @@ def test_pde_lines_warm_start_and_status_codes():
     assert (info3 == -1).all() and (sto3 == -1).all() and (it3 == 2).all()
 
 
-def test_divergence_and_zero_rhs():
+def test_divergence_and_zero_rhs(sip_path):
     sw = wl.sweep_lines(wl.smooth_lines(8, 512, seed=9), r=2047.0, order=2)
     x, it, rr, info, xo, ito, rro, sto = run_both(sw, 8, 1e-10, 200, 1, 1)
     say(f"divergence: gpu info {info.tolist()} oracle {sto.tolist()}")
@@ -65,7 +76,7 @@ def test_divergence_and_zero_rhs():
     assert info[1] == 0 and it[1] == 0 and (x[1] == 0).all()
 
 
-def test_precomputed_factors_and_ragged_batch():
+def test_precomputed_factors_and_ragged_batch(sip_path):
     ws = wl.dominant_batch(67, 700, seed=12)
     t = to_device(ws, 67, ld=128)
     f, finfo = bs.factor(diags_of(t), batch=67)
@@ -76,3 +87,50 @@ def test_precomputed_factors_and_ragged_batch():
     torch.cuda.synchronize()
     assert (i1.cpu() == 0).all() and torch.equal(it1, it2)
     assert torch.equal(x1[:, :67], x2[:, :67])
+
+
+@pytest.mark.parametrize("n,batch,ld,sL,sU", [(40, 5, 64, 2, 2), (209, 16, 16, 3, 4),
+                                              (5000, 33, 64, 3, 4), (3001, 17, 20, 1, 5),
+                                              (1500, 3, 3, 4, 1)])
+def test_split_rows_shapes(n, batch, ld, sL, sU):
+    """Rows split over lanes: one tile, several tiles with a ragged last one,
+    padded leading dimension, uneven halos."""
+    ws = wl.dominant_batch(batch, n, seed=5000 + n)
+    say(f"tile SIP n={n} batch={batch} ld={ld} sL={sL} sU={sU}")
+    x, it, rr, info, xo, ito, rro, sto = run_both(ws, batch, 1e-12, 300, sL, sU, ld=ld)
+    say(f"  iters gpu {it.min()}..{it.max()} oracle {ito.min()}..{ito.max()}")
+    assert (sto == 0).all() and (info == 0).all()
+    assert np.abs(it - ito).max() <= 1 and (rr < 1e-12).all()
+    assert rel_err(x, xo).max() <= 1e-10
+
+
+def test_split_rows_full_sweep_batch():
+    """The 2048 x 2048 second-order sweep batch (r = 4), HB (3, 4), to 1e-10:
+    iteration counts of every system against the oracle's."""
+    pd, _, _ = wl.config1()
+    say("tile SIP config1 n=2048 batch=2048 sL=3 sU=4")
+    x, it, rr, info, xo, ito, rro, sto = run_both(pd, 2048, 1e-10, 100, 3, 4)
+    say(f"  iters gpu {np.bincount(it).tolist()} oracle {np.bincount(ito).tolist()}")
+    assert (sto == 0).all() and (info == 0).all()
+    assert np.abs(it - ito).max() <= 1 and (rr < 1e-10).all()
+    xd, _ = oracle.npdm_batch(pd["e"], pd["c"], pd["d"], pd["a"], pd["b"], pd["y"])
+    assert rel_err(x, xd).max() <= 1e-7
+
+
+def test_split_rows_bad_pivot_and_max_iter_zero():
+    ws = wl.dominant_batch(4, 600, seed=13)
+    ws["d"][2, 0] = 0.0     # ILU(0) pivot u0_0 = 0: no step, x untouched
+    t = to_device(ws, 4)
+    x0 = torch.full_like(t["y"], 3.0)
+    x, it, rr, info = bs.sip(diags_of(t), t["y"], x0, tol=1e-12, max_iter=50, s_L=2, s_U=2,
+                             batch=4)
+    torch.cuda.synchronize()
+    i = info.cpu().numpy()
+    assert i[2] == 1 and (np.delete(i, 2) == 0).all()
+    assert (x[:, 2] == 3.0).all()
+    # max_iter = 0: the test alone; relres of x0 reported
+    x, it, rr, info = bs.sip(diags_of(t), t["y"], tol=1e-12, max_iter=0, s_L=2, s_U=2, batch=4)
+    torch.cuda.synchronize()
+    i = info.cpu().numpy()
+    assert (it.cpu().numpy() == 0).all() and i[2] == 1 and (np.delete(i, 2) == -1).all()
+    assert (rr.cpu().numpy()[[0, 1, 3]] == 1.0).all()   # x0 = 0: ||b - A 0|| = ||b||
