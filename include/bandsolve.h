@@ -25,8 +25,10 @@
  *     e_i x_{i-2} + c_i x_{i-1} + d_i x_i + a_i x_{i+1} + b_i x_{i+2} = y_i
  * with diags[0]=e, [1]=c, [2]=d, [3]=a, [4]=b.  Kind 3 reads only c, d, a
  * (diags[0] and diags[4] may be NULL).  The corner slots e_0, e_1, c_0,
- * a_{n-1}, b_{n-2}, b_{n-1} are never read (they may hold anything, NaN
- * included).  Inputs are never written.  x may alias rhs.
+ * a_{n-1}, b_{n-2}, b_{n-1} lie outside the matrix: their values are never
+ * used (they may hold anything, NaN included; the memory must exist, as
+ * every array spans n*ld elements).  Inputs are never written.  x may alias
+ * rhs.
  *
  * PRECISION.  dtype BS_F64: every array is double.  dtype BS_F32 (fused
  * band_solve only, n >= 8): diags, rhs and x are stored as float, and every
@@ -199,7 +201,13 @@ int32_t band_solve_refine(int32_t kind, int64_t n, int64_t batch, int64_t ld,
  * outer_b[k*ld + s] (coefficient b of that row).  All other e_i, b_i are 0.
  * Products with absent entries are skipped; on finite data the result equals
  * NPDM on the full diagonals.  kmax may be 0 (then the three list pointers
- * may be NULL).  dtype must be BS_F64. */
+ * may be NULL).  dtype must be BS_F64.
+ * Kernels: as band_solve -- by default the rows of a system are split over
+ * lanes (n <= M*PW*TMAX of the first two PD variants; the diagonals e, b are
+ * never read as arrays, so a row costs c, d, a, rhs and x only), the
+ * workspace then holds the meeting counters (zero before first use, left
+ * zero); otherwise one lane walks each system.  With an invalid list (info
+ * -3) x of that system is unspecified. */
 int32_t band_solve_mnpdm(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
                          const void* const cda[3], int32_t kmax,
                          const int32_t* outer_row, const void* outer_e,

@@ -252,7 +252,8 @@ def solve_mnpdm(cda, outer_row, outer_e, outer_b, rhs, x=None, *, batch=None,
                               _ptr(outer_e) if kmax else None,
                               _ptr(outer_b) if kmax else None, _ptr(rhs), _ptr(x),
                               _ptr(info), _ptr(workspace),
-                              workspace.numel() * workspace.element_size(), _stream(stream))
+                              0 if workspace is None else workspace.numel() * workspace.element_size(),
+                              _stream(stream))
     _raise(st, "band_solve_mnpdm")
     return x, info
 

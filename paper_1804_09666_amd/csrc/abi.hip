@@ -128,6 +128,13 @@ namespace {
 
 int32_t launched(hipError_t e) { return e == hipSuccess ? BS_OK : BS_ELAUNCH; }
 
+// Split-row MNPDM variant for (n, ld) under the current options, or -1 for
+// one lane per system.
+int mnpdm_part_idx(int64_t n, int64_t ld) {
+  if (g_direct_path.load() == 1) return -1;
+  return bs::part_mnpdm_pick(part_idx(5), n, ld);
+}
+
 bool have_device() {
   int count = 0;
   return hipGetDeviceCount(&count) == hipSuccess && count > 0;
@@ -205,8 +212,10 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
       return bs::direct_ws_bytes(kind, dtype, n, batch, ld);
     case BS_OP_SOLVE_FACTORED:
       return kind_ok(kind) ? 0 : bad;
-    case BS_OP_MNPDM:
-      return (size_t)(2 * plane) * 8;
+    case BS_OP_MNPDM: {
+      const int idx = mnpdm_part_idx(n, ld);
+      return idx >= 0 ? bs::part_workspace_bytes(5, idx, n, batch) : (size_t)(2 * plane) * 8;
+    }
     case BS_OP_SIP: {
       // ILU(0) factors (4 planes, batch-interleaved with pitch ws_ld), then
       // either one plane for the forward pass (one lane per system) or the
@@ -303,8 +312,19 @@ int32_t band_solve_mnpdm(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
     return BS_EINVAL;
   const size_t need = bs_workspace_bytes(BS_OP_MNPDM, 5, dtype, n, batch, ld);
   if (ws_bytes < need) return BS_EWORKSPACE;
-  if (!array_ok(workspace, dtype)) return BS_EINVAL;
+  if (need > 0 && !array_ok(workspace, dtype)) return BS_EINVAL;
   if (!have_device()) return BS_ENODEV;
+  const int idx = mnpdm_part_idx(n, ld);
+  if (idx >= 0) {
+    const double* cd[3] = {static_cast<const double*>(cda[0]),
+                           static_cast<const double*>(cda[1]),
+                           static_cast<const double*>(cda[2])};
+    return launched(bs::launch_part_mnpdm(
+        idx, n, batch, ld, cd, kmax, outer_row, static_cast<const double*>(outer_e),
+        static_cast<const double*>(outer_b), static_cast<const double*>(rhs),
+        static_cast<double*>(x), info, static_cast<double*>(workspace),
+        static_cast<hipStream_t>(stream)));
+  }
   bs::Diags A;
   A.e = nullptr;
   A.c = static_cast<const double*>(cda[0]);

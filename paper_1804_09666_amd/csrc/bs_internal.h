@@ -55,6 +55,14 @@ size_t part_workspace_bytes(int kind, int idx, int64_t n, int64_t batch);
 hipError_t launch_part(int kind, int idx, int dtype, int64_t n, int64_t batch, int64_t ld,
                        const void* const dg[5], const void* y, void* x, int32_t* info,
                        double* ws, hipStream_t st, const int32_t* skip = nullptr);
+// MNPDM (outer diagonals as a per-system list) on the split kernels: the
+// variant to use for (n, ld) (-1 if none) and its launch; the workspace is
+// part_workspace_bytes(5, idx, n, batch).
+int part_mnpdm_pick(int idx, int64_t n, int64_t ld);
+hipError_t launch_part_mnpdm(int idx, int64_t n, int64_t batch, int64_t ld,
+                             const double* const cda[3], int32_t kmax, const int32_t* orow,
+                             const double* oe, const double* ob, const double* y, double* x,
+                             int32_t* info, double* ws, hipStream_t st);
 // Any length: three launches (tile maps, per-system reduction, finish).
 bool long_supported(int64_t n, int64_t ld, int dtype);
 size_t long_workspace_bytes(int kind, int64_t n, int64_t batch);

@@ -11,6 +11,7 @@
 // sequential recurrences, with IEEE division and without contraction into
 // FMAs, so their results are the sequential recurrence's to the last bit.
 #include "bs_internal.h"
+#include "lane_stream.h"
 
 #pragma clang fp contract(off)
 
@@ -20,6 +21,8 @@ namespace {
 constexpr int kLaneBlock = 64;  // one wave per block: spreads few systems over many CUs
 
 __device__ inline bool bad_pivot(double m) { return !(m != 0.0) || !isfinite(m); }
+
+constexpr int kPF = 8;  // rows in flight per lane (x <= 8 memory operations < 64)
 
 // NPDM: gamma_i = c_i - alpha_{i-2} e_i;  mu_i = (d_i - beta_{i-2} e_i) -
 // alpha_{i-1} gamma_i;  alpha_i = (a_i - beta_{i-1} gamma_i) / mu_i;
@@ -36,55 +39,72 @@ __global__ __launch_bounds__(kLaneBlock) void npdm_lane_kernel(
   T* al = ws;
   T* be = ws + n * lw;
   T am1 = 0, am2 = 0, bm1 = 0, bm2 = 0, zm1 = 0, zm2 = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t o = i * ld + s;
-    T gamma = 0, mu;
-    if (i == 0) {
-      mu = D[o];
-    } else if (i == 1) {
-      gamma = C[o];
-      mu = D[o] - am1 * gamma;
-    } else {
-      const T ei = E[o];
-      gamma = C[o] - am2 * ei;
-      mu = (D[o] - bm2 * ei) - am1 * gamma;
-    }
-    if (bad_pivot(mu)) {
-      info[s] = (int32_t)(i + 1);
-      return;
-    }
-    T ali = 0, bei = 0, zi;
-    if (i <= n - 2) ali = (i == 0) ? A[o] / mu : (A[o] - bm1 * gamma) / mu;
-    if (i <= n - 3) bei = B[o] / mu;
-    if (i == 0)
-      zi = Y[o] / mu;
-    else if (i == 1)
-      zi = (Y[o] - zm1 * gamma) / mu;
-    else
-      zi = ((Y[o] - zm2 * E[o]) - zm1 * gamma) / mu;
-    al[i * lw + s] = ali;
-    be[i * lw + s] = bei;
-    X[o] = zi;
-    am2 = am1; am1 = ali;
-    bm2 = bm1; bm1 = bei;
-    zm2 = zm1; zm1 = zi;
+  int64_t bad = -1;  // first bad pivot (the sweeps run on; x is then unspecified)
+  {
+    T re[kPF], rc[kPF], rd[kPF], ra[kPF], rb[kPF], ry[kPF];
+    auto fetch = [&](int q, int64_t i) {
+      const int64_t o = i * ld + s;
+      re[q] = E[o];
+      rc[q] = C[o];
+      rd[q] = D[o];
+      ra[q] = A[o];
+      rb[q] = B[o];
+      ry[q] = Y[o];
+    };
+    auto use = [&](int q, int64_t i) {
+      const int64_t o = i * ld + s;
+      T gamma = 0, mu;
+      if (i == 0) {
+        mu = rd[q];
+      } else if (i == 1) {
+        gamma = rc[q];
+        mu = rd[q] - am1 * gamma;
+      } else {
+        gamma = rc[q] - am2 * re[q];
+        mu = (rd[q] - bm2 * re[q]) - am1 * gamma;
+      }
+      if (bad < 0 && bad_pivot(mu)) bad = i;
+      T ali = 0, bei = 0, zi;
+      if (i <= n - 2) ali = (i == 0) ? ra[q] / mu : (ra[q] - bm1 * gamma) / mu;
+      if (i <= n - 3) bei = rb[q] / mu;
+      if (i == 0)
+        zi = ry[q] / mu;
+      else if (i == 1)
+        zi = (ry[q] - zm1 * gamma) / mu;
+      else
+        zi = ((ry[q] - zm2 * re[q]) - zm1 * gamma) / mu;
+      al[i * lw + s] = ali;
+      be[i * lw + s] = bei;
+      X[o] = zi;
+      am2 = am1; am1 = ali;
+      bm2 = bm1; bm1 = bei;
+      zm2 = zm1; zm1 = zi;
+    };
+    stream_rows<kPF, false>(n, fetch, use);
   }
-  T xp1 = 0, xp2 = 0;  // x_{i+1}, x_{i+2}
-  for (int64_t i = n - 1; i >= 0; --i) {
-    const int64_t o = i * ld + s;
-    const T zi = X[o];
-    T xi;
-    if (i == n - 1)
-      xi = zi;
-    else if (i == n - 2)
-      xi = zi - al[i * lw + s] * xp1;
-    else
-      xi = (zi - al[i * lw + s] * xp1) - be[i * lw + s] * xp2;
-    X[o] = xi;
-    xp2 = xp1;
-    xp1 = xi;
+  {
+    T rz[kPF], ral[kPF], rbe[kPF];
+    T xp1 = 0, xp2 = 0;  // x_{i+1}, x_{i+2}
+    auto fetch = [&](int q, int64_t i) {
+      rz[q] = X[i * ld + s];
+      ral[q] = al[i * lw + s];
+      rbe[q] = be[i * lw + s];
+    };
+    auto use = [&](int q, int64_t i) {
+      T xi;
+      if (i == n - 1)
+        xi = rz[q];
+      else if (i == n - 2)
+        xi = rz[q] - ral[q] * xp1;
+      else
+        xi = (rz[q] - ral[q] * xp1) - rbe[q] * xp2;
+      X[i * ld + s] = xi;
+      xp2 = xp1;
+      xp1 = xi;
+    };
+    stream_rows<kPF, true>(n, fetch, use);
   }
-  info[s] = 0;
+  info[s] = bad < 0 ? 0 : (int32_t)(bad + 1);
 }
 
 // NTDM (Thomas): mu_i = d_i - alpha_{i-1} c_i;  alpha_i = a_i / mu_i;
@@ -98,36 +118,50 @@ __global__ __launch_bounds__(kLaneBlock) void ntdm_lane_kernel(
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
   if (s >= batch) return;
   T am1 = 0, zm1 = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t o = i * ld + s;
-    T mu, ci = 0;
-    if (i == 0) {
-      mu = D[o];
-    } else {
-      ci = C[o];
-      mu = D[o] - am1 * ci;
-    }
-    if (bad_pivot(mu)) {
-      info[s] = (int32_t)(i + 1);
-      return;
-    }
-    T ali = 0;
-    if (i <= n - 2) ali = A[o] / mu;
-    const T zi = (i == 0) ? Y[o] / mu : (Y[o] - zm1 * ci) / mu;
-    ws[i * lw + s] = ali;
-    X[o] = zi;
-    am1 = ali;
-    zm1 = zi;
+  int64_t bad = -1;
+  {
+    T rc[kPF], rd[kPF], ra[kPF], ry[kPF];
+    auto fetch = [&](int q, int64_t i) {
+      const int64_t o = i * ld + s;
+      rc[q] = C[o];
+      rd[q] = D[o];
+      ra[q] = A[o];
+      ry[q] = Y[o];
+    };
+    auto use = [&](int q, int64_t i) {
+      T mu, ci = 0;
+      if (i == 0) {
+        mu = rd[q];
+      } else {
+        ci = rc[q];
+        mu = rd[q] - am1 * ci;
+      }
+      if (bad < 0 && bad_pivot(mu)) bad = i;
+      T ali = 0;
+      if (i <= n - 2) ali = ra[q] / mu;
+      const T zi = (i == 0) ? ry[q] / mu : (ry[q] - zm1 * ci) / mu;
+      ws[i * lw + s] = ali;
+      X[i * ld + s] = zi;
+      am1 = ali;
+      zm1 = zi;
+    };
+    stream_rows<kPF, false>(n, fetch, use);
   }
-  T xp1 = 0;
-  for (int64_t i = n - 1; i >= 0; --i) {
-    const int64_t o = i * ld + s;
-    const T zi = X[o];
-    const T xi = (i == n - 1) ? zi : zi - ws[i * lw + s] * xp1;
-    X[o] = xi;
-    xp1 = xi;
+  {
+    T rz[kPF], ral[kPF];
+    T xp1 = 0;
+    auto fetch = [&](int q, int64_t i) {
+      rz[q] = X[i * ld + s];
+      ral[q] = ws[i * lw + s];
+    };
+    auto use = [&](int q, int64_t i) {
+      const T xi = (i == n - 1) ? rz[q] : rz[q] - ral[q] * xp1;
+      X[i * ld + s] = xi;
+      xp1 = xi;
+    };
+    stream_rows<kPF, true>(n, fetch, use);
   }
-  info[s] = 0;
+  info[s] = bad < 0 ? 0 : (int32_t)(bad + 1);
 }
 
 // MNPDM: NPDM with the products of absent outer entries skipped.  The list of
@@ -244,25 +278,32 @@ __global__ __launch_bounds__(kLaneBlock) void factor_lane_kernel(
   double* L1 = (KIND == 5) ? F + plane : F;
   double* U0 = (KIND == 5) ? F + 2 * plane : F + plane;
   double* U1 = (KIND == 5) ? F + 3 * plane : nullptr;
-  double u0m1 = 0, u0m2 = 0, u1m1 = 0, u1m2 = 0, u2m1 = 0, u2m2 = 0;
-  for (int64_t i = 0; i < n; ++i) {
+  double re[kPF], rc[kPF], rd[kPF], ra[kPF], rb[kPF];
+  auto fetch = [&](int q, int64_t i) {
     const int64_t o = i * ld + s;
+    if (KIND == 5) re[q] = E[o];
+    rc[q] = C[o];
+    rd[q] = D[o];
+    ra[q] = A[o];
+    if (KIND == 5) rb[q] = B[o];
+  };
+  double u0m1 = 0, u0m2 = 0, u1m1 = 0, u1m2 = 0, u2m1 = 0, u2m2 = 0;
+  int64_t bad = -1;  // first bad pivot (the sweep runs on; later factors unspecified)
+  auto use = [&](int q, int64_t i) {
+    // corner slots (e_0, e_1, c_0, a_{n-1}, b_{n-2}, b_{n-1}) are never used
     double l2 = 0.0, l1 = 0.0, u0, u1 = 0.0, u2 = 0.0;
-    if (KIND == 5 && i >= 2) l2 = E[o] / u0m2;
-    if (i == 1) l1 = C[o] / u0m1;
-    if (i >= 2) l1 = (KIND == 5) ? (C[o] - l2 * u1m2) / u0m1 : C[o] / u0m1;
+    if (KIND == 5 && i >= 2) l2 = re[q] / u0m2;
+    if (i == 1) l1 = rc[q] / u0m1;
+    if (i >= 2) l1 = (KIND == 5) ? (rc[q] - l2 * u1m2) / u0m1 : rc[q] / u0m1;
     if (i == 0)
-      u0 = D[o];
+      u0 = rd[q];
     else if (i == 1 || KIND == 3)
-      u0 = D[o] - l1 * u1m1;
+      u0 = rd[q] - l1 * u1m1;
     else
-      u0 = (D[o] - l2 * u2m2) - l1 * u1m1;
-    if (bad_pivot(u0)) {
-      info[s] = (int32_t)(i + 1);
-      return;
-    }
-    if (i <= n - 2) u1 = (i == 0 || KIND == 3) ? A[o] : A[o] - l1 * u2m1;
-    if (KIND == 5 && i <= n - 3) u2 = B[o];
+      u0 = (rd[q] - l2 * u2m2) - l1 * u1m1;
+    if (bad < 0 && bad_pivot(u0)) bad = i;
+    if (i <= n - 2) u1 = (i == 0 || KIND == 3) ? ra[q] : ra[q] - l1 * u2m1;
+    if (KIND == 5 && i <= n - 3) u2 = rb[q];
     const int64_t fo = i * fld + s;
     if (KIND == 5) {
       L2[fo] = l2;
@@ -273,8 +314,9 @@ __global__ __launch_bounds__(kLaneBlock) void factor_lane_kernel(
     u0m2 = u0m1; u0m1 = u0;
     u1m2 = u1m1; u1m1 = u1;
     u2m2 = u2m1; u2m1 = u2;
-  }
-  info[s] = 0;
+  };
+  stream_rows<kPF, false>(n, fetch, use);
+  info[s] = bad < 0 ? 0 : (int32_t)(bad + 1);
 }
 
 // Substitution with the band factors: z_i = (y_i - l1_i z_{i-1}) - l2_i z_{i-2}
@@ -292,26 +334,45 @@ __global__ __launch_bounds__(kLaneBlock) void subst_lane_kernel(
   const double* L1 = (KIND == 5) ? F + plane : F;
   const double* U0 = (KIND == 5) ? F + 2 * plane : F + plane;
   const double* U1 = (KIND == 5) ? F + 3 * plane : Aa;  // TD: u1 = a
-  double zm1 = 0, zm2 = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    const int64_t o = i * ld + s;
-    double t = Y[o];
-    if (i >= 1) t = t - L1[o] * zm1;
-    if (KIND == 5 && i >= 2) t = t - L2[o] * zm2;
-    X[o] = t;
-    zm2 = zm1;
-    zm1 = t;
+  {
+    double ry[kPF], rl1[kPF], rl2[kPF];
+    double zm1 = 0, zm2 = 0;
+    auto fetch = [&](int q, int64_t i) {
+      const int64_t o = i * ld + s;
+      ry[q] = Y[o];
+      rl1[q] = L1[o];
+      if (KIND == 5) rl2[q] = L2[o];
+    };
+    auto use = [&](int q, int64_t i) {
+      double t = ry[q];
+      if (i >= 1) t = t - rl1[q] * zm1;
+      if (KIND == 5 && i >= 2) t = t - rl2[q] * zm2;
+      X[i * ld + s] = t;
+      zm2 = zm1;
+      zm1 = t;
+    };
+    stream_rows<kPF, false>(n, fetch, use);
   }
-  double xp1 = 0, xp2 = 0;
-  for (int64_t i = n - 1; i >= 0; --i) {
-    const int64_t o = i * ld + s;
-    double t = X[o];
-    if (i + 1 < n) t = t - U1[o] * xp1;
-    if (KIND == 5 && i + 2 < n) t = t - B[o] * xp2;
-    const double xi = t / U0[o];
-    X[o] = xi;
-    xp2 = xp1;
-    xp1 = xi;
+  {
+    double rz[kPF], ru1[kPF], ru2[kPF], ru0[kPF];
+    double xp1 = 0, xp2 = 0;
+    auto fetch = [&](int q, int64_t i) {
+      const int64_t o = i * ld + s;
+      rz[q] = X[o];
+      ru1[q] = U1[o];
+      if (KIND == 5) ru2[q] = B[o];
+      ru0[q] = U0[o];
+    };
+    auto use = [&](int q, int64_t i) {
+      double t = rz[q];
+      if (i + 1 < n) t = t - ru1[q] * xp1;
+      if (KIND == 5 && i + 2 < n) t = t - ru2[q] * xp2;
+      const double xi = t / ru0[q];
+      X[i * ld + s] = xi;
+      xp2 = xp1;
+      xp1 = xi;
+    };
+    stream_rows<kPF, true>(n, fetch, use);
   }
   info[s] = 0;
 }

@@ -391,6 +391,16 @@ __device__ inline double ld_coherent(const double* p) {
 constexpr int kWaitVmem = 0x0F70;  // s_waitcnt vmcnt(0): this wave's memory ops done
 
 constexpr int kBadNone = INT_MAX;
+constexpr int kBadList = -3;
+
+// MNPDM's outer diagonals as a list per system: entry k of system s is row
+// row[k*ld + s] (-1 = unused) with e = e[k*ld + s], b = b[k*ld + s].
+struct Outer {
+  int32_t kmax;
+  const int32_t* row;
+  const double* e;
+  const double* b;
+};
 constexpr int kTimeout = -4;
 constexpr uint64_t kWaitTicks = 100000000;  // 1 s of the 100 MHz real-time counter
 
@@ -398,7 +408,7 @@ constexpr uint64_t kWaitTicks = 100000000;  // 1 s of the 100 MHz real-time coun
 // identity rows past n, zero couplings outside the matrix.  Byte offsets fit
 // in 32 bits (checked on the host), so every load is an SGPR base plus one
 // per-row VGPR offset shared by the six arrays.
-template <int KIND, int M, typename TIO>
+template <int KIND, int M, typename TIO, bool OUTER = true>
 __device__ inline void load_chunk(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
                                   int64_t row_base,
                                   const TIO* __restrict__ E, const TIO* __restrict__ C,
@@ -418,7 +428,7 @@ __device__ inline void load_chunk(int64_t n, int64_t ld, int64_t s, bool live, i
       y[r] = in ? ldg(Y, o) : 0.0;
       c[r] = (in && i >= 1) ? ldg(C, o) : 0.0;
       a[r] = (in && i <= n - 2) ? ldg(A, o) : 0.0;
-      if (KIND == 5) {
+      if (KIND == 5 && OUTER) {
         e[r] = (in && i >= 2) ? ldg(E, o) : 0.0;
         b[r] = (in && i <= n - 3) ? ldg(B, o) : 0.0;
       } else {
@@ -517,14 +527,16 @@ __device__ inline void write_chunk(int64_t n, int64_t ld, int64_t s, bool live, 
 // they exchange their tile maps through `xch` and meet at the counter pair
 // cnt[2*grp], cnt[2*grp+1] (arrivals, departures; reset by the last tile to
 // leave, so the counters are zero again after every completed call).
-template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE>
+// SPARSE: the outer diagonals come from an MNPDM list (absent entries are
+// zero, so every product with them is an exact zero).
+template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false>
 __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void part_kernel(
     int64_t n, int64_t batch, int64_t ld, const TIO* __restrict__ E,
     const TIO* __restrict__ C, const TIO* __restrict__ D,
     const TIO* __restrict__ A, const TIO* __restrict__ B,
     const TIO* __restrict__ Y, TIO* __restrict__ X,
     int32_t* __restrict__ info, double* __restrict__ xch,
-    unsigned* __restrict__ cnt, int T, const int32_t* __restrict__ skip) {
+    unsigned* __restrict__ cnt, int T, const int32_t* __restrict__ skip, Outer ol) {
   constexpr int NB = KIND == 5 ? 2 : 1;
   constexpr int RS = kRecSz<NB>;
   constexpr int RT = M * PW;
@@ -560,7 +572,38 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
 
   // ---- 1. load the chunk and eliminate it locally -------------------------
   double c[M], d[M], a[M], y[M], e[M], b[M];
-  load_chunk<KIND, M>(n, ld, s, live, r0, 0, E, C, D, A, B, Y, e, c, d, a, b, y);
+  load_chunk<KIND, M, TIO, !SPARSE>(n, ld, s, live, r0, 0, E, C, D, A, B, Y, e, c, d, a, b, y);
+  bool list_bad = false;
+  if constexpr (SPARSE) {
+    // every lane of the system checks the whole list (strictly ascending
+    // rows in [0, n), then only -1) and picks the entries of its rows
+    int64_t prev = -1;
+    bool ended = false;
+    for (int k = 0; k < ol.kmax; ++k) {
+      const int64_t lo = (int64_t)k * ld + s;
+      const int32_t rr = live ? ol.row[lo] : -1;
+      if (rr < 0) {
+        ended = true;
+        continue;
+      }
+      if (ended || rr >= n || rr <= prev) {
+        list_bad = true;
+        continue;
+      }
+      prev = rr;
+      const int64_t loc = rr - r0;
+      if (loc >= 0 && loc < M) {
+        const double ev = (rr >= 2) ? ol.e[lo] : 0.0;
+        const double bv = (rr <= n - 3) ? ol.b[lo] : 0.0;
+#pragma unroll
+        for (int r = 0; r < M; ++r)
+          if (loc == r) {
+            e[r] = ev;
+            b[r] = bv;
+          }
+      }
+    }
+  }
   double p[M], v[NB][M], w[NB][M];
   int bad;
   eliminate_chunk<KIND, M>(e, c, d, a, b, y, p, v, w, bad);
@@ -655,7 +698,7 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
   write_chunk<NB, M>(n, ld, s, live, r0, 0, p, v, w, xl, xr, X);
   if (j == 0 && tile == 0 && live) {
     const int b0 = s_bad[g];
-    info[s] = s_timeout ? kTimeout : ((b0 == kBadNone) ? 0 : b0);
+    info[s] = list_bad ? kBadList : (s_timeout ? kTimeout : ((b0 == kBadNone) ? 0 : b0));
   }
 }
 
@@ -832,19 +875,19 @@ constexpr Variant kVariants[] = {
 // Shape of the long-system path (both kinds).
 constexpr int kLongM = 32, kLongPW = 16, kLongG = 16;
 
-template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE>
+template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false>
 hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, const void* const* dg,
                       const void* y, void* x, int32_t* info, double* ws, hipStream_t st,
-                      const int32_t* skip) {
+                      const int32_t* skip, Outer ol = Outer{0, nullptr, nullptr, nullptr}) {
   constexpr int RT = M * PW;
   const int T = (int)((n + RT - 1) / RT);
   const int64_t groups = (batch + G - 1) / G;
   unsigned* cnt = (T > 1) ? reinterpret_cast<unsigned*>(ws) : nullptr;
   double* xch = (T > 1) ? ws + (2 * groups + 1) / 2 + 1 : nullptr;
-  hipLaunchKernelGGL((part_kernel<TIO, KIND, M, PW, G, TMAX, WPE>), dim3((unsigned)(groups * T)),
-                     dim3(G * PW), 0, st, n, batch, ld, (const TIO*)dg[0], (const TIO*)dg[1],
-                     (const TIO*)dg[2], (const TIO*)dg[3], (const TIO*)dg[4], (const TIO*)y,
-                     (TIO*)x, info, xch, cnt, T, skip);
+  hipLaunchKernelGGL((part_kernel<TIO, KIND, M, PW, G, TMAX, WPE, SPARSE>),
+                     dim3((unsigned)(groups * T)), dim3(G * PW), 0, st, n, batch, ld,
+                     (const TIO*)dg[0], (const TIO*)dg[1], (const TIO*)dg[2], (const TIO*)dg[3],
+                     (const TIO*)dg[4], (const TIO*)y, (TIO*)x, info, xch, cnt, T, skip, ol);
   return hipGetLastError();
 }
 
@@ -956,6 +999,30 @@ hipError_t launch_part(int kind, int idx, int dtype, int64_t n, int64_t batch, i
     BS_PV(float, 3, 32, 16, 16, 4, 1) BS_PV(float, 3, 32, 16, 16, 8, 1)
   }
 #undef BS_PV
+  return hipErrorInvalidValue;
+}
+
+// MNPDM with the rows split over lanes: the first two PD variants.
+int part_mnpdm_pick(int idx, int64_t n, int64_t ld) {
+  const int k = part_pick(5, idx, n, ld, 0);
+  if (k == 0 || k == 1) return k;
+  for (int q = 0; q < 2; ++q)
+    if (covers(find_variant(5, q), n, ld, 0)) return q;
+  return -1;
+}
+
+hipError_t launch_part_mnpdm(int idx, int64_t n, int64_t batch, int64_t ld,
+                             const double* const cda[3], int32_t kmax, const int32_t* orow,
+                             const double* oe, const double* ob, const double* y, double* x,
+                             int32_t* info, double* ws, hipStream_t st) {
+  const void* dg[5] = {nullptr, cda[0], cda[1], cda[2], nullptr};
+  const Outer ol{kmax, orow, oe, ob};
+  if (idx == 0)
+    return launch_cfg<double, 5, 32, 16, 16, 4, 1, true>(n, batch, ld, dg, y, x, info, ws, st,
+                                                         nullptr, ol);
+  if (idx == 1)
+    return launch_cfg<double, 5, 32, 16, 16, 8, 1, true>(n, batch, ld, dg, y, x, info, ws, st,
+                                                         nullptr, ol);
   return hipErrorInvalidValue;
 }
 

@@ -18,6 +18,7 @@
 // i+1, i+2 (U); the M sweeps therefore run as an M-stage pipeline inside the
 // single streaming pass, with 2M values of state per lane in registers.
 #include "bs_internal.h"
+#include "lane_stream.h"
 
 #pragma clang fp contract(off)
 
@@ -49,7 +50,12 @@ __global__ __launch_bounds__(kSipBlock) void sip_lane_kernel(
 
   // ||b||_inf; a zero right-hand side has the solution x = 0 and needs no step
   double bnorm = 0.0;
-  for (int64_t i = 0; i < n; ++i) bnorm = fmax(bnorm, fabs(Y[i * ld + s]));
+  {
+    double ry[16];
+    stream_rows<16, false>(
+        n, [&](int q, int64_t i) { ry[q] = Y[i * ld + s]; },
+        [&](int q, int64_t) { bnorm = fmax(bnorm, fabs(ry[q])); });
+  }
   if (bnorm == 0.0) {
     for (int64_t i = 0; i < n; ++i) X[i * ld + s] = 0.0;
     iters[s] = 0;
@@ -58,11 +64,18 @@ __global__ __launch_bounds__(kSipBlock) void sip_lane_kernel(
     return;
   }
   // ILU(0) pivots must be usable (a zero u0 would make every step undefined)
-  for (int64_t i = 0; i < n; ++i) {
-    if (bad_pivot(U0[i * fld + s])) {
+  {
+    int64_t bad = -1;
+    double ru[16];
+    stream_rows<16, false>(
+        n, [&](int q, int64_t i) { ru[q] = U0[i * fld + s]; },
+        [&](int q, int64_t i) {
+          if (bad < 0 && bad_pivot(ru[q])) bad = i;
+        });
+    if (bad >= 0) {
       iters[s] = 0;
       relres[s] = NAN;
-      info[s] = (int32_t)(i + 1);
+      info[s] = (int32_t)(bad + 1);
       return;
     }
   }
@@ -82,31 +95,48 @@ __global__ __launch_bounds__(kSipBlock) void sip_lane_kernel(
     double wm1 = 0.0, wm2 = 0.0;  // exact L solve: w_{i-1}, w_{i-2}
     // Algorithm 1 as written: K = LU - A on the fly from factor rows i-1, i-2
     double u0m1 = 0, u0m2 = 0, u1m1 = 0, u1m2 = 0, u2m1 = 0, u2m2 = 0;
-    for (int64_t i = 0; i < n; ++i) {
+    constexpr int PFF = MMAX >= 64 ? 1 : 4;  // 11 loads + 1 store per row; registers at 64 stages
+    double rx2[PFF], re[PFF], rc[PFF], rd[PFF], ra[PFF], rb[PFF], ry[PFF], rl2[PFF], rl1[PFF],
+        ru0[PFF], ru1[PFF];
+    auto fetch = [&](int q, int64_t i) {
       const int64_t o = i * ld + s;
-      const double xp2 = (i + 2 < n) ? X[o + 2 * ld] : 0.0;
-      const double ei = (i >= 2) ? E[o] : 0.0;
-      const double ci = (i >= 1) ? C[o] : 0.0;
-      const double di = D[o];
-      const double ai = (i + 1 < n) ? A[o] : 0.0;
-      const double bi = (i + 2 < n) ? B[o] : 0.0;
+      const int64_t fo = i * fld + s;
+      rx2[q] = X[(i + 2 < n ? i + 2 : i) * ld + s];
+      re[q] = E[o];
+      rc[q] = C[o];
+      rd[q] = D[o];
+      ra[q] = A[o];
+      rb[q] = B[o];
+      ry[q] = Y[o];
+      rl2[q] = L2[fo];
+      rl1[q] = L1[fo];
+      ru0[q] = U0[fo];
+      ru1[q] = U1[fo];
+    };
+    auto use = [&](int q, int64_t i) {
+      // corner slots of A and the factors outside the band are never used
+      const double xp2 = (i + 2 < n) ? rx2[q] : 0.0;
+      const double ei = (i >= 2) ? re[q] : 0.0;
+      const double ci = (i >= 1) ? rc[q] : 0.0;
+      const double di = rd[q];
+      const double ai = (i + 1 < n) ? ra[q] : 0.0;
+      const double bi = (i + 2 < n) ? rb[q] : 0.0;
       double ax = di * x0v;
       if (i >= 2) ax = ax + ei * xm2;
       if (i >= 1) ax = ax + ci * xm1;
       if (i + 1 < n) ax = ax + ai * xp1;
       if (i + 2 < n) ax = ax + bi * xp2;
-      const double yi = Y[o];
+      const double yi = ry[q];
       const double r = yi - ax;
       const double ar = fabs(r);
       if (!isfinite(ar)) nonfinite = true;
       rmax = fmax(rmax, ar);
-      const int64_t fo = i * fld + s;
-      const double l2 = (i >= 2) ? L2[fo] : 0.0;
-      const double l1 = (i >= 1) ? L1[fo] : 0.0;
+      const double l2 = (i >= 2) ? rl2[q] : 0.0;
+      const double l1 = (i >= 1) ? rl1[q] : 0.0;
       double wi;
       if (literal) {
-        const double u0 = U0[fo];
-        const double u1 = (i + 1 < n) ? U1[fo] : 0.0;
+        const double u0 = ru0[q];
+        const double u1 = (i + 1 < n) ? ru1[q] : 0.0;
         // v = K x + b with K = LU - A, then w = L^{-1} v
         double kx = ((u0 + (i >= 1 ? l1 * u1m1 : 0.0) + (i >= 2 ? l2 * u2m2 : 0.0)) - di) * x0v;
         if (i >= 2) kx = kx + (l2 * u0m2 - ei) * xm2;
@@ -145,7 +175,8 @@ __global__ __launch_bounds__(kSipBlock) void sip_lane_kernel(
       xm1 = x0v;
       x0v = xp1;
       xp1 = xp2;
-    }
+    };
+    stream_rows<PFF, false>(n, fetch, use);
     rr = nonfinite ? NAN : rmax / bnorm;
     if (relres0 < 0.0) relres0 = rr;
     if (!isfinite(rr)) { status = -2; break; }
@@ -158,18 +189,27 @@ __global__ __launch_bounds__(kSipBlock) void sip_lane_kernel(
 #pragma unroll
     for (int t = 0; t < MMAX; ++t) pu1[t] = pu2[t] = 0.0;
     double qp1 = 0.0, qp2 = 0.0;  // exact U solve: q_{i+1}, q_{i+2}
-    for (int64_t i = n - 1; i >= 0; --i) {
+    constexpr int PFB = MMAX >= 64 ? 1 : 8;  // 5 loads + 1 store per row
+    double bv[PFB], bu0[PFB], bu1[PFB], bu2[PFB], bx[PFB];
+    auto fetchb = [&](int q, int64_t i) {
       const int64_t o = i * ld + s;
-      const double v = V[i * lw + s];
       const int64_t fo = i * fld + s;
-      const double u0 = U0[fo];
-      const double u1 = (i + 1 < n) ? U1[fo] : 0.0;
-      const double u2 = (i + 2 < n) ? B[o] : 0.0;
-      double q;
+      bv[q] = V[i * lw + s];
+      bu0[q] = U0[fo];
+      bu1[q] = U1[fo];
+      bu2[q] = B[o];
+      bx[q] = X[o];
+    };
+    auto useb = [&](int q, int64_t i) {
+      const double v = bv[q];
+      const double u0 = bu0[q];
+      const double u1 = (i + 1 < n) ? bu1[q] : 0.0;
+      const double u2 = (i + 2 < n) ? bu2[q] : 0.0;
+      double qv;
       if (exactU) {
-        q = ((v - u1 * qp1) - u2 * qp2) / u0;
+        qv = ((v - u1 * qp1) - u2 * qp2) / u0;
         qp2 = qp1;
-        qp1 = q;
+        qp1 = qv;
       } else {
         // stage t: y_t[i] = (v_i - u1_i y_{t-1}[i+1] - u2_i y_{t-1}[i+2]) / u0_i
         const double inv = 1.0 / u0;
@@ -183,13 +223,14 @@ __global__ __launch_bounds__(kSipBlock) void sip_lane_kernel(
         }
         pu2[0] = pu1[0];
         pu1[0] = v * inv;
-        q = pu1[0];
+        qv = pu1[0];
 #pragma unroll
         for (int t = 1; t < MMAX; ++t)
-          if (t == MU - 1) q = pu1[t];
+          if (t == MU - 1) qv = pu1[t];
       }
-      X[o] = literal ? q : X[o] + q;
-    }
+      X[i * ld + s] = literal ? qv : bx[q] + qv;
+    };
+    stream_rows<PFB, true>(n, fetchb, useb);
     ++k;
   }
   iters[s] = k;

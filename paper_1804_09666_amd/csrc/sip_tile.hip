@@ -26,7 +26,9 @@
 // launches return at once.
 #include "bs_internal.h"
 
-#pragma clang fp contract(off)
+// Products and sums may contract into FMAs, and the upper sweeps multiply by
+// 1/u0 (one division per row and step) instead of dividing in every sweep;
+// both change only the rounding of the iterates.
 
 namespace bs {
 namespace {
@@ -163,9 +165,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   }
 
   // ---- z = X_U y: K_U upper sweeps, rows ascending within the lane -------
-  double z[kM];
+  double z[kM], ru[kM];
 #pragma unroll
-  for (int r = 0; r < kM; ++r) z[r] = y[r] / u0[r];
+  for (int r = 0; r < kM; ++r) {
+    ru[r] = 1.0 / u0[r];
+    z[r] = y[r] * ru[r];
+  }
   for (int t = 1; t <= KU; ++t) {
     const int p = t & 1;
     s_lo[p][j][g][0] = z[0];
@@ -180,7 +185,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
       double ty = u0[r] * z[r];
       ty = ty + u1[r] * z_p1;
       ty = ty + b[r] * z_p2;
-      z[r] = z[r] + (y[r] - ty) / u0[r];
+      z[r] = z[r] + (y[r] - ty) * ru[r];
     }
   }
 

@@ -47,7 +47,15 @@ def test_workspace_query(bs):
     assert bs.workspace_bytes(bs.OP_FACTOR, 5, n, batch) == 0
     assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 3, n, batch) == 0
     assert bs.workspace_bytes(bs.OP_SIP, 5, n, batch) == 5 * n * lw * 8
-    assert bs.workspace_bytes(bs.OP_MNPDM, 5, n, batch) == 2 * n * lw * 8
+    # MNPDM: the split PD kernel's exchange area, or alpha and beta planes
+    assert bs.workspace_bytes(bs.OP_MNPDM, 5, n, batch) == \
+        bs.workspace_bytes(bs.OP_SOLVE, 5, n, batch)
+    bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_LANE)
+    try:
+        assert bs.workspace_bytes(bs.OP_MNPDM, 5, n, batch) == 2 * n * lw * 8
+    finally:
+        bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_AUTO)
+    assert bs.workspace_bytes(bs.OP_MNPDM, 5, 40000, batch) == 2 * 40000 * lw * 8
     lib = bs.load()
     bad = ctypes.c_size_t(-1).value
     assert lib.bs_workspace_bytes(bs.OP_SOLVE, 4, 0, n, batch, batch) == bad
@@ -107,6 +115,9 @@ def test_options(bs):
         bs.set_option(bs.OPT_PART_TD_VARIANT, -1)
     with pytest.raises(bs.BandSolveError):
         bs.set_option(99, 1)
+    with pytest.raises(bs.BandSolveError):
+        bs.set_option(bs.OPT_SIP_PATH, 3)
+    assert bs.get_option(bs.OPT_SIP_PATH) == 0
     assert bs.get_option(99) == -1
     for kind in (5, 3):
         vs = bs.part_variants(kind)
@@ -173,7 +184,8 @@ def test_invalid_arguments_rejected_on_host(bs):
                                 big, None) == E
     assert lib.band_solve_mnpdm(0, n, batch, ld, d3, 2, None, None, None, y, x, info, ws,
                                 big, None) == E
-    assert lib.band_solve_mnpdm(0, n, batch, ld, d3, 0, None, None, None, y, x, info, ws,
+    # n beyond the split variants: one lane per system, whose workspace is needed
+    assert lib.band_solve_mnpdm(0, 5000, batch, ld, d3, 0, None, None, None, y, x, info, ws,
                                 0, None) == bs.BS_EWORKSPACE
     # sip_solve
     it, rr = _fake(11), _fake(12)

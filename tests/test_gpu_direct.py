@@ -196,7 +196,7 @@ def test_factor_and_factored_solve():
             assert rel_err(host(x, 70)[s:s + 1], xo[None]).max() <= TOL
 
 
-def test_mnpdm_matches_npdm_and_oracle():
+def test_mnpdm_matches_npdm_and_oracle(path):
     pd, _, _ = wl.config1(N=256, seed=11)
     batch, n = 256, 256
     t = to_device(pd, batch)
@@ -212,6 +212,8 @@ def test_mnpdm_matches_npdm_and_oracle():
     xn, infon = bs.solve(diags_of(t), t["y"], batch=batch)
     torch.cuda.synchronize()
     assert (info.cpu().numpy() == 0).all()
+    # the skipped products are exact zeros: bitwise the NPDM of the same kernel
+    assert torch.equal(x[:, :batch], xn[:, :batch])
     for s in range(0, batch, 17):
         xo, io = oracle.mnpdm(pd["c"][s], pd["d"][s], pd["a"][s], [0, n - 1],
                               [0.0, pd["e"][s][n - 1]], [pd["b"][s][0], 0.0], pd["y"][s])
@@ -224,3 +226,49 @@ def test_mnpdm_matches_npdm_and_oracle():
     torch.cuda.synchronize()
     i2 = info2.cpu().numpy()
     assert i2[5] == -3 and (np.delete(i2, 5) == 0).all()
+
+
+@pytest.mark.parametrize("n,batch,ld,kmax", [(2048, 100, 128, 5), (3001, 33, 40, 9),
+                                             (5000, 7, 8, 4), (300, 64, 64, 0)])
+def test_mnpdm_random_lists(n, batch, ld, kmax, path):
+    """Random sparse outer diagonals (K entries per system, some lists shorter
+    than kmax): MNPDM against the oracle and bitwise against NPDM on the
+    zero-filled diagonals; several tiles, ragged batch, padded ld, and a
+    length beyond the split variants (one lane per system)."""
+    rng = np.random.default_rng(n + batch)
+    ws = wl.dominant_batch(batch, n, kind=5, seed=600 + n)
+    rows = np.full((max(kmax, 1), batch), -1, dtype=np.int32)
+    oe = np.zeros((max(kmax, 1), batch))
+    ob = np.zeros((max(kmax, 1), batch))
+    e = np.zeros((batch, n))
+    b = np.zeros((batch, n))
+    for s in range(batch):
+        k = int(rng.integers(0, kmax + 1)) if kmax else 0
+        r = np.sort(rng.choice(n, size=k, replace=False))
+        rows[:k, s] = r
+        oe[:k, s] = rng.uniform(-1, 1, k)
+        ob[:k, s] = rng.uniform(-1, 1, k)
+        for q in range(k):
+            if r[q] >= 2:
+                e[s, r[q]] = oe[q, s]
+            if r[q] <= n - 3:
+                b[s, r[q]] = ob[q, s]
+    ws["e"], ws["b"] = e, b
+    ws["d"] = np.abs(ws["c"]) + np.abs(ws["a"]) + np.abs(e) + np.abs(b) + 1.5
+    say(f"mnpdm random lists n={n} batch={batch} ld={ld} kmax={kmax} path={path}")
+    t = to_device(ws, batch, ld=ld)
+    row_t = torch.from_numpy(np.ascontiguousarray(
+        np.pad(rows, ((0, 0), (0, ld - batch)), constant_values=-1))).cuda()
+    oe_t = torch.from_numpy(np.ascontiguousarray(np.pad(oe, ((0, 0), (0, ld - batch))))).cuda()
+    ob_t = torch.from_numpy(np.ascontiguousarray(np.pad(ob, ((0, 0), (0, ld - batch))))).cuda()
+    if kmax == 0:
+        row_t = oe_t = ob_t = None
+    x, info = bs.solve_mnpdm([t["c"], t["d"], t["a"]], row_t, oe_t, ob_t, t["y"], batch=batch)
+    xn, infon = bs.solve(diags_of(t), t["y"], batch=batch)
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all() and (infon.cpu().numpy() == 0).all()
+    M, PW, G, TMAX = bs.part_variants(5)[1]
+    if path == "lane" or n <= M * PW * TMAX:   # both calls ran the same kernel family
+        assert torch.equal(x[:, :batch], xn[:, :batch])
+    xr, _ = oracle.npdm_batch(ws["e"], ws["c"], ws["d"], ws["a"], ws["b"], ws["y"])
+    assert rel_err(host(x, batch), xr).max() <= TOL
