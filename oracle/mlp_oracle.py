@@ -5,11 +5,12 @@ benchmark use this module; the product never imports it, and it imports
 nothing of the product.  Plain numpy in float64, written from the definitions:
 
   * patch features: system s, rows [64 j, 64 j + 64) give one input vector of
-    7 x 64 values -- the diagonals e, c, d, a, b, the right-hand side and the
-    previous-step solution of those rows, each standardised with a per-feature
-    mean and scale; slots outside the matrix (e_0, e_1, c_0, a_{n-1},
-    b_{n-2}, b_{n-1}) and rows past n count as raw value 0 before scaling,
-    and rows past n are 0 after it;
+    7 x 64 values -- the diagonals e, c, d, a, b, the residual of the
+    previous-step solution r0 = rhs - A u_prev (the right-hand side enters
+    through it) and u_prev itself, each standardised with a per-feature mean
+    and scale; slots outside the matrix (e_0, e_1, c_0, a_{n-1}, b_{n-2},
+    b_{n-1}) count as raw value 0 before scaling, and rows past n are 0 after
+    it;
   * the network: three hidden layers with ReLU and a linear output,
         h1 = relu(X W1^T + b1), h2 = relu(h1 W2^T + b2),
         h3 = relu(h2 W3^T + b3), Y = h3 W4^T + b4;
@@ -82,6 +83,15 @@ def features(e, c, d, a, b, rhs, uprev, mean, scale):
     raw[1][:, :1] = 0.0
     raw[3][:, n - 1:] = 0.0
     raw[4][:, max(n - 2, 0):] = 0.0
+    # r0_i = rhs_i - (((d_i u_i + e_i u_{i-2}) + c_i u_{i-1}) + a_i u_{i+1}) + b_i u_{i+2},
+    # terms outside the matrix omitted
+    u = raw[6]
+    ax = raw[2] * u
+    ax[:, 2:] = ax[:, 2:] + raw[0][:, 2:] * u[:, :-2]
+    ax[:, 1:] = ax[:, 1:] + raw[1][:, 1:] * u[:, :-1]
+    ax[:, :-1] = ax[:, :-1] + raw[3][:, :-1] * u[:, 1:]
+    ax[:, :-2] = ax[:, :-2] + raw[4][:, :-2] * u[:, 2:]
+    raw[5] = raw[5] - ax
     X = np.zeros((batch * npatch, NFEAT * PATCH))
     for f in range(NFEAT):
         z = (raw[f] - mean[f]) / scale[f]

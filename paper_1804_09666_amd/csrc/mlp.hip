@@ -1,0 +1,610 @@
+// mlp.hip -- the learned SIP start vector (declared in include/warmstart.h):
+// patch features, a 448-512-512-512-64 ReLU network on the matrix cores
+// (forward, backward, Adam), and the start vector x0.
+//
+// One GEMM kernel serves every product, C = A B^T with both operands K-
+// contiguous (the layout of X W^T with W stored [out, in]); the backward pass
+// brings its operands into that layout with a tiled transpose.  A block
+// computes a 128 x 128 tile of C with four waves of 64 x 64 (2 x 2 MFMA
+// 32 x 32 tiles); K advances in steps of 32 staged through LDS.  Lane layout
+// of v_mfma_f32_32x32x16_bf16 / v_mfma_f32_32x32x2_f32 (checked on the
+// device): lane l holds A row (l mod 32) and B column (l mod 32) at
+// k = (l div 32) * KS/2 .. + KS/2 - 1; accumulator v of lane l is
+// C[8 (v div 4) + 4 (l div 32) + (v mod 4)][l mod 32].
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cmath>
+
+#include "bandsolve.h"
+#include "warmstart.h"
+
+namespace wsm {
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBM = 128, kBN = 128, kBK = 32, kThreads = 256;
+
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<bf16> {
+  static constexpr int KS = 16;  // k per instruction
+  typedef bf16x8 Frag;           // 8 values per lane
+  static __device__ inline f32x16 run(Frag a, Frag b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  static constexpr int KS = 2;
+  typedef float Frag;
+  static __device__ inline f32x16 run(Frag a, Frag b, f32x16 c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+};
+
+typedef uint32_t Vec16 __attribute__((ext_vector_type(4)));  // one 16-byte chunk
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void gemm_nt_kernel(int64_t M, int64_t N, int64_t K,
+                                                           const T* __restrict__ A,
+                                                           const T* __restrict__ B,
+                                                           const float* __restrict__ bias,
+                                                           int relu, const T* __restrict__ mask,
+                                                           float* __restrict__ C32,
+                                                           T* __restrict__ CT) {
+  typedef Mfma<T> MF;
+  constexpr int VEC = 16 / sizeof(T);  // elements per 16-byte chunk
+  constexpr int LDR = kBK + VEC;       // LDS row pitch: 16 bytes of padding
+  constexpr int CPR = kBK / VEC;       // chunks per tile row
+  __shared__ __attribute__((aligned(16))) T sA[kBM * LDR];
+  __shared__ __attribute__((aligned(16))) T sB[kBN * LDR];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int64_t m0 = (int64_t)blockIdx.y * kBM, n0 = (int64_t)blockIdx.x * kBN;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+  const int hi = lane >> 5, lo = lane & 31;
+
+  for (int64_t k0 = 0; k0 < K; k0 += kBK) {
+    // ---- global -> LDS (zero outside the matrices; K % VEC == 0) --------
+#pragma unroll
+    for (int q = 0; q < kBM * CPR / kThreads; ++q) {
+      const int c = tid + q * kThreads;
+      const int r = c / CPR, kc = (c % CPR) * VEC;
+      const int64_t k = k0 + kc;
+      Vec16 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
+      if (m0 + r < M && k < K) va = *reinterpret_cast<const Vec16*>(A + (m0 + r) * K + k);
+      if (n0 + r < N && k < K) vb = *reinterpret_cast<const Vec16*>(B + (n0 + r) * K + k);
+      *reinterpret_cast<Vec16*>(sA + r * LDR + kc) = va;
+      *reinterpret_cast<Vec16*>(sB + r * LDR + kc) = vb;
+    }
+    __syncthreads();
+    // ---- matrix cores -----------------------------------------------------
+#pragma unroll
+    for (int kk = 0; kk < kBK; kk += MF::KS) {
+      typename MF::Frag fa[2], fb[2];
+      const int ko = kk + hi * (MF::KS / 2);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        fa[t] = *reinterpret_cast<const typename MF::Frag*>(sA + (wm + 32 * t + lo) * LDR + ko);
+        fb[t] = *reinterpret_cast<const typename MF::Frag*>(sB + (wn + 32 * t + lo) * LDR + ko);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = MF::run(fa[i], fb[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+
+  // ---- epilogue: bias, ReLU, mask; consecutive lanes write consecutive n --
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int64_t col = n0 + wn + 32 * j + lo;
+      if (col >= N) continue;
+      const float bv = bias ? bias[col] : 0.0f;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * hi + (v & 3);
+        if (row >= M) continue;
+        float val = acc[i][j][v] + bv;
+        if (relu) val = val > 0.0f ? val : 0.0f;
+        if (mask && !((float)mask[row * N + col] > 0.0f)) val = 0.0f;
+        if (C32) C32[row * N + col] = val;
+        if (CT) CT[row * N + col] = (T)val;
+      }
+    }
+}
+
+// out[C, R] = in[R, C]^T through a 32 x 32 LDS tile.
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(int64_t R, int64_t C,
+                                                        const T* __restrict__ in,
+                                                        T* __restrict__ out) {
+  __shared__ T tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int k = ty; k < 32; k += 8)
+    if (r0 + k < R && c0 + tx < C) tile[k][tx] = in[(r0 + k) * C + c0 + tx];
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8)
+    if (c0 + k < C && r0 + tx < R) out[(c0 + k) * R + r0 + tx] = tile[tx][k];
+}
+
+// Column sums in a fixed order: partial[g][n] over rows [256 g, 256 g + 256),
+// then out[n] = sum_g partial[g][n].
+template <typename T>
+__global__ __launch_bounds__(256) void colsum_partial_kernel(int64_t M, int64_t N,
+                                                             const T* __restrict__ in,
+                                                             float* __restrict__ partial) {
+  const int64_t n = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int q = threadIdx.x >> 6;  // 4 row groups of 64
+  __shared__ float s[4][64];
+  float acc = 0.0f;
+  if (n < N) {
+    const int64_t rb = (int64_t)blockIdx.y * 256 + q * 64;
+    for (int k = 0; k < 64; ++k) {
+      const int64_t m = rb + k;
+      if (m < M) acc += (float)in[m * N + n];
+    }
+  }
+  s[q][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (q == 0 && n < N)
+    partial[(int64_t)blockIdx.y * N + n] = ((s[0][threadIdx.x] + s[1][threadIdx.x]) +
+                                            s[2][threadIdx.x]) + s[3][threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void colsum_final_kernel(int64_t G, int64_t N,
+                                                           const float* __restrict__ partial,
+                                                           float* __restrict__ out) {
+  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  float acc = 0.0f;
+  for (int64_t g = 0; g < G; ++g) acc += partial[g * N + n];
+  out[n] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void convert_kernel(int64_t count, const float* __restrict__ in,
+                                                      T* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256)
+    out[i] = (T)in[i];
+}
+
+__global__ __launch_bounds__(256) void mse_kernel(int64_t count, const float* __restrict__ Y,
+                                                  const float* __restrict__ T,
+                                                  float* __restrict__ dY,
+                                                  double* __restrict__ partial) {
+  __shared__ double s[256];
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double sq = 0.0;
+  if (i < count) {
+    const float d = Y[i] - T[i];
+    dY[i] = (float)(2.0 * (double)d / (double)count);
+    sq = (double)d * (double)d;
+  }
+  s[threadIdx.x] = sq;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = s[0];
+}
+
+__global__ void mse_final_kernel(int64_t G, int64_t count, const double* __restrict__ partial,
+                                 double* __restrict__ loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double acc = 0.0;
+  for (int64_t g = 0; g < G; ++g) acc += partial[g];
+  *loss = acc / (double)count;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void adam_kernel(int64_t count, float* __restrict__ p,
+                                                   T* __restrict__ pT,
+                                                   const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v,
+                                                   float lr, float b1, float b2, float eps,
+                                                   float c1, float c2) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    if (pT) pT[i] = (T)pi;
+  }
+}
+
+struct Norm {
+  float mean[7], scale[7];
+};
+
+// r0_i = rhs_i - (((d_i u_i + e_i u_{i-2}) + c_i u_{i-1}) + a_i u_{i+1}) + b_i u_{i+2}
+// (terms outside the matrix omitted), every product and sum rounded on its
+// own: the residual of the previous-step solution, the input through which the
+// right-hand side reaches the network.
+__device__ inline double residual(int64_t n, int64_t ld, int64_t i, int64_t o,
+                                  const double* __restrict__ E, const double* __restrict__ C,
+                                  const double* __restrict__ D, const double* __restrict__ A,
+                                  const double* __restrict__ B, double rhs,
+                                  const double* __restrict__ U) {
+#pragma clang fp contract(off)
+  double ax = D[o] * U[o];
+  if (i >= 2) ax = ax + E[o] * U[o - 2 * ld];
+  if (i >= 1) ax = ax + C[o] * U[o - ld];
+  if (i <= n - 2) ax = ax + A[o] * U[o + ld];
+  if (i <= n - 3) ax = ax + B[o] * U[o + 2 * ld];
+  return rhs - ax;
+}
+
+// One block: 64 systems x one patch row (64 rows); every feature plane goes
+// through an LDS tile so that reads (consecutive systems) and writes
+// (consecutive rows of a patch) are both contiguous.
+template <typename T>
+__global__ __launch_bounds__(256) void features_kernel(int64_t n, int64_t batch, int64_t ld,
+                                                       const double* __restrict__ P0,
+                                                       const double* __restrict__ P1,
+                                                       const double* __restrict__ P2,
+                                                       const double* __restrict__ P3,
+                                                       const double* __restrict__ P4,
+                                                       const double* __restrict__ P5,
+                                                       const double* __restrict__ P6, Norm nm,
+                                                       T* __restrict__ X) {
+  __shared__ float tile[64][65];
+  const int64_t s0 = (int64_t)blockIdx.x * 64, j = blockIdx.y;
+  const int64_t npatch = (n + 63) / 64;
+  const double* planes[7] = {P0, P1, P2, P3, P4, P5, P6};
+  for (int f = 0; f < 7; ++f) {
+    const double* P = planes[f];
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+      const int r = idx >> 6, sl = idx & 63;
+      const int64_t i = j * 64 + r, s = s0 + sl;
+      float val = 0.0f;
+      if (i < n && s < batch) {
+        const bool outside = (f == 0 && i < 2) || (f == 1 && i < 1) || (f == 3 && i > n - 2) ||
+                             (f == 4 && i > n - 3);
+        const int64_t o = i * ld + s;
+        double raw = outside ? 0.0 : P[o];
+        if (f == 5) raw = residual(n, ld, i, o, P0, P1, P2, P3, P4, raw, P6);
+        val = (float)((raw - (double)nm.mean[f]) / (double)nm.scale[f]);
+      }
+      tile[r][sl] = val;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+      const int sl = idx >> 6, r = idx & 63;
+      const int64_t s = s0 + sl;
+      if (s < batch) X[(s * npatch + j) * 448 + f * 64 + r] = (T)tile[r][sl];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void apply_kernel(int64_t n, int64_t batch, int64_t ld,
+                                                    const float* __restrict__ Y,
+                                                    const double* __restrict__ U, float mu,
+                                                    float sigma, double* __restrict__ X0) {
+  __shared__ float tile[64][65];
+  const int64_t s0 = (int64_t)blockIdx.x * 64, j = blockIdx.y;
+  const int64_t npatch = (n + 63) / 64;
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+    const int sl = idx >> 6, r = idx & 63;
+    const int64_t s = s0 + sl;
+    tile[r][sl] = s < batch ? Y[(s * npatch + j) * 64 + r] : 0.0f;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+    const int r = idx >> 6, sl = idx & 63;
+    const int64_t i = j * 64 + r, s = s0 + sl;
+    if (i < n && s < batch) {
+      const int64_t o = i * ld + s;
+      X0[o] = U[o] + ((double)mu + (double)sigma * (double)tile[r][sl]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- host ---
+int grid1(int64_t work) {
+  const int64_t b = (work + 255) / 256;
+  return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
+}
+
+bool al16(const void* p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+size_t esz(int32_t dtype) { return dtype == WS_BF16 ? 2 : 4; }
+bool dtype_ok(int32_t dtype) { return dtype == WS_BF16 || dtype == WS_F32; }
+
+template <typename T>
+hipError_t gemm(int64_t M, int64_t N, int64_t K, const void* A, const void* B, const float* bias,
+                int relu, const void* mask, float* C32, void* CT, hipStream_t st) {
+  const dim3 grid((unsigned)((N + kBN - 1) / kBN), (unsigned)((M + kBM - 1) / kBM));
+  hipLaunchKernelGGL(gemm_nt_kernel<T>, grid, dim3(kThreads), 0, st, M, N, K,
+                     static_cast<const T*>(A), static_cast<const T*>(B), bias, relu,
+                     static_cast<const T*>(mask), C32, static_cast<T*>(CT));
+  return hipGetLastError();
+}
+
+template <typename T>
+void transpose(int64_t R, int64_t C, const void* in, void* out, hipStream_t st) {
+  const dim3 grid((unsigned)((C + 31) / 32), (unsigned)((R + 31) / 32));
+  hipLaunchKernelGGL(transpose_kernel<T>, grid, dim3(256), 0, st, R, C,
+                     static_cast<const T*>(in), static_cast<T*>(out));
+}
+
+template <typename T>
+void colsum(int64_t M, int64_t N, const void* in, float* partial, float* out, hipStream_t st) {
+  const int64_t G = (M + 255) / 256;
+  hipLaunchKernelGGL(colsum_partial_kernel<T>, dim3((unsigned)((N + 63) / 64), (unsigned)G),
+                     dim3(256), 0, st, M, N, static_cast<const T*>(in), partial);
+  hipLaunchKernelGGL(colsum_final_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st,
+                     G, N, partial, out);
+}
+
+// Parameter offsets (elements) of layer k: W then b.
+struct Layer {
+  int64_t in, out, w, b;
+};
+constexpr int kLayers = 4;
+void layers(Layer L[kLayers]) {
+  const int64_t dims[5] = {WS_IN, WS_HIDDEN, WS_HIDDEN, WS_HIDDEN, WS_OUT};
+  int64_t o = 0;
+  for (int k = 0; k < kLayers; ++k) {
+    L[k].in = dims[k];
+    L[k].out = dims[k + 1];
+    L[k].w = o;
+    o += L[k].in * L[k].out;
+    L[k].b = o;
+    o += L[k].out;
+  }
+}
+int64_t param_count() {
+  Layer L[kLayers];
+  layers(L);
+  return L[kLayers - 1].b + L[kLayers - 1].out;
+}
+
+// Workspace: h1, h2, h3 [P, 512] (forward); then for training dY in dtype
+// [P, 64], two [512, P] transposes, two [P, 512] gradient buffers, a
+// [512, 512] weight transpose and the column-sum partials.
+struct WsLayout {
+  size_t h[3], dyT, ta, tb, ga, gb, wt, part, fwd_total, train_total;
+};
+WsLayout ws_layout(int32_t dtype, int64_t P) {
+  WsLayout L;
+  const size_t e = esz(dtype);
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  size_t o = 0;
+  for (int k = 0; k < 3; ++k) {
+    L.h[k] = o;
+    o = up(o + (size_t)P * WS_HIDDEN * e);
+  }
+  L.fwd_total = o;
+  L.dyT = o;  o = up(o + (size_t)P * WS_OUT * e);
+  L.ta = o;   o = up(o + (size_t)P * WS_HIDDEN * e);
+  L.tb = o;   o = up(o + (size_t)P * WS_HIDDEN * e);
+  L.ga = o;   o = up(o + (size_t)P * WS_HIDDEN * e);
+  L.gb = o;   o = up(o + (size_t)P * WS_HIDDEN * e);
+  L.wt = o;   o = up(o + (size_t)WS_HIDDEN * WS_HIDDEN * e);
+  L.part = o; o = up(o + (size_t)((P + 255) / 256) * WS_HIDDEN * 4);
+  L.train_total = o;
+  return L;
+}
+
+template <typename T>
+hipError_t forward(int64_t P, const void* X, const float* p32, const void* pT, float* Y,
+                   char* ws, hipStream_t st) {
+  Layer L[kLayers];
+  layers(L);
+  const WsLayout W = ws_layout(sizeof(T) == 2 ? WS_BF16 : WS_F32, P);
+  const T* w = static_cast<const T*>(pT);
+  const void* in = X;
+  for (int k = 0; k < kLayers; ++k) {
+    const bool last = k == kLayers - 1;
+    void* out = last ? nullptr : ws + W.h[k];
+    hipError_t e = gemm<T>(P, L[k].out, L[k].in, in, w + L[k].w, p32 + L[k].b, last ? 0 : 1,
+                           nullptr, last ? Y : nullptr, out, st);
+    if (e != hipSuccess) return e;
+    in = out;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t backward(int64_t P, const void* X, const void* pT, const float* dY, float* g,
+                    char* ws, hipStream_t st) {
+  Layer L[kLayers];
+  layers(L);
+  const WsLayout W = ws_layout(sizeof(T) == 2 ? WS_BF16 : WS_F32, P);
+  const T* w = static_cast<const T*>(pT);
+  float* part = reinterpret_cast<float*>(ws + W.part);
+  // output layer: gradient operand in dtype, bias gradient from FP32 dY
+  T* gcur = reinterpret_cast<T*>(ws + W.dyT);
+  hipLaunchKernelGGL(convert_kernel<T>, dim3(grid1(P * WS_OUT)), dim3(256), 0, st, P * WS_OUT,
+                     dY, gcur);
+  colsum<float>(P, WS_OUT, dY, part, g + L[3].b, st);
+  T* gbuf[2] = {reinterpret_cast<T*>(ws + W.ga), reinterpret_cast<T*>(ws + W.gb)};
+  for (int k = kLayers - 1; k >= 0; --k) {
+    const int64_t out = L[k].out, in = L[k].in;
+    const void* hin = k == 0 ? X : ws + W.h[k - 1];
+    if (k < kLayers - 1) colsum<T>(P, out, gcur, part, g + L[k].b, st);
+    // dW_k [out, in] = g^T [out, P] (h_in^T [in, P])^T
+    transpose<T>(P, out, gcur, ws + W.ta, st);
+    transpose<T>(P, in, hin, ws + W.tb, st);
+    hipError_t e = gemm<T>(out, in, P, ws + W.ta, ws + W.tb, nullptr, 0, nullptr, g + L[k].w,
+                           nullptr, st);
+    if (e != hipSuccess) return e;
+    if (k == 0) break;
+    // g_{k-1} [P, in] = (g [P, out] W_k [out, in]) * [h_{k-1} > 0];  W_k^T is [in, out]
+    transpose<T>(out, in, w + L[k].w, ws + W.wt, st);
+    T* gnext = gbuf[k & 1];
+    e = gemm<T>(P, in, out, gcur, ws + W.wt, nullptr, 0, ws + W.h[k - 1], nullptr, gnext, st);
+    if (e != hipSuccess) return e;
+    gcur = gnext;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+}  // namespace wsm
+
+using namespace wsm;
+
+extern "C" {
+
+int64_t ws_param_count(void) { return param_count(); }
+
+size_t ws_workspace_bytes(int32_t op, int32_t dtype, int64_t P) {
+  if (!dtype_ok(dtype) || P < 1 || P > (int64_t(1) << 31)) return (size_t)-1;
+  const WsLayout L = ws_layout(dtype, P);
+  if (op == WS_OP_FORWARD) return L.fwd_total;
+  if (op == WS_OP_TRAIN) return L.train_total;
+  return (size_t)-1;
+}
+
+int32_t ws_gemm_nt(int32_t dtype, int64_t M, int64_t N, int64_t K, const void* A, const void* B,
+                   const float* bias, int32_t relu, const void* mask, float* C32, void* CT,
+                   void* stream) {
+  if (!dtype_ok(dtype) || M < 1 || N < 1 || K < 1) return BS_EINVAL;
+  if (K % (int64_t)(16 / esz(dtype)) != 0) return BS_EINVAL;
+  if (M > (int64_t(1) << 31) || N > (int64_t(1) << 31) || (M + kBM - 1) / kBM > 65535)
+    return BS_EINVAL;
+  if (!al16(A) || !al16(B) || (C32 == nullptr && CT == nullptr)) return BS_EINVAL;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = dtype == WS_BF16 ? gemm<bf16>(M, N, K, A, B, bias, relu, mask, C32, CT, st)
+                                  : gemm<float>(M, N, K, A, B, bias, relu, mask, C32, CT, st);
+  return e == hipSuccess ? BS_OK : BS_ELAUNCH;
+}
+
+int32_t ws_convert(int32_t dtype, int64_t count, const float* in, void* out, void* stream) {
+  if (!dtype_ok(dtype) || count < 0 || !al16(in) || !al16(out)) return BS_EINVAL;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == WS_BF16)
+    hipLaunchKernelGGL(convert_kernel<bf16>, dim3(grid1(count)), dim3(256), 0, st, count, in,
+                       static_cast<bf16*>(out));
+  else
+    hipLaunchKernelGGL(convert_kernel<float>, dim3(grid1(count)), dim3(256), 0, st, count, in,
+                       static_cast<float*>(out));
+  return hipGetLastError() == hipSuccess ? BS_OK : BS_ELAUNCH;
+}
+
+int32_t ws_forward(int32_t dtype, int64_t P, const void* X, const float* params32,
+                   const void* paramsT, float* Y, void* workspace, size_t ws_bytes,
+                   void* stream) {
+  const size_t need = ws_workspace_bytes(WS_OP_FORWARD, dtype, P);
+  if (need == (size_t)-1 || (P + kBM - 1) / kBM > 65535) return BS_EINVAL;
+  if (!al16(X) || !al16(params32) || !al16(paramsT) || !al16(Y) || !al16(workspace))
+    return BS_EINVAL;
+  if (ws_bytes < need) return BS_EWORKSPACE;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  hipError_t e = dtype == WS_BF16 ? forward<bf16>(P, X, params32, paramsT, Y, ws, st)
+                                  : forward<float>(P, X, params32, paramsT, Y, ws, st);
+  return e == hipSuccess ? BS_OK : BS_ELAUNCH;
+}
+
+int32_t ws_backward(int32_t dtype, int64_t P, const void* X, const float* params32,
+                    const void* paramsT, const float* dY, float* grads, void* workspace,
+                    size_t ws_bytes, void* stream) {
+  const size_t need = ws_workspace_bytes(WS_OP_TRAIN, dtype, P);
+  if (need == (size_t)-1 || P % 8 != 0 || (P + kBM - 1) / kBM > 65535) return BS_EINVAL;
+  if (!al16(X) || !al16(params32) || !al16(paramsT) || !al16(dY) || !al16(grads) ||
+      !al16(workspace))
+    return BS_EINVAL;
+  if (ws_bytes < need) return BS_EWORKSPACE;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  hipError_t e = dtype == WS_BF16 ? backward<bf16>(P, X, paramsT, dY, grads, ws, st)
+                                  : backward<float>(P, X, paramsT, dY, grads, ws, st);
+  return e == hipSuccess ? BS_OK : BS_ELAUNCH;
+}
+
+int32_t ws_mse(int64_t P, const float* Y, const float* T, float* dY, double* loss,
+               double* partial, void* stream) {
+  if (P < 1 || !al16(Y) || !al16(T) || !al16(dY) || loss == nullptr || partial == nullptr)
+    return BS_EINVAL;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t count = P * WS_OUT;
+  const int64_t G = (count + 255) / 256;
+  hipLaunchKernelGGL(mse_kernel, dim3((unsigned)G), dim3(256), 0, st, count, Y, T, dY, partial);
+  hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(64), 0, st, G, count, partial, loss);
+  return hipGetLastError() == hipSuccess ? BS_OK : BS_ELAUNCH;
+}
+
+int32_t ws_adam(int32_t dtype, int64_t count, float* params, void* paramsT, const float* grads,
+                float* m, float* v, float lr, float beta1, float beta2, float eps, int32_t step,
+                void* stream) {
+  if (!dtype_ok(dtype) || count < 1 || step < 1 || !al16(params) || !al16(grads) || !al16(m) ||
+      !al16(v))
+    return BS_EINVAL;
+  if (paramsT != nullptr && !al16(paramsT)) return BS_EINVAL;
+  const float c1 = (float)(1.0 - std::pow((double)beta1, step));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, step));
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if (dtype == WS_BF16)
+    hipLaunchKernelGGL(adam_kernel<bf16>, dim3(grid1(count)), dim3(256), 0, st, count, params,
+                       static_cast<bf16*>(paramsT), grads, m, v, lr, beta1, beta2, eps, c1, c2);
+  else
+    hipLaunchKernelGGL(adam_kernel<float>, dim3(grid1(count)), dim3(256), 0, st, count, params,
+                       static_cast<float*>(paramsT), grads, m, v, lr, beta1, beta2, eps, c1,
+                       c2);
+  return hipGetLastError() == hipSuccess ? BS_OK : BS_ELAUNCH;
+}
+
+int32_t ws_features(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
+                    const double* const planes[7], const float norm[14], void* X,
+                    void* stream) {
+  if (!dtype_ok(dtype) || n < 1 || batch < 1 || ld < batch || planes == nullptr ||
+      norm == nullptr || !al16(X))
+    return BS_EINVAL;
+  if ((n + 63) / 64 > 65535) return BS_EINVAL;
+  Norm nm;
+  for (int f = 0; f < 7; ++f) {
+    if (planes[f] == nullptr || !(norm[7 + f] > 0.0f)) return BS_EINVAL;
+    nm.mean[f] = norm[f];
+    nm.scale[f] = norm[7 + f];
+  }
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 grid((unsigned)((batch + 63) / 64), (unsigned)((n + 63) / 64));
+  if (dtype == WS_BF16)
+    hipLaunchKernelGGL(features_kernel<bf16>, grid, dim3(256), 0, st, n, batch, ld, planes[0],
+                       planes[1], planes[2], planes[3], planes[4], planes[5], planes[6], nm,
+                       static_cast<bf16*>(X));
+  else
+    hipLaunchKernelGGL(features_kernel<float>, grid, dim3(256), 0, st, n, batch, ld, planes[0],
+                       planes[1], planes[2], planes[3], planes[4], planes[5], planes[6], nm,
+                       static_cast<float*>(X));
+  return hipGetLastError() == hipSuccess ? BS_OK : BS_ELAUNCH;
+}
+
+int32_t ws_apply(int64_t n, int64_t batch, int64_t ld, const float* Y, const double* uprev,
+                 float mu_t, float sigma_t, double* x0, void* stream) {
+  if (n < 1 || batch < 1 || ld < batch || !al16(Y) || uprev == nullptr || x0 == nullptr)
+    return BS_EINVAL;
+  if ((n + 63) / 64 > 65535) return BS_EINVAL;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const dim3 grid((unsigned)((batch + 63) / 64), (unsigned)((n + 63) / 64));
+  hipLaunchKernelGGL(apply_kernel, grid, dim3(256), 0, st, n, batch, ld, Y, uprev, mu_t, sigma_t,
+                     x0);
+  return hipGetLastError() == hipSuccess ? BS_OK : BS_ELAUNCH;
+}
+
+}  // extern "C"

@@ -205,3 +205,35 @@ def test_valid_call_without_device_reports_enodev(bs):
     d5 = lib.VP5(*[_fake(k) for k in range(5)])
     st = lib.band_factor(5, 0, 16, 8, 8, d5, _fake(7), _fake(9), None)
     assert st == bs.BS_ENODEV
+
+
+def test_warmstart_symbols_and_host_checks(bs):
+    """include/warmstart.h: every declared function is exported; bad
+    arguments are rejected before any device work."""
+    from paper_1804_09666_amd import warmstart as wsm
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "warmstart.h")).read(),
+                  flags=re.S)
+    names = set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", text, flags=re.M))
+    assert names == set(wsm.EXPORTED), names
+    lib = wsm.load()
+    assert wsm.param_count() == 448 * 512 + 512 + 2 * (512 * 512 + 512) + 64 * 512 + 64
+    bad = ctypes.c_size_t(-1).value
+    assert lib.ws_workspace_bytes(0, 3, 16) == bad and lib.ws_workspace_bytes(2, 1, 16) == bad
+    assert lib.ws_workspace_bytes(1, 2, 16) > lib.ws_workspace_bytes(0, 2, 16) > 0
+    E = bs.BS_EINVAL
+    a, b, c = _fake(1), _fake(2), _fake(3)
+    mis = ctypes.c_void_p(0x10008)
+    assert lib.ws_gemm_nt(2, 16, 16, 12, a, b, None, 0, None, c, None, None) == E   # K % 8
+    assert lib.ws_gemm_nt(1, 16, 16, 6, a, b, None, 0, None, c, None, None) == E    # K % 4
+    assert lib.ws_gemm_nt(2, 16, 16, 16, mis, b, None, 0, None, c, None, None) == E
+    assert lib.ws_gemm_nt(2, 16, 16, 16, a, b, None, 0, None, None, None, None) == E
+    assert lib.ws_gemm_nt(3, 16, 16, 16, a, b, None, 0, None, c, None, None) == E
+    ws_need = lib.ws_workspace_bytes(1, 2, 16)
+    assert lib.ws_backward(2, 12, a, b, c, a, b, c, ws_need, None) == E                # P % 8
+    assert lib.ws_backward(2, 16, a, b, c, a, b, c, ws_need - 1, None) == bs.BS_EWORKSPACE
+    assert lib.ws_forward(2, 16, a, b, c, a, c, 0, None) == bs.BS_EWORKSPACE
+    assert lib.ws_adam(2, 10, a, None, b, c, a, 1e-3, 0.9, 0.999, 1e-8, 0, None) == E  # step 0
+    planes = (ctypes.c_void_p * 7)(*[_fake(k) for k in range(7)])
+    norm = (ctypes.c_float * 14)(*([0.0] * 7 + [1.0] * 6 + [0.0]))                    # scale 0
+    assert lib.ws_features(2, 64, 4, 4, planes, norm, a, None) == E
+    assert lib.ws_apply(64, 4, 3, a, b, 0.0, 1.0, c, None) == E                       # ld < batch

@@ -1,0 +1,185 @@
+"""GPU parity of the learned SIP start vector (matrix-core GEMM, network
+forward/backward, loss, Adam, patch features, start vector) against the FP64
+CPU oracle, and its effect on SIP iteration counts."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_oracle as mo
+from paper_1804_09666_amd import bandsolve as bs
+from paper_1804_09666_amd import warmstart as wsm
+from paper_1804_09666_amd import workloads as wl
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+DT = {"f32": wsm.WS_F32, "bf16": wsm.WS_BF16}
+
+
+def dev(a, dtype=torch.float32):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def host(t):
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("M,N,K", [(300, 200, 448), (128, 128, 32), (1000, 64, 512),
+                                   (64, 512, 72), (5, 3, 8)])
+def test_gemm_nt_parity(dt, M, N, K):
+    rng = np.random.default_rng(M + N + K)
+    A, B = rng.normal(size=(M, K)), rng.normal(size=(N, K))
+    bias = rng.normal(size=N)
+    mask = rng.normal(size=(M, N))
+    if dt == "bf16":
+        A, B = mo.bf16_round(A), mo.bf16_round(B)
+        mask = mo.bf16_round(mask)
+    tdt = wsm.TORCH_DTYPE[DT[dt]]
+    At, Bt, mt = dev(A, tdt), dev(B, tdt), dev(mask, tdt)
+    bt = dev(bias)
+    C32 = torch.empty((M, N), dtype=torch.float32, device="cuda")
+    CT = torch.empty((M, N), dtype=tdt, device="cuda")
+    say(f"gemm {dt} M={M} N={N} K={K}")
+    wsm.gemm_nt(At, Bt, bt, True, mt, C32, CT)
+    torch.cuda.synchronize()
+    bias32 = bias.astype(np.float32).astype(np.float64)
+    ref = np.maximum(A @ B.T + bias32, 0.0) * (mask > 0)
+    scale = np.abs(A) @ np.abs(B).T + np.abs(bias32)
+    err = np.abs(host(C32) - ref)
+    assert (err <= K * 2.0**-23 * scale + 1e-30).all()   # FP32 products and sums over K terms
+    rt = np.abs(host(CT) - host(C32))
+    tol = 2.0**-24 if dt == "f32" else 2.0**-8
+    assert (rt <= tol * np.abs(host(C32))).all()    # one rounding to the output type
+
+
+def _problem(P, seed):
+    rng = np.random.default_rng(seed)
+    p = wsm.init_params(seed).astype(np.float64)
+    # non-zero biases so that their gradients and the ReLU masks are exercised
+    layers = mo.unpack(p)
+    for W, b in layers:
+        b[:] = rng.normal(0, 0.1, b.size)
+    p = mo.pack(layers).astype(np.float32).astype(np.float64)
+    X = rng.normal(size=(P, mo.DIMS[0]))
+    T = rng.normal(size=(P, mo.DIMS[-1]))
+    return p, X, T
+
+
+@pytest.mark.parametrize("dt,tol", [("f32", 1e-4), ("bf16", 3e-2)])
+def test_forward_backward_against_oracle(dt, tol):
+    """Gradients of the matrix-core forward/backward against the oracle's
+    chain rule (itself pinned to finite differences), layer by layer."""
+    P = 264
+    p, X, T = _problem(P, 7)
+    dtype = DT[dt]
+    if dt == "bf16":
+        X = mo.bf16_round(X)
+    p32 = dev(p)
+    pT = wsm.convert(p32, dtype) if dtype == wsm.WS_BF16 else p32
+    Xt = dev(X, wsm.TORCH_DTYPE[dtype])
+    ws = wsm.workspace(wsm.OP_TRAIN, dtype, P)
+    Y = wsm.forward(dtype, Xt, p32, pT, ws=ws)
+    dY = torch.empty_like(Y)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    part = torch.empty(P, dtype=torch.float64, device="cuda")
+    wsm.mse(Y, dev(T), dY, loss, part)
+    grads = torch.empty_like(p32)
+    wsm.backward(dtype, Xt, p32, pT, dY, grads, ws)
+    torch.cuda.synchronize()
+    Yo, acts = mo.forward(X, p, bf16=(dt == "bf16"))
+    lo, dYo = mo.mse(Yo, T)
+    go = mo.backward(host(dY), acts, p, bf16=(dt == "bf16"))
+    say(f"{dt}: loss gpu {loss.item():.6e} oracle {lo:.6e}")
+    assert abs(loss.item() - lo) <= tol * lo
+    assert np.abs(host(Y) - Yo).max() <= tol * np.abs(Yo).max()
+    assert np.abs(host(dY) - dYo).max() <= tol * np.abs(dYo).max()
+    g = host(grads)
+    for k, ((Wg, bg), (Wo, bo)) in enumerate(zip(mo.unpack(g), mo.unpack(go))):
+        ew = np.abs(Wg - Wo).max() / np.abs(Wo).max()
+        eb = np.abs(bg - bo).max() / np.abs(bo).max()
+        say(f"  layer {k + 1}: dW rel err {ew:.2e}, db rel err {eb:.2e}")
+        assert ew <= tol and eb <= tol
+
+
+def test_adam_step_against_oracle():
+    rng = np.random.default_rng(11)
+    n = wsm.param_count()
+    p, g = rng.normal(size=n), rng.normal(size=n)
+    m, v = rng.normal(size=n) * 0.1, np.abs(rng.normal(size=n)) * 0.01
+    p32, g32, m32, v32 = (dev(a) for a in (p, g, m, v))
+    pT = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+    wsm.adam(wsm.WS_BF16, p32, pT, g32, m32, v32, lr=1e-3, step=7)
+    torch.cuda.synchronize()
+    f = lambda a: a.astype(np.float32).astype(np.float64)
+    po, mo_, vo = mo.adam(f(p), f(g), f(m), f(v), 7, lr=1e-3)
+    assert np.abs(host(p32) - po).max() <= 1e-6
+    assert np.abs(host(m32) - mo_).max() <= 1e-6 and np.abs(host(v32) - vo).max() <= 1e-6
+    assert np.array_equal(host(pT), mo.bf16_round(host(p32)))
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+@pytest.mark.parametrize("n,batch,ld", [(4096, 16, 16), (70, 5, 64), (200, 70, 72)])
+def test_features_and_start_vector(dt, n, batch, ld):
+    rng = np.random.default_rng(n + batch)
+    arrs = [rng.normal(size=(batch, n)) for _ in range(7)]
+    for k, (i, j) in {0: (0, 2), 1: (0, 1), 3: (n - 1, n), 4: (n - 2, n)}.items():
+        arrs[k][:, i:j] = np.nan     # slots outside the matrix are never used
+    norm = np.array([0.1, -0.2, 3.0, 0.5, -1.0, 0.25, 0.0] + [1.5, 2.0, 0.5, 1.0, 4.0, 0.75, 1.0],
+                    dtype=np.float32)
+    planes = [dev(wl.interleave(a, ld, fill=np.nan), torch.float64) for a in arrs]
+    dtype = DT[dt]
+    X = wsm.features(dtype, planes, norm, n, batch)
+    torch.cuda.synchronize()
+    Xo = mo.features(*arrs, norm[:7].astype(np.float64), norm[7:].astype(np.float64))
+    Xo = Xo.astype(np.float32).astype(np.float64)
+    if dt == "bf16":
+        Xo = mo.bf16_round(Xo)
+    assert np.array_equal(host(X), Xo)
+    Y = rng.normal(size=(X.shape[0], 64)).astype(np.float32)
+    x0 = wsm.apply(dev(Y), planes[6], 0.125, 0.5, n, batch)
+    torch.cuda.synchronize()
+    ref = mo.apply_start(Y.astype(np.float64), arrs[6], 0.125, 0.5)
+    assert np.array_equal(wl.deinterleave(x0.cpu().numpy(), batch), ref)
+
+
+def test_learned_start_reduces_sip_iterations():
+    """Train on the x-sweeps of the first 24 steps of a 256 x 256 ADI run,
+    then start SIP-HB on the 8 steps after them from zero, from the previous
+    step's solution, and from the network's prediction."""
+    N, steps, train_steps = 256, 32, 24
+    rec = []
+
+    def keep(step, planes, w):
+        rec.append(([p.clone() for p in planes], w.clone()))
+    wsm.adi_trajectory(N, steps, r=4.0, on_xsweep=keep)
+    net = wsm.WarmStart(wsm.WS_BF16, seed=3)
+    sample = rec[1:train_steps]
+    net.fit_scaling(sample, N, N)
+    X = torch.cat([wsm.features(net.dtype, planes, net.norm, N, N) for planes, _ in sample])
+    T = torch.cat([net.targets(planes, w, N, N) for planes, w in sample])
+    g = torch.Generator(device="cuda").manual_seed(0)
+    losses = []
+    iters = 1500
+    for it in range(iters):
+        idx = torch.randint(0, X.shape[0], (1024,), device="cuda", generator=g)
+        loss = net.train_step(X[idx].contiguous(), T[idx].contiguous(),
+                              1e-3 * 0.1 ** (it / iters))
+        if it % 100 == 0 or it == iters - 1:
+            losses.append(loss.item())
+    say(f"loss trace {[round(v, 4) for v in losses]}")
+    assert losses[-1] < 0.2 * losses[0]
+    its = {"zero": [], "prev": [], "learned": []}
+    for planes, w in rec[train_steps:]:
+        diags, rhs, up = planes[:5], planes[5], planes[6]
+        starts = {"zero": torch.zeros_like(rhs), "prev": up.clone(),
+                  "learned": net.predict(diags, rhs, up, N, N)}
+        for name, x0 in starts.items():
+            x, it, rr, info = bs.sip(diags, rhs, x0, tol=1e-10, max_iter=200, s_L=3, s_U=3,
+                                     batch=N)
+            assert (info == 0).all()
+            its[name].append(float(it.float().mean()))
+            assert (x - w).abs().max().item() <= 1e-7 * w.abs().max().item()
+    mean = {k: float(np.mean(v)) for k, v in its.items()}
+    say(f"mean SIP iterations to 1e-10: {mean}")
+    assert mean["learned"] < mean["prev"] < mean["zero"]

@@ -80,6 +80,7 @@ def test_features_positions_masks_and_padding():
     batch, n = 2, 70          # two patches per system, the second one ragged
     arrs = [np.full((batch, n), 10.0 * (f + 1)) for f in range(7)]
     arrs[5] = np.arange(batch * n, dtype=float).reshape(batch, n)
+    arrs[6] = np.zeros((batch, n))      # u_prev = 0: the residual feature is the rhs
     mean = np.array([1.0] * 7)
     scale = np.array([2.0] * 7)
     X = mo.features(*arrs, mean, scale)
@@ -91,6 +92,27 @@ def test_features_positions_masks_and_padding():
     assert X[0, 64] == -0.5 and X[0, 65] == (20.0 - 1) / 2                    # c_0
     assert X[1, 3 * 64 + 5] == -0.5 and X[1, 3 * 64 + 4] == (40.0 - 1) / 2   # a_{n-1}
     assert X[1, 4 * 64 + 4] == -0.5 and X[1, 4 * 64 + 3] == (50.0 - 1) / 2   # b_{n-2}
+
+
+def test_residual_feature_of_exact_solution_is_zero():
+    """Feature 5 is rhs - A u_prev: zero when u_prev solves the system, and
+    the plain product otherwise (dense check)."""
+    rng = np.random.default_rng(9)
+    batch, n = 3, 130
+    dg = [rng.normal(size=(batch, n)) for _ in range(5)]
+    dg[2] += 6.0
+    x = rng.normal(size=(batch, n))
+    Ad = np.zeros((batch, n, n))
+    for s in range(batch):
+        for off, arr in zip((-2, -1, 0, 1, 2), dg):
+            idx = np.arange(max(0, -off), min(n, n - off))
+            Ad[s, idx, idx + off] = arr[s, idx]
+    rhs = np.einsum("sij,sj->si", Ad, x)
+    X = mo.features(*dg, rhs, x, np.zeros(7), np.ones(7))
+    r = X[:, 5 * 64:6 * 64].reshape(batch, -1)[:, :n]
+    assert np.abs(r).max() <= 1e-12 * np.abs(rhs).max()
+    X2 = mo.features(*dg, rhs, np.zeros((batch, n)), np.zeros(7), np.ones(7))
+    assert np.array_equal(X2[:, 5 * 64:6 * 64].reshape(batch, -1)[:, :n], rhs)
 
 
 def test_apply_start_round_trip():
