@@ -284,6 +284,106 @@ def other_rows(pd, td):
     return out
 
 
+def warmstart_rows(N=4096, steps=200, train_steps=150, eval_every=5, hb_s=(3, 3), tol=1e-10,
+                   iters=2000, per_step=4096, batch=4096):
+    """Learned SIP start vector on an N x N ADI run: train on the x-sweeps of
+    the first `train_steps` steps (sampled patches), then start SIP-HB on
+    held-out later steps from zero, from the previous step's solution and
+    from the network's prediction; iterations and wall time to `tol`."""
+    from paper_1804_09666_amd import warmstart as wsm
+    t_start = time.perf_counter()
+    net = wsm.WarmStart(wsm.WS_BF16, seed=7)
+    gen = wsm.adi_steps(N)
+    npatch = N * ((N + 63) // 64)
+    g = torch.Generator(device="cuda").manual_seed(1)
+    fit, Xs, Ts = [], [], []
+    for step, planes, w in gen:
+        if step == 0:
+            continue
+        if len(fit) < 8:                       # scaling from the first training sweeps
+            fit.append(([p.clone() for p in planes], w.clone()))
+            if len(fit) < 8:
+                continue
+            net.fit_scaling(fit, N, N)
+            todo = fit
+        else:
+            todo = [(planes, w)]
+        for pl, ww in todo:
+            idx = torch.randint(0, npatch, (per_step,), device="cuda", generator=g)
+            Xs.append(wsm.features(net.dtype, pl, net.norm, N, N)[idx])
+            Ts.append(net.targets(pl, ww, N, N)[idx])
+        if step >= train_steps - 1:
+            break
+    del fit
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    del Xs, Ts
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t_start
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    losses = []
+    for it in range(iters):
+        idx = torch.randint(0, X.shape[0], (batch,), device="cuda", generator=g)
+        loss = net.train_step(X[idx], T[idx], 1e-3 * 0.1 ** (it / iters))
+        if it % 250 == 0 or it == iters - 1:
+            losses.append(loss.item())
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1)
+    del X, T
+    # held-out sweeps
+    res = {k: {"iters_mean": [], "iters_max": [], "ms": []} for k in ("zero", "prev", "learned")}
+    ws_fwd = wsm.workspace(wsm.OP_FORWARD, net.dtype, npatch)
+    Xb = torch.empty((npatch, wsm.IN), dtype=torch.bfloat16, device="cuda")
+    Yb = torch.empty((npatch, wsm.OUT), dtype=torch.float32, device="cuda")
+    f = None
+    infer_ms = []
+    for step, planes, w in gen:
+        if step >= steps:
+            break
+        if (step - train_steps) % eval_every:
+            continue
+        diags, rhs, up = planes[:5], planes[5], planes[6]
+        if f is None:
+            f = torch.empty((4, N, N), dtype=torch.float64, device="cuda")
+            wsip = torch.empty(bs.workspace_bytes(bs.OP_SIP, 5, N, N) // 8 + 1,
+                               dtype=torch.float64, device="cuda")
+        bs.factor(diags, batch=N, out=f)
+        for name in ("zero", "prev", "learned"):
+            x0 = torch.zeros_like(rhs) if name != "prev" else up.clone()
+            torch.cuda.synchronize()
+            a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            a.record()
+            if name == "learned":
+                net.predict(diags, rhs, up, N, N, x0=x0, ws=ws_fwd, X=Xb, Y=Yb)
+            b.record()
+            x, it, rr, info = bs.sip(diags, rhs, None, tol=tol, max_iter=40, s_L=hb_s[0],
+                                     s_U=hb_s[1], factors=f, batch=N, x=x0, workspace=wsip)
+            c.record()
+            torch.cuda.synchronize()
+            if name == "learned":
+                infer_ms.append(a.elapsed_time(b))
+            res[name]["iters_mean"].append(float(it.float().mean()))
+            res[name]["iters_max"].append(int(it.max()))
+            res[name]["ms"].append(a.elapsed_time(c))
+            res[name]["ok"] = bool((info == 0).all()) and res[name].get("ok", True)
+            res[name]["err_vs_direct_max"] = max(
+                res[name].get("err_vs_direct_max", 0.0),
+                float((x - w).abs().max() / w.abs().max()))
+    out = {"grid": N, "steps": steps, "train_steps": train_steps,
+           "held_out_steps_evaluated": len(res["zero"]["ms"]), "hb_s": list(hb_s), "tol": tol,
+           "dataset_s": t_data, "train_iters": iters, "train_batch": batch,
+           "train_ms": train_ms, "loss_trace": losses,
+           "inference_ms_mean": float(np.mean(infer_ms)),
+           "inference_forward_TFLOPs": 2 * npatch * (448 * 512 + 2 * 512 * 512 + 512 * 64) /
+                                       (float(np.mean(infer_ms)) * 1e-3) / 1e12}
+    for k, v in res.items():
+        out[k] = {"iters_mean": float(np.mean(v["iters_mean"])),
+                  "iters_max": int(max(v["iters_max"])), "ms_mean": float(np.mean(v["ms"])),
+                  "converged": v["ok"], "err_vs_direct_max": v["err_vs_direct_max"]}
+    return out
+
+
 def pmc_run():
     """Workload for the rocprofv3 counter passes: 5 PD solves of the sweep
     batch (rotating inputs) and one plain 1 GiB device copy whose HBM bytes
@@ -428,6 +528,9 @@ def main():
         prec, prec_x, prec_samples = precision_rows()
         line["fp32_ir"] = prec
         samples.update(prec_samples)
+        log("learned warm start (4096 x 4096 ADI run)")
+        line["warm_start"] = warmstart_rows()
+        torch.cuda.empty_cache()
     if not args.no_cpu:
         log("timing the CPU oracle")
         line["cpu_baseline"], refs = cpu_baseline(pd, samples)
