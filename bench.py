@@ -384,6 +384,94 @@ def warmstart_rows(N=4096, steps=200, train_steps=150, eval_every=5, hb_s=(3, 3)
     return out
 
 
+def profile_rows():
+    """Workload for `rocprofv3 --kernel-trace --stats`: a few launches of every
+    hot-path row (the per-kernel durations are read from the profiler)."""
+    KEYS = ("e", "c", "d", "a", "b", "y")
+    pd, td, _ = wl.config1(r=R_ADI, N=N_ROWS)
+    t5 = {k: torch.from_numpy(wl.interleave(pd[k])).cuda() for k in KEYS}
+    t3 = {k: torch.from_numpy(wl.interleave(td[k])).cuda() for k in ("c", "d", "a", "y")}
+    D5, D3 = diags_of(t5, 5), diags_of(t3, 3)
+    x = torch.empty_like(t5["y"])
+    info = torch.empty(BATCH, dtype=torch.int32, device="cuda")
+
+    def rep(name, fn, k=5):
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        log(f"profiled {name}")
+    rep("npdm split PD", lambda: bs.solve(D5, t5["y"], x, batch=BATCH, info=info))
+    rep("ntdm split TD", lambda: bs.solve(D3, t3["y"], x, kind=3, batch=BATCH, info=info))
+    rows = np.full((2, BATCH), -1, dtype=np.int32)
+    oe, ob = np.zeros((2, BATCH)), np.zeros((2, BATCH))
+    rows[0], ob[0] = 0, pd["b"][:, 0]
+    rows[1], oe[1] = N_ROWS - 1, pd["e"][:, N_ROWS - 1]
+    dv = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (rows, oe, ob)]
+    rep("mnpdm split", lambda: bs.solve_mnpdm([t5["c"], t5["d"], t5["a"]], *dv, t5["y"], x,
+                                              batch=BATCH, info=info))
+    t32 = {k: v.float() for k, v in t5.items()}
+    x32 = torch.empty_like(t32["y"])
+    rep("fp32 storage PD", lambda: bs.solve(diags_of(t32, 5), t32["y"], x32, batch=BATCH,
+                                            info=info))
+    f = torch.empty((4, N_ROWS, BATCH), dtype=torch.float64, device="cuda")
+    rep("ilu0 factor", lambda: bs.factor(D5, batch=BATCH, out=f, info=info))
+    rep("substitution", lambda: bs.solve(D5, t5["y"], x, batch=BATCH, factors=f, info=info))
+    rep("sip hb(3,4)", lambda: bs.sip(D5, t5["y"], tol=1e-10, max_iter=12, s_L=3, s_U=4,
+                                      factors=f, batch=BATCH), k=1)
+    rep("sip exact", lambda: bs.sip(D5, t5["y"], tol=1e-10, max_iter=3, factors=f, batch=BATCH),
+        k=1)
+    del t5, t3, t32, x, x32, f
+    nsys, n = 256, 1_000_000
+    v = wl.smooth_lines(nsys, n, wl.BASE_SEED + 3)
+    c3 = wl.sweep_lines_interleaved(torch.from_numpy(np.ascontiguousarray(v.T)).cuda(), R_ADI, 2)
+    del v
+    xc = torch.empty_like(c3["y"])
+    ic = torch.empty(nsys, dtype=torch.int32, device="cuda")
+    rep("long path n=1e6", lambda: bs.solve(diags_of(c3, 5), c3["y"], xc, batch=nsys, info=ic),
+        k=2)
+    rep("refine n=1e6", lambda: bs.refine(diags_of(c3, 5), c3["y"], xc, batch=nsys, tol=1e-10,
+                                          max_steps=4), k=1)
+    del c3, xc
+    torch.cuda.empty_cache()
+    from paper_1804_09666_amd import warmstart as wsm
+    net = wsm.WarmStart(wsm.WS_BF16, seed=7)
+    P = 4096 * 64
+    X = torch.zeros((P, wsm.IN), dtype=torch.bfloat16, device="cuda")
+    Y = torch.empty((P, wsm.OUT), dtype=torch.float32, device="cuda")
+    wsf = wsm.workspace(wsm.OP_FORWARD, wsm.WS_BF16, P)
+    rep("warm-start network forward, 262144 patches",
+        lambda: wsm.forward(wsm.WS_BF16, X, net.p32, net.pT, Y, wsf), k=3)
+
+
+def summarize_stats(csv_dir, out_path, title, command):
+    """rocprofv3 kernel statistics (CSV) -> short text table."""
+    import csv
+    import glob
+    import re
+    rows = []
+    for fn in glob.glob(os.path.join(csv_dir, "**", "*kernel_stats.csv"), recursive=True):
+        for r in csv.DictReader(open(fn)):
+            name = r["Name"]
+            if name.startswith("_Z"):
+                import subprocess
+                name = subprocess.run(["c++filt"], input=name, capture_output=True,
+                                      text=True).stdout.strip() or name
+            name = name.replace("(anonymous namespace)::", "")
+            name = re.sub(r"\(.*", "", name)
+            name = re.sub(r"^void ", "", name)
+            rows.append((name[:100], int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                         float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3,
+                         float(r["Percentage"])))
+    rows.sort(key=lambda t: -t[5])
+    with open(out_path, "w") as fh:
+        fh.write(f"# rocprofv3 kernel statistics: {title}\n")
+        fh.write(f"# command (from the repository root):\n#   {command}\n")
+        fh.write("name | calls | avg_us | min_us | max_us | share_%\n")
+        for t in rows:
+            fh.write(f"{t[0]} | {t[1]} | {t[2]:.2f} | {t[3]:.2f} | {t[4]:.2f} | {t[5]:.2f}\n")
+    print(open(out_path).read())
+
+
 def pmc_run():
     """Workload for the rocprofv3 counter passes: 5 PD solves of the sweep
     batch (rotating inputs) and one plain 1 GiB device copy whose HBM bytes
@@ -422,7 +510,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path=TRAFFIC_FILE):
     res = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = read(d, counter)
-        kern = [v for k, v in rows if "part_kernel<5" in k]
+        kern = [v for k, v in rows if "part_kernel<double, 5," in k]
         copy = [v for k, v in rows if "copybuffer" in k.lower()]
         if not kern or not copy:
             raise SystemExit(f"{counter}: kernel or copy dispatch not found in {d}")
@@ -465,7 +553,18 @@ def main():
                     help="only run the workload of the rocprofv3 counter passes")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the HBM traffic summary from two counter passes")
+    ap.add_argument("--profile-rows", action="store_true",
+                    help="only run a few launches of every hot-path row (for rocprofv3)")
+    ap.add_argument("--summarize-stats", nargs=4,
+                    metavar=("CSV_DIR", "OUT", "TITLE", "COMMAND"),
+                    help="write a kernel-statistics table from rocprofv3 CSV output")
     args = ap.parse_args()
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats)
+        return
+    if args.profile_rows:
+        profile_rows()
+        return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
         return

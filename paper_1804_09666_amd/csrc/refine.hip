@@ -30,21 +30,27 @@ struct Planes {
 };
 
 // A32 = fl32(A) for every plane, r32 = fl32(b), x = 0, |b|_inf per system.
+// Work item q = (s, part) walks rows part, part + P, ... of system s and
+// folds |b| into one maximum before its single atomic.
 __global__ __launch_bounds__(kBlock) void setup_kernel(
     int64_t n, int64_t batch, int64_t ld, int nplanes, Planes pl, float* __restrict__ a32,
     const double* __restrict__ b, float* __restrict__ r32, double* __restrict__ x,
-    unsigned long long* __restrict__ bmax) {
-  const int64_t total = n * batch;
+    unsigned long long* __restrict__ bmax, int64_t parts) {
   const int64_t plane = n * ld;
-  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < total;
+  for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < batch * parts;
        q += (int64_t)gridDim.x * kBlock) {
-    const int64_t s = q % batch, i = q / batch;
-    const int64_t o = i * ld + s;
-    for (int k = 0; k < nplanes; ++k) a32[k * plane + o] = (float)pl.p[k][o];
-    const double bv = b[o];
-    r32[o] = (float)bv;
-    x[o] = 0.0;
-    atomic_max_nonneg(&bmax[s], fabs(bv));
+    const int64_t s = q % batch, part = q / batch;
+    double m = 0.0;
+    for (int64_t i = part; i < n; i += parts) {
+      const int64_t o = i * ld + s;
+      for (int k = 0; k < nplanes; ++k) a32[k * plane + o] = (float)pl.p[k][o];
+      const double bv = b[o];
+      r32[o] = (float)bv;
+      x[o] = 0.0;
+      const double av = fabs(bv);
+      m = (av > m || av != av) ? av : m;
+    }
+    atomic_max_nonneg(&bmax[s], m);
   }
 }
 
@@ -214,8 +220,12 @@ hipError_t launch_refine(int kind, int64_t n, int64_t batch, int64_t ld, const d
                      rmax, bmax, steps, relres, done);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(setup_kernel, dim3(grid_for(n * batch)), dim3(kBlock), 0, st, n, batch, ld,
-                     np, pl, a32, rhs, r32, x, bmax);
+  // rows of a system split over `parts` work items: about 2^19 items in all
+  // (256 CUs x 32 waves x 64 lanes), at least one row each
+  int64_t parts = ((int64_t(1) << 19) + batch - 1) / batch;
+  if (parts > n) parts = n;
+  hipLaunchKernelGGL(setup_kernel, dim3(grid_for(batch * parts)), dim3(kBlock), 0, st, n, batch,
+                     ld, np, pl, a32, rhs, r32, x, bmax, parts);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
 
@@ -225,10 +235,6 @@ hipError_t launch_refine(int kind, int64_t n, int64_t batch, int64_t ld, const d
     for (int k = 0; k < 5; ++k)
       if (kind == 5 || (k >= 1 && k <= 3)) d32planes[k] = a32 + (q++) * L.plane;
   }
-  // rows of a system split over `parts` work items: about 2^19 items in all
-  // (256 CUs x 32 waves x 64 lanes), at least one row each
-  int64_t parts = ((int64_t(1) << 19) + batch - 1) / batch;
-  if (parts > n) parts = n;
   for (int32_t step = 0; step < max_steps; ++step) {
     e = launch_direct(kind, 1, n, batch, ld, d32planes, r32, d32, sinfo, sws, st, done);
     if (e != hipSuccess) return e;
