@@ -245,6 +245,54 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
                   double* relres, int32_t* info, void* workspace,
                   size_t ws_bytes, void* stream);
 
+/* ---- Uneven batches --------------------------------------------------------
+ * NPDM / NTDM (Sec. 1) for `count` systems of different lengths n[i] >= 8 in
+ * one solve.  Layout: systems sorted by length (longest first) in groups of
+ * 16; group g is an [n_g][16] block (n_g = its longest member), so row r of
+ * system i is element offset[i] + 16 r of every array (e, c, d, a, b, rhs, x;
+ * FP64), and its status goes to info[slot[i]] (info has 16 * groups
+ * entries).  Elements of a block beyond a system's own length are never read
+ * or written; corner slots as for band_solve.
+ * Three launches over all groups (tile maps, per-system reduction, finish);
+ * the tile shape is one of bs_varlen_variants() compiled variants
+ * (bs_varlen_variant_shape: rows per lane M, lanes per system PW). */
+typedef struct {
+  int64_t count;       /* systems                                              */
+  int64_t groups;      /* groups of 16                                         */
+  int64_t elems;       /* elements every per-row array must hold               */
+  int64_t tiles[4];    /* tiles of the whole batch for each variant (unused 0) */
+  size_t table_bytes;  /* bytes of the device table                            */
+} bs_varlen_info;
+
+int32_t bs_varlen_variants(void);
+int32_t bs_varlen_variant_shape(int32_t variant, int32_t shape[2]);
+
+/* Host-only planning: fills *info, offset[count] and slot[count] (host
+ * arrays, nullable) and, when table != NULL, the table (host buffer of
+ * info->table_bytes) that the caller copies to a 256-byte-aligned device
+ * buffer for the solves.  BS_EINVAL for count < 1 or any n[i] < 8. */
+int32_t bs_varlen_layout(int64_t count, const int64_t* n, int64_t* offset, int32_t* slot,
+                         void* table, bs_varlen_info* info);
+
+/* Workspace bytes of band_solve_varlen for `variant` ((size_t)-1 if invalid);
+ * no initialisation needed. */
+size_t bs_varlen_workspace_bytes(int32_t kind, const bs_varlen_info* info, int32_t variant);
+
+/* Solve every system of the uneven batch (asynchronous on `stream`).  info[slot]
+ * as band_solve (0, or i+1 for the first bad pivot of the elimination). */
+int32_t band_solve_varlen(int32_t kind, const bs_varlen_info* vinfo, const void* table,
+                          int32_t variant, const void* const diags[5], const void* rhs, void* x,
+                          int32_t* info, void* workspace, size_t ws_bytes, void* stream);
+
+/* Autotuner: runs every variant `reps` times on the caller's batch (after one
+ * warm-up each), writes the mean time per solve to ms[variant] (nullable) and
+ * the fastest variant to *best.  Synchronises with `stream`; x and info hold
+ * the last run's results.  The workspace must fit every variant. */
+int32_t bs_varlen_tune(int32_t kind, const bs_varlen_info* vinfo, const void* table,
+                       const void* const diags[5], const void* rhs, void* x, int32_t* info,
+                       void* workspace, size_t ws_bytes, int32_t reps, float* ms,
+                       int32_t* best, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,9 +26,17 @@ OP_FACTOR, OP_SOLVE, OP_SOLVE_FACTORED, OP_MNPDM, OP_SIP, OP_REFINE = range(6)
 
 EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "bs_set_option",
             "bs_get_option", "bs_part_variant", "band_factor", "band_solve",
-            "band_solve_refine", "band_solve_mnpdm", "sip_solve")
+            "band_solve_refine", "band_solve_mnpdm", "sip_solve", "bs_varlen_variants",
+            "bs_varlen_variant_shape", "bs_varlen_layout", "bs_varlen_workspace_bytes",
+            "band_solve_varlen", "bs_varlen_tune")
 OPT_DIRECT_PATH, OPT_PART_PD_VARIANT, OPT_PART_TD_VARIANT, OPT_SIP_PATH = range(4)
 PATH_AUTO, PATH_LANE, PATH_PART = range(3)
+
+
+class VarlenInfo(ctypes.Structure):
+    """bs_varlen_info of include/bandsolve.h."""
+    _fields_ = [("count", ctypes.c_int64), ("groups", ctypes.c_int64), ("elems", ctypes.c_int64),
+                ("tiles", ctypes.c_int64 * 4), ("table_bytes", ctypes.c_size_t)]
 
 
 class BandSolveError(RuntimeError):
@@ -67,6 +75,15 @@ def load():
         "sip_solve": (i32, [i32, i64, i64, i64, vp5, vp, vp, vp, ctypes.c_double, i32,
                             i32, i32, vp, vp, vp, vp, sz, vp]),
     }
+    vip = ctypes.POINTER(VarlenInfo)
+    sig.update({
+        "bs_varlen_variants": (i32, []),
+        "bs_varlen_variant_shape": (i32, [i32, ctypes.POINTER(i32)]),
+        "bs_varlen_layout": (i32, [i64, vp, vp, vp, vp, vip]),
+        "bs_varlen_workspace_bytes": (sz, [i32, vip, i32]),
+        "band_solve_varlen": (i32, [i32, vip, vp, i32, vp5, vp, vp, vp, vp, sz, vp]),
+        "bs_varlen_tune": (i32, [i32, vip, vp, vp5, vp, vp, vp, vp, sz, i32, vp, vp, vp]),
+    })
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype = res
@@ -281,3 +298,84 @@ def sip(diags, rhs, x0=None, *, tol, max_iter, s_L=-1, s_U=-1, factors=None,
                        _stream(stream))
     _raise(st, "sip_solve")
     return x, iters, relres, info
+
+
+# ------------------------------------------------------------ uneven batches --
+class Varlen:
+    """Plan of an uneven batch (bs_varlen_layout): sizes -> group layout.
+    offset[i]: element of row 0 of system i (row r at offset[i] + 16 r);
+    slot[i]: its info entry.  The device table is uploaded once."""
+
+    def __init__(self, n, device="cuda"):
+        import numpy as np
+        lib = load()
+        n = np.ascontiguousarray(np.asarray(n, dtype=np.int64))
+        self.count = n.size
+        self.n = n
+        self.info = VarlenInfo()
+        self.offset = np.empty(n.size, dtype=np.int64)
+        self.slot = np.empty(n.size, dtype=np.int32)
+        st = lib.bs_varlen_layout(n.size, n.ctypes.data, self.offset.ctypes.data,
+                                  self.slot.ctypes.data, None, ctypes.byref(self.info))
+        if st != BS_OK:
+            raise BandSolveError(st, "bs_varlen_layout")
+        table = np.zeros(self.info.table_bytes, dtype=np.uint8)
+        lib.bs_varlen_layout(n.size, n.ctypes.data, None, None, table.ctypes.data,
+                             ctypes.byref(self.info))
+        self.table = torch.from_numpy(table).to(device)
+        self.elems = self.info.elems
+        self.slots = self.info.groups * 16
+
+    def variants(self):
+        lib = load()
+        out, shape = [], (ctypes.c_int32 * 2)()
+        for v in range(lib.bs_varlen_variants()):
+            lib.bs_varlen_variant_shape(v, shape)
+            out.append(tuple(shape))
+        return out
+
+    def workspace(self, kind, variant=None):
+        lib = load()
+        vs = range(lib.bs_varlen_variants()) if variant is None else [variant]
+        nbytes = max(lib.bs_varlen_workspace_bytes(kind, ctypes.byref(self.info), v) for v in vs)
+        return torch.empty(nbytes // 8 + 1, dtype=torch.float64, device=self.table.device)
+
+    def pack(self, systems, fill=0.0):
+        """Host list of 1-D arrays (system i's rows) -> flat float64 numpy array
+        in the group layout."""
+        import numpy as np
+        out = np.full(self.elems, fill, dtype=np.float64)
+        for i, v in enumerate(systems):
+            out[self.offset[i] + 16 * np.arange(len(v))] = v
+        return out
+
+    def unpack(self, flat):
+        """Inverse of pack for a host array."""
+        import numpy as np
+        return [flat[self.offset[i] + 16 * np.arange(self.n[i])] for i in range(self.count)]
+
+    def solve(self, kind, diags, rhs, x=None, info=None, variant=0, workspace=None, stream=None):
+        lib = load()
+        x = torch.empty_like(rhs) if x is None else x
+        info = torch.empty(self.slots, dtype=torch.int32, device=rhs.device) if info is None else info
+        ws = self.workspace(kind, variant) if workspace is None else workspace
+        st = lib.band_solve_varlen(kind, ctypes.byref(self.info), _ptr(self.table), variant,
+                                   lib.VP5(*[_ptr(t) for t in diags]), _ptr(rhs), _ptr(x),
+                                   _ptr(info), _ptr(ws), ws.numel() * ws.element_size(),
+                                   _stream(stream))
+        _raise(st, "band_solve_varlen")
+        return x, info
+
+    def tune(self, kind, diags, rhs, x, info, workspace, reps=5, stream=None):
+        """Autotuner: (best variant, [ms per variant])."""
+        lib = load()
+        nv = lib.bs_varlen_variants()
+        ms = (ctypes.c_float * nv)()
+        best = ctypes.c_int32(-1)
+        st = lib.bs_varlen_tune(kind, ctypes.byref(self.info), _ptr(self.table),
+                                lib.VP5(*[_ptr(t) for t in diags]), _ptr(rhs), _ptr(x),
+                                _ptr(info), _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), int(reps), ms,
+                                ctypes.byref(best), _stream(stream))
+        _raise(st, "bs_varlen_tune")
+        return best.value, list(ms)

@@ -1,0 +1,504 @@
+// split_core.h -- device building blocks of the split-row (partitioned)
+// NPDM / NTDM elimination shared by the fixed-shape kernels (direct_part.hip)
+// and the uneven-batch kernels (varlen.hip).  See direct_part.hip for the
+// method.
+#pragma once
+
+#include <climits>
+
+#include "bs_internal.h"
+
+namespace bs {
+namespace split {
+
+template <int NB>
+struct Map {  // T = pt - Vt xL - Wt xR,  B = pb - Vb xL - Wb xR
+  double pt[NB], pb[NB];
+  double Vt[NB][NB], Vb[NB][NB], Wt[NB][NB], Wb[NB][NB];
+};
+
+template <int NB>
+struct Node {  // interface: B_A = g0 + G1 xL + G2 xR,  T_B = h0 + H1 xL + H2 xR
+  double g0[NB], h0[NB];
+  double G1[NB][NB], G2[NB][NB], H1[NB][NB], H2[NB][NB];
+};
+
+template <int NB>
+constexpr int kRecSz = 2 * NB + 4 * NB * NB;  // doubles per Map or Node
+
+// The map of a range of identity rows (no couplings, zero solution).
+template <int NB>
+__device__ inline void zero_map(Map<NB>& m) {
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    m.pt[q] = m.pb[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) m.Vt[q][k] = m.Vb[q][k] = m.Wt[q][k] = m.Wb[q][k] = 0.0;
+  }
+}
+
+template <int NB>
+__device__ inline void mm(const double (&A)[NB][NB], const double (&B)[NB][NB],
+                          double (&C)[NB][NB]) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) acc = fma(A[i][k], B[k][j], acc);
+      C[i][j] = acc;
+    }
+}
+
+template <int NB>
+__device__ inline void mv(const double (&A)[NB][NB], const double (&x)[NB],
+                          double (&y)[NB]) {
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < NB; ++k) acc = fma(A[i][k], x[k], acc);
+    y[i] = acc;
+  }
+}
+
+// Inverse of a 1x1 or 2x2 block; false if singular or not finite.
+__device__ inline bool inv(const double (&M)[1][1], double (&R)[1][1]) {
+  R[0][0] = 1.0 / M[0][0];
+  return M[0][0] != 0.0 && isfinite(R[0][0]);
+}
+// 1/x from the hardware reciprocal estimate and two Newton steps (full
+// double precision up to an ulp; the interface blocks are far from the
+// subnormal range).
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+__device__ inline bool inv(const double (&M)[2][2], double (&R)[2][2]) {
+  const double det = fma(M[0][0], M[1][1], -M[0][1] * M[1][0]);
+  const double r = recip(det);
+  R[0][0] = M[1][1] * r;
+  R[0][1] = -M[0][1] * r;
+  R[1][0] = -M[1][0] * r;
+  R[1][1] = M[0][0] * r;
+  return det != 0.0 && isfinite(r);
+}
+
+// Merge left part A with right part B (B's x_L is A's bottom pair, A's x_R
+// is B's top pair).  Returns false if the interface block is singular.
+template <int NB>
+__device__ bool merge(const Map<NB>& A, const Map<NB>& B, Map<NB>& AB, Node<NB>& nd) {
+  double Mx[NB][NB], S[NB][NB], T1[NB][NB], t[NB];
+  mm<NB>(A.Wb, B.Vt, Mx);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) Mx[i][j] = (i == j ? 1.0 : 0.0) - Mx[i][j];
+  const bool ok = inv(Mx, S);
+  mv<NB>(A.Wb, B.pt, t);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) t[i] = A.pb[i] - t[i];
+  mv<NB>(S, t, nd.g0);
+  mm<NB>(S, A.Vb, nd.G1);
+  mm<NB>(A.Wb, B.Wt, T1);
+  mm<NB>(S, T1, nd.G2);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) nd.G1[i][j] = -nd.G1[i][j];
+  mv<NB>(B.Vt, nd.g0, t);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) nd.h0[i] = B.pt[i] - t[i];
+  mm<NB>(B.Vt, nd.G1, nd.H1);
+  mm<NB>(B.Vt, nd.G2, nd.H2);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      nd.H1[i][j] = -nd.H1[i][j];
+      nd.H2[i][j] = -(nd.H2[i][j] + B.Wt[i][j]);
+    }
+  Map<NB> R;
+  mv<NB>(A.Wt, nd.h0, t);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) R.pt[i] = A.pt[i] - t[i];
+  mm<NB>(A.Wt, nd.H1, T1);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) R.Vt[i][j] = A.Vt[i][j] + T1[i][j];
+  mm<NB>(A.Wt, nd.H2, R.Wt);
+  mv<NB>(B.Vb, nd.g0, t);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) R.pb[i] = B.pb[i] - t[i];
+  mm<NB>(B.Vb, nd.G1, R.Vb);
+  mm<NB>(B.Vb, nd.G2, T1);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) R.Wb[i][j] = T1[i][j] + B.Wb[i][j];
+  AB = R;
+  return ok;
+}
+
+template <typename R>
+__device__ inline void store_rec(const R& r, double* dst) {
+  const double* src = reinterpret_cast<const double*>(&r);
+#pragma unroll
+  for (int q = 0; q < (int)(sizeof(R) / sizeof(double)); ++q) dst[q] = src[q];
+}
+template <typename R>
+__device__ inline void load_rec(R& r, const double* src) {
+  double* dst = reinterpret_cast<double*>(&r);
+#pragma unroll
+  for (int q = 0; q < (int)(sizeof(R) / sizeof(double)); ++q) dst[q] = src[q];
+}
+
+__device__ inline bool bad_pivot(double m) { return !(m != 0.0) || !isfinite(m); }
+
+// Streaming accesses: every input element is read once and every x element
+// written once, so they carry the non-temporal hint.  Storage may be FP64 or
+// FP32 (TIO); arithmetic is always FP64.
+template <typename TIO>
+__device__ inline TIO ldg(const TIO* __restrict__ base, uint32_t byte_off) {
+  return __builtin_nontemporal_load(
+      reinterpret_cast<const TIO*>(reinterpret_cast<const char*>(base) + byte_off));
+}
+template <typename TIO>
+__device__ inline void stg(TIO* __restrict__ base, uint32_t byte_off, double v) {
+  __builtin_nontemporal_store((TIO)v, reinterpret_cast<TIO*>(reinterpret_cast<char*>(base) + byte_off));
+}
+
+// Chunk of a pentadiagonal system: local NPDM with the couplings to
+// x_L = (x_{-2}, x_{-1}) (entries e_0, c_0 of row 0 and e_1 of row 1) and to
+// x_R = (x_M, x_{M+1}) (b_{M-2} of row M-2, a_{M-1} and b_{M-1} of row M-1)
+// as right-hand sides.  On return p, v0, v1, w0, w1 hold U^{-1} L^{-1} of
+// y and of the coupling columns; `bad` is the first local row with a bad
+// pivot (M if none).
+template <int M>
+__device__ inline void chunk_pd(const double (&e)[M], const double (&c)[M],
+                                const double (&d)[M], const double (&a)[M],
+                                const double (&b)[M], const double (&y)[M],
+                                double (&p)[M], double (&v0)[M], double (&v1)[M],
+                                double (&w0)[M], double (&w1)[M], int& bad) {
+  double al[M], be[M];
+  double fm2 = 0.0;  // L^{-1} of the x_M column at row M-2
+  bad = M;
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    double ga, mu;
+    if (r == 0) {
+      ga = 0.0;
+      mu = d[0];
+    } else if (r == 1) {
+      ga = c[1];
+      mu = fma(-al[0], ga, d[1]);
+    } else {
+      ga = fma(-al[r - 2], e[r], c[r]);
+      mu = fma(-al[r - 1], ga, fma(-be[r - 2], e[r], d[r]));
+    }
+    if (bad == M && bad_pivot(mu)) bad = r;
+    const double rc = 1.0 / mu;
+    if (r == 0)
+      al[0] = a[0] * rc;
+    else if (r <= M - 2)
+      al[r] = fma(-be[r - 1], ga, a[r]) * rc;
+    else
+      al[r] = 0.0;
+    be[r] = (r <= M - 3) ? b[r] * rc : 0.0;
+    if (r == 0) {
+      p[0] = y[0] * rc;
+      v0[0] = e[0] * rc;
+      v1[0] = c[0] * rc;
+    } else if (r == 1) {
+      p[1] = fma(-ga, p[0], y[1]) * rc;
+      v0[1] = (-ga * v0[0]) * rc;
+      v1[1] = fma(-ga, v1[0], e[1]) * rc;
+    } else {
+      p[r] = fma(-ga, p[r - 1], fma(-e[r], p[r - 2], y[r])) * rc;
+      v0[r] = fma(-ga, v0[r - 1], -e[r] * v0[r - 2]) * rc;
+      v1[r] = fma(-ga, v1[r - 1], -e[r] * v1[r - 2]) * rc;
+    }
+    if (r == M - 2) fm2 = b[M - 2] * rc;
+    if (r == M - 1) {
+      w0[M - 1] = fma(-ga, fm2, a[M - 1]) * rc;
+      w1[M - 1] = b[M - 1] * rc;
+    }
+  }
+  w0[M - 2] = fma(-al[M - 2], w0[M - 1], fm2);
+  w1[M - 2] = -al[M - 2] * w1[M - 1];
+  p[M - 2] = fma(-al[M - 2], p[M - 1], p[M - 2]);
+  v0[M - 2] = fma(-al[M - 2], v0[M - 1], v0[M - 2]);
+  v1[M - 2] = fma(-al[M - 2], v1[M - 1], v1[M - 2]);
+#pragma unroll
+  for (int r = M - 3; r >= 0; --r) {
+    p[r] = fma(-be[r], p[r + 2], fma(-al[r], p[r + 1], p[r]));
+    v0[r] = fma(-be[r], v0[r + 2], fma(-al[r], v0[r + 1], v0[r]));
+    v1[r] = fma(-be[r], v1[r + 2], fma(-al[r], v1[r + 1], v1[r]));
+    w0[r] = fma(-be[r], w0[r + 2], -al[r] * w0[r + 1]);
+    w1[r] = fma(-be[r], w1[r + 2], -al[r] * w1[r + 1]);
+  }
+}
+
+// Chunk of a tridiagonal system: local Thomas with the couplings to x_{-1}
+// (c_0 of row 0) and x_M (a_{M-1} of row M-1) as right-hand sides.
+template <int M>
+__device__ inline void chunk_td(const double (&c)[M], const double (&d)[M],
+                                const double (&a)[M], const double (&y)[M],
+                                double (&p)[M], double (&v0)[M], double (&w0)[M],
+                                int& bad) {
+  double al[M];
+  bad = M;
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    const double mu = (r == 0) ? d[0] : fma(-al[r - 1], c[r], d[r]);
+    if (bad == M && bad_pivot(mu)) bad = r;
+    const double rc = 1.0 / mu;
+    al[r] = (r <= M - 2) ? a[r] * rc : 0.0;
+    if (r == 0) {
+      p[0] = y[0] * rc;
+      v0[0] = c[0] * rc;
+    } else {
+      p[r] = fma(-c[r], p[r - 1], y[r]) * rc;
+      v0[r] = (-c[r] * v0[r - 1]) * rc;
+    }
+    if (r == M - 1) w0[M - 1] = a[M - 1] * rc;
+  }
+#pragma unroll
+  for (int r = M - 2; r >= 0; --r) {
+    p[r] = fma(-al[r], p[r + 1], p[r]);
+    v0[r] = fma(-al[r], v0[r + 1], v0[r]);
+    w0[r] = -al[r] * w0[r + 1];
+  }
+}
+
+// Binary tree over NL leaf maps held by lanes (leaf, g), leaf in [0, NL);
+// lanes with leaf >= NL only take part in the barriers.  Each internal node
+// owns one record slot in s_node: the right child parks its map there, the
+// left child merges and overwrites it with the node record, and on the way
+// down the left child replaces the record with the right child's outer pairs.
+// leaf_rows: rows per leaf, row0: first row of leaf 0 (for breakdown rows).
+template <int NB, int NL, int G>
+__device__ inline void tree_up(Map<NB>& mp, int leaf, int g, double* s_node,
+                               int* s_bad, int64_t leaf_rows, int64_t row0, int64_t n) {
+  constexpr int RS = kRecSz<NB>;
+  constexpr int L = __builtin_ctz(NL);
+  const bool active = leaf < NL;
+  int node_off = 0;
+#pragma unroll
+  for (int lvl = 1; lvl <= L; ++lvl) {
+    const int stride = 1 << lvl, half = stride >> 1;
+    const int k = leaf >> lvl;
+    double* slot = s_node + ((node_off + k) * G + g) * RS;
+    if (active && (leaf & (stride - 1)) == half) store_rec(mp, slot);
+    __syncthreads();
+    if (active && (leaf & (stride - 1)) == 0) {
+      Map<NB> rb;
+      load_rec(rb, slot);
+      Node<NB> nd;
+      if (!merge<NB>(mp, rb, mp, nd)) {
+        const int64_t row = row0 + (int64_t)(leaf + half) * leaf_rows - NB;
+        if (row < n) atomicMin(&s_bad[g], (int)(row + 1));
+      }
+      store_rec(nd, slot);
+    }
+    node_off += NL >> lvl;
+  }
+}
+
+// Walk back down: on entry the lanes with leaf == 0 hold the outer pairs of
+// the whole range; on exit every lane with leaf < NL holds its leaf's pairs.
+// The caller puts a barrier between tree_up and tree_down.
+template <int NB, int NL, int G>
+__device__ inline void tree_down(double (&xl)[NB], double (&xr)[NB], int leaf, int g,
+                                 double* s_node) {
+  constexpr int RS = kRecSz<NB>;
+  constexpr int L = __builtin_ctz(NL);
+  const bool active = leaf < NL;
+  int node_off = NL - 1;
+#pragma unroll
+  for (int lvl = L; lvl >= 1; --lvl) {
+    const int stride = 1 << lvl, half = stride >> 1;
+    const int k = leaf >> lvl;
+    node_off -= NL >> lvl;
+    double* slot = s_node + ((node_off + k) * G + g) * RS;
+    if (active && (leaf & (stride - 1)) == 0) {
+      Node<NB> nd;
+      load_rec(nd, slot);
+      double ba[NB], tb[NB], t1[NB], t2[NB];
+      mv<NB>(nd.G1, xl, t1);
+      mv<NB>(nd.G2, xr, t2);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) ba[q] = nd.g0[q] + t1[q] + t2[q];
+      mv<NB>(nd.H1, xl, t1);
+      mv<NB>(nd.H2, xr, t2);
+#pragma unroll
+      for (int q = 0; q < NB; ++q) tb[q] = nd.h0[q] + t1[q] + t2[q];
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        slot[q] = ba[q];        // right part: x_L = B_A, x_R unchanged
+        slot[NB + q] = xr[q];
+        xr[q] = tb[q];          // left part: x_R = T_B
+      }
+    }
+    __syncthreads();
+    if (active && (leaf & (stride - 1)) == half) {
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        xl[q] = slot[q];
+        xr[q] = slot[NB + q];
+      }
+    }
+  }
+}
+
+__device__ inline unsigned ld_counter(unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Device-coherent (write-through / cache-bypassing) accesses for data that
+// blocks on other XCDs read.
+__device__ inline void st_coherent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_coherent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+constexpr int kWaitVmem = 0x0F70;  // s_waitcnt vmcnt(0): this wave's memory ops done
+
+constexpr int kBadNone = INT_MAX;
+constexpr int kBadList = -3;
+
+// MNPDM's outer diagonals as a list per system: entry k of system s is row
+// row[k*ld + s] (-1 = unused) with e = e[k*ld + s], b = b[k*ld + s].
+struct Outer {
+  int32_t kmax;
+  const int32_t* row;
+  const double* e;
+  const double* b;
+};
+constexpr int kTimeout = -4;
+constexpr uint64_t kWaitTicks = 100000000;  // 1 s of the 100 MHz real-time counter
+
+// Loads the M rows of a chunk (first row r0) of system s into registers:
+// identity rows past n, zero couplings outside the matrix.  Byte offsets fit
+// in 32 bits (checked on the host), so every load is an SGPR base plus one
+// per-row VGPR offset shared by the six arrays.
+template <int KIND, int M, typename TIO, bool OUTER = true>
+__device__ inline void load_chunk(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
+                                  int64_t row_base,
+                                  const TIO* __restrict__ E, const TIO* __restrict__ C,
+                                  const TIO* __restrict__ D, const TIO* __restrict__ A,
+                                  const TIO* __restrict__ B, const TIO* __restrict__ Y,
+                                  double (&e)[M], double (&c)[M], double (&d)[M],
+                                  double (&a)[M], double (&b)[M], double (&y)[M]) {
+  const uint32_t row_bytes = (uint32_t)(ld * sizeof(TIO));
+  const uint32_t off0 = (uint32_t)((r0 * ld + s) * (int64_t)sizeof(TIO));
+  if constexpr (sizeof(TIO) == 8) {
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      const int64_t i = row_base + r0 + r;  // global row
+      const uint32_t o = off0 + (uint32_t)r * row_bytes;
+      const bool in = live && i < n;
+      d[r] = in ? ldg(D, o) : 1.0;
+      y[r] = in ? ldg(Y, o) : 0.0;
+      c[r] = (in && i >= 1) ? ldg(C, o) : 0.0;
+      a[r] = (in && i <= n - 2) ? ldg(A, o) : 0.0;
+      if (KIND == 5 && OUTER) {
+        e[r] = (in && i >= 2) ? ldg(E, o) : 0.0;
+        b[r] = (in && i <= n - 3) ? ldg(B, o) : 0.0;
+      } else {
+        e[r] = 0.0;
+        b[r] = 0.0;
+      }
+    }
+  } else {
+    // FP32 storage: unconditional loads (slots outside the matrix read the
+    // array's first element instead, and are replaced afterwards), all
+    // issued before the first widening to FP64 waits for its operand.
+    // Conditional loads would each sit in a branch with their widening, and
+    // the chunk's loads would then complete one at a time.
+    TIO re[M], rc[M], rd[M], ra[M], rb[M], ry[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      const int64_t i = row_base + r0 + r;
+      const uint32_t o = off0 + (uint32_t)r * row_bytes;
+      const bool in = live && i < n;
+      rd[r] = ldg(D, in ? o : 0u);
+      ry[r] = ldg(Y, in ? o : 0u);
+      rc[r] = ldg(C, (in && i >= 1) ? o : 0u);
+      ra[r] = ldg(A, (in && i <= n - 2) ? o : 0u);
+      if (KIND == 5) {
+        re[r] = ldg(E, (in && i >= 2) ? o : 0u);
+        rb[r] = ldg(B, (in && i <= n - 3) ? o : 0u);
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+      const int64_t i = row_base + r0 + r;
+      const bool in = live && i < n;
+      d[r] = in ? (double)rd[r] : 1.0;
+      y[r] = in ? (double)ry[r] : 0.0;
+      c[r] = (in && i >= 1) ? (double)rc[r] : 0.0;
+      a[r] = (in && i <= n - 2) ? (double)ra[r] : 0.0;
+      e[r] = (KIND == 5 && in && i >= 2) ? (double)re[r] : 0.0;
+      b[r] = (KIND == 5 && in && i <= n - 3) ? (double)rb[r] : 0.0;
+    }
+  }
+}
+
+// The chunk's affine map: tip rows of p, V, W.
+template <int NB, int M>
+__device__ inline Map<NB> chunk_map(const double (&p)[M], const double (&v)[NB][M],
+                                    const double (&w)[NB][M]) {
+  Map<NB> mp;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    mp.pt[q] = p[q];
+    mp.pb[q] = p[M - NB + q];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      mp.Vt[q][k] = v[k][q];
+      mp.Wt[q][k] = w[k][q];
+      mp.Vb[q][k] = v[k][M - NB + q];
+      mp.Wb[q][k] = w[k][M - NB + q];
+    }
+  }
+  return mp;
+}
+
+template <int KIND, int M>
+__device__ inline void eliminate_chunk(const double (&e)[M], const double (&c)[M],
+                                       const double (&d)[M], const double (&a)[M],
+                                       const double (&b)[M], const double (&y)[M],
+                                       double (&p)[M], double (&v)[KIND == 5 ? 2 : 1][M],
+                                       double (&w)[KIND == 5 ? 2 : 1][M], int& bad) {
+  if constexpr (KIND == 5)
+    chunk_pd<M>(e, c, d, a, b, y, p, v[0], v[1], w[0], w[1], bad);
+  else
+    chunk_td<M>(c, d, a, y, p, v[0], w[0], bad);
+}
+
+template <int NB, int M, typename TIO>
+__device__ inline void write_chunk(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
+                                   int64_t row_base,
+                                   const double (&p)[M], const double (&v)[NB][M],
+                                   const double (&w)[NB][M], const double (&xl)[NB],
+                                   const double (&xr)[NB], TIO* __restrict__ X) {
+  const uint32_t row_bytes = (uint32_t)(ld * sizeof(TIO));
+  const uint32_t off0 = (uint32_t)((r0 * ld + s) * (int64_t)sizeof(TIO));
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    const int64_t i = row_base + r0 + r;
+    double xv = p[r];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) xv = fma(-v[k][r], xl[k], fma(-w[k][r], xr[k], xv));
+    if (live && i < n) stg(X, off0 + (uint32_t)r * row_bytes, xv);
+  }
+}
+
+}  // namespace split
+}  // namespace bs

@@ -1,5 +1,7 @@
-"""Host checks of the seeded input generators (no solver arithmetic)."""
+"""Host checks of the seeded input generators (no solver arithmetic) and of the
+host-side planning of uneven batches."""
 import numpy as np
+import pytest
 import torch
 
 from paper_1804_09666_amd import workloads as wl
@@ -32,3 +34,24 @@ def test_config_shapes_and_seeds():
     a = wl.config3(nsys=4, n=100)
     b = wl.config3(nsys=4, n=100)
     assert all(np.array_equal(a[k], b[k]) for k in a)
+
+
+def test_uneven_batch_layout_host():
+    """Planning of an uneven batch (host only): groups of 16 sorted by length,
+    disjoint row positions, tile counts per compiled shape, rejection of
+    systems shorter than 8 rows."""
+    from paper_1804_09666_amd import bandsolve as bs
+    rng = np.random.default_rng(1)
+    n = np.floor(np.exp(rng.uniform(np.log(8), np.log(5000), 101))).astype(np.int64)
+    plan = bs.Varlen(n, device="cpu")
+    assert plan.info.groups == 7 and plan.slots == 112
+    order = np.argsort(plan.slot)
+    assert (np.diff(n[order]) <= 0).all()                       # longest first
+    pos = np.concatenate([plan.offset[i] + 16 * np.arange(n[i]) for i in range(n.size)])
+    assert np.unique(pos).size == pos.size and pos.max() < plan.elems
+    gn = [n[order[16 * g]] for g in range(plan.info.groups)]
+    assert plan.elems == 16 * sum(gn)
+    for v, (M, PW) in enumerate(plan.variants()):
+        assert plan.info.tiles[v] == sum(-(-x // (M * PW)) for x in gn)
+    with pytest.raises(bs.BandSolveError):
+        bs.Varlen(np.array([100, 7]), device="cpu")
