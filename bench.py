@@ -38,7 +38,15 @@ TD_BYTES_PER_ROW = 40            # c, d, a, y read + x written
 ROTATE = 4
 COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_npdm_split_pd_n2048_b2048.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_1804_09666_amd", "csrc", "direct_part.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1804_09666_amd", "csrc", f)
+               for f in ("direct_part.hip", "split_core.h")]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def log(msg):
@@ -92,8 +100,7 @@ def traffic_from_profile():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
-    if kv.get("kernel_source_sha256_16") != src_hash:
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -282,6 +289,91 @@ def other_rows(pd, td):
                         "us_per_iteration": ms * 1e3 / max(float(its.max()), 1.0),
                         "converged": int((res["si"] == 0).sum())}
     return out
+
+
+def varlen_rows(reps=5):
+    """Uneven batch: 10 000 dominant PD systems with n log-uniform in
+    [64, 65536] (about 1e8 rows).  The uneven-batch solver (tile shape from
+    the autotuner) eagerly and as one captured graph, against one band_solve
+    launch per size octave (systems padded with identity rows to the
+    octave's longest).  Returns (row, sampled GPU results, sampled host
+    systems)."""
+    KEYS = ("e", "c", "d", "a", "b", "y")
+    sizes = wl.config2_sizes()
+    plan = bs.Varlen(sizes)
+    dev = wl.dominant_groups(plan.slot_sizes)
+    del dev["x_true"]
+    assert dev["y"].numel() == plan.elems
+    diags = [dev[k] for k in ("e", "c", "d", "a", "b")]
+    x = torch.empty_like(dev["y"])
+    info = torch.empty(plan.slots, dtype=torch.int32, device="cuda")
+    ws = plan.workspace(5)
+    best, tune_ms = plan.tune(5, diags, dev["y"], x, info, ws, reps=3)
+    ms_eager = t_ms(lambda: plan.solve(5, diags, dev["y"], x, info, variant=best, workspace=ws),
+                    reps)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.solve(5, diags, dev["y"], x, info, variant=best, workspace=ws, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    ms_graph = t_ms(g.replay, reps)
+    torch.cuda.synchronize()
+    ok = bool((info.cpu().numpy()[plan.slot] == 0).all())
+    xh = x.cpu().numpy()
+    t = {k: v.cpu().numpy() for k, v in dev.items()}
+    pick = [int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 4242, 9999]
+    got, samples = {}, {}
+    for i in pick:
+        p = plan.offset[i] + 16 * np.arange(sizes[i])
+        samples[f"varlen_{i}"] = {k: t[k][p][None] for k in KEYS}
+        got[f"varlen_{i}"] = xh[p][None]
+    del dev, diags, x, ws, g
+    torch.cuda.empty_cache()
+    # one launch per size octave
+    edges = 64 * 2 ** np.arange(11)
+    buckets = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        idx = np.nonzero((sizes >= lo) & (sizes < hi if hi < edges[-1] else sizes <= hi))[0]
+        if idx.size == 0:
+            continue
+        nb, batch = int(sizes[idx].max()), idx.size
+        ld = wl.padded_ld(batch)
+        arr = {k: np.zeros((nb, ld)) for k in KEYS}
+        arr["d"][:] = 1.0                                  # padding rows: identity
+        for col, i in enumerate(idx):
+            p = plan.offset[i] + 16 * np.arange(sizes[i])
+            for k in KEYS:
+                arr[k][:sizes[i], col] = t[k][p]
+        bt = {k: torch.from_numpy(v).cuda() for k, v in arr.items()}
+        buckets.append((bt, batch, torch.empty_like(bt["y"]),
+                        torch.empty(batch, dtype=torch.int32, device="cuda"),
+                        torch.zeros(max(bs.workspace_bytes(bs.OP_SOLVE, 5, nb, batch, ld=ld), 8)
+                                    // 8, dtype=torch.float64, device="cuda")))
+
+    def per_bucket():
+        for bt, batch, xb, ib, wsb in buckets:
+            bs.solve([bt[k] for k in ("e", "c", "d", "a", "b")], bt["y"], xb, batch=batch,
+                     info=ib, workspace=wsb)
+    ms_bucket = t_ms(per_bucket, reps)
+    pad_rows = sum(bt["y"].shape[0] * batch for bt, batch, *_ in buckets)
+    rows = int(sizes.sum())
+    del buckets, t
+    torch.cuda.empty_cache()
+    shapes = plan.variants()
+    return {
+        "systems": int(sizes.size), "rows": rows, "n_range": [int(sizes.min()), int(sizes.max())],
+        "groups": int(plan.info.groups), "group_padding_rows": int(plan.elems // 16 * 16 - rows),
+        "autotuner_ms": {f"M{m}xPW{pw}": v for (m, pw), v in zip(shapes, tune_ms)},
+        "chosen_shape": list(shapes[best]),
+        "varlen_eager_ms": ms_eager, "varlen_graph_ms": ms_graph,
+        "varlen_algorithmic_GBps": PD_BYTES_PER_ROW * rows / ms_graph / 1e6,
+        "per_octave_launches_ms": ms_bucket, "per_octave_buckets": len(edges) - 1,
+        "per_octave_padded_rows": int(pad_rows),
+        "speedup_graph_vs_per_octave": ms_bucket / ms_graph,
+        "info_ok": ok,
+    }, got, samples
 
 
 def warmstart_rows(N=4096, steps=200, train_steps=150, eval_every=5, hb_s=(3, 3), tol=1e-10,
@@ -520,7 +612,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path=TRAFFIC_FILE):
     f_scale = COPY_BYTES / (fetch_c * 1024.0)
     w_scale = COPY_BYTES / (write_c * 1024.0)
     hbm = fetch_k * 1024.0 * f_scale + write_k * 1024.0 * w_scale
-    src_hash = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    src_hash = kernel_source_hash()
     alg = PD_BYTES_PER_ROW * N_ROWS * BATCH
     with open(out_path, "w") as fh:
         fh.write("# HBM traffic per launch of the split-row NPDM kernel on the n=2048 x 2048\n"
@@ -630,6 +722,9 @@ def main():
         log("learned warm start (4096 x 4096 ADI run)")
         line["warm_start"] = warmstart_rows()
         torch.cuda.empty_cache()
+        log("uneven batch (10 000 systems, n log-uniform in [64, 65536])")
+        line["uneven_batch"], vl_x, vl_samples = varlen_rows()
+        samples.update(vl_samples)
     if not args.no_cpu:
         log("timing the CPU oracle")
         line["cpu_baseline"], refs = cpu_baseline(pd, samples)
@@ -638,6 +733,8 @@ def main():
             return float((np.abs(x - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
         line["parity_max_rel_err_sampled"] = rel(x_last, refs["timed"])
         if not args.no_rows:
+            line["uneven_batch"]["sampled_err_vs_oracle"] = max(
+                rel(xv, refs[k]) for k, xv in vl_x.items())
             for name, xsamp in prec_x.items():
                 ref = refs["prec_" + name]
                 for key, xv in xsamp.items():

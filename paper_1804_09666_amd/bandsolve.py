@@ -325,6 +325,8 @@ class Varlen:
         self.table = torch.from_numpy(table).to(device)
         self.elems = self.info.elems
         self.slots = self.info.groups * 16
+        self.slot_sizes = np.zeros(self.slots, dtype=np.int64)   # length of the system in each slot
+        self.slot_sizes[self.slot] = n
 
     def variants(self):
         lib = load()

@@ -175,6 +175,47 @@ def config2_sizes(count=10000, lo=64, hi=65536, seed=BASE_SEED + 2):
     return np.floor(np.exp(rng.uniform(math.log(lo), math.log(hi), count))).astype(np.int64)
 
 
+def dominant_groups(slot_sizes, seed=BASE_SEED + 2, device="cuda"):
+    """Diagonally dominant PD systems (off-diagonals U[-1,1], d = sum|off| +
+    U[1,2], x_true ~ U[-1,1], y = A x_true) in groups of 16: slot_sizes[16 g + l]
+    is the length of the system in lane l of group g (0 = empty); group g is
+    an [n_g][16] block (n_g = max of its lanes) and the blocks follow each
+    other.  Generated on `device` with a seeded torch generator; returns flat
+    float64 tensors e, c, d, a, b, y, x_true (positions of no system and slots
+    outside a matrix hold 0)."""
+    import torch
+    sn = torch.as_tensor(np.asarray(slot_sizes, dtype=np.int64), device=device)
+    groups = sn.numel() // 16
+    gn = sn.view(groups, 16).max(dim=1).values
+    elems = int(gn.sum()) * 16
+    gid = torch.repeat_interleave(torch.arange(groups, device=device), gn * 16)
+    goff = torch.cumsum(gn * 16, 0) - gn * 16
+    pos = torch.arange(elems, device=device)
+    row = (pos - goff[gid]) // 16
+    nl = sn[gid * 16 + pos % 16]
+    inside = row < nl
+    masks = {"e": inside & (row >= 2), "c": inside & (row >= 1),
+             "a": inside & (row <= nl - 2), "b": inside & (row <= nl - 3)}
+    gen = torch.Generator(device=device).manual_seed(int(seed))
+
+    def uni(lo, hi):
+        return torch.rand(elems, generator=gen, device=device, dtype=torch.float64) * (hi - lo) + lo
+    out = {}
+    offsum = torch.zeros(elems, device=device, dtype=torch.float64)
+    for k in ("e", "c", "a", "b"):
+        out[k] = uni(-1.0, 1.0) * masks[k]
+        offsum += out[k].abs()
+    out["d"] = (offsum + uni(1.0, 2.0)) * inside
+    x = uni(-1.0, 1.0) * inside
+    y = out["d"] * x
+    y[32:] += out["e"][32:] * x[:-32]
+    y[16:] += out["c"][16:] * x[:-16]
+    y[:-16] += out["a"][:-16] * x[16:]
+    y[:-32] += out["b"][:-32] * x[32:]
+    out["y"], out["x_true"] = y, x
+    return out
+
+
 def config3(nsys=256, n=1_000_000, r=4.0, seed=BASE_SEED + 3):
     """nsys PD lines of length n from smooth 1-D fields (second-order rows)."""
     return sweep_lines(smooth_lines(nsys, n, seed), r, 2)
