@@ -258,6 +258,26 @@ def other_rows(pd, td):
                       "info_ok": bool((info == 0).all())}
     del tds
 
+    # the sweep assembled inside the solver from the field: 8 B read + 8 B written per row
+    u0 = torch.from_numpy(wl.smooth_field(N_ROWS, wl.BASE_SEED + 1)).cuda()
+    us_ = [u0.clone() for _ in range(ROTATE)]
+    xa = torch.empty_like(u0)
+    for kind in (5, 3):
+        nb = bs.workspace_bytes(bs.OP_ADI, kind, N_ROWS, BATCH)
+        wsa = torch.zeros(max(nb, 8) // 8, dtype=torch.float64, device="cuda")
+        k[0] = 0
+
+        def adi():
+            v = us_[k[0] % ROTATE]
+            k[0] += 1
+            bs.solve_adi(v, R_ADI, xa, kind=kind, batch=BATCH, info=info, workspace=wsa)
+        ms = t_ms(adi, reps=20)
+        out["adi_fused_" + ("pd" if kind == 5 else "td")] = {
+            "us": ms * 1e3, "systems_per_s": BATCH / ms * 1e3,
+            "bytes_per_row": 16, "algorithmic_GBps": 16 * N_ROWS * BATCH / ms / 1e6,
+            "info_ok": bool((info == 0).all())}
+    del us_, xa, u0
+
     t = to_dev(pd)
     # MNPDM: outer diagonals given as the two entries per system (rows 0, n-1)
     rows = np.full((2, BATCH), -1, dtype=np.int32)

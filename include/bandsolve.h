@@ -84,7 +84,8 @@ enum bs_op_code {
   BS_OP_SOLVE_FACTORED = 2, /* band_solve with factors from band_factor    */
   BS_OP_MNPDM = 3,        /* band_solve_mnpdm                              */
   BS_OP_SIP = 4,          /* sip_solve                                     */
-  BS_OP_REFINE = 5        /* band_solve_refine (dtype BS_F64)              */
+  BS_OP_REFINE = 5,       /* band_solve_refine (dtype BS_F64)              */
+  BS_OP_ADI = 6           /* band_solve_adi (dtype BS_F64)                 */
 };
 
 /* Human-readable name of a status code (static string). */
@@ -166,6 +167,27 @@ int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
                    int64_t ld, const void* const diags[5], const void* factors,
                    const void* rhs, void* x, int32_t* info, void* workspace,
                    size_t ws_bytes, void* stream);
+
+/* One ADI sweep assembled inside the solver: for every line s (column s of
+ * the batch-interleaved [n, ld] input v, the field the sweep starts from),
+ * solve (I - tau L(k(v))) w = v for u_t = (k(u) u_x)_x, k(u) = 1 + u^2 (the
+ * nonlinear parabolic problem of Sec. 1), r = tau / h^2:
+ *   interior rows  c_i = -r k_{i-1/2},  a_i = -r k_{i+1/2},
+ *                  d_i = 1 + r (k_{i-1/2} + k_{i+1/2}),  rhs_i = v_i,
+ *                  k_{i+1/2} = (k(v_i) + k(v_{i+1})) / 2;
+ *   zero-flux boundary rows, rhs 0: kind 3 (first order, tridiagonal) [1, -1]
+ *   and [-1, 1]; kind 5 (second order, pentadiagonal) [-3, 4, -1] and
+ *   [1, -4, 3].
+ * The coefficients are formed in registers in this order (each product and
+ * sum rounded on its own): the sweep reads v once and writes x once, 16 bytes
+ * per row instead of the 56 (PD) of band_solve on assembled diagonals, and
+ * the result is bitwise band_solve's on those diagonals.  Split-row kernels
+ * only: 8 <= n <= M*PW*TMAX of the first two variants of `kind`; FP64;
+ * x may alias v; workspace as bs_workspace_bytes(BS_OP_ADI, ...) (meeting
+ * counters: zero before first use, left zero). */
+int32_t band_solve_adi(int32_t kind, int64_t n, int64_t batch, int64_t ld, double r,
+                       const double* v, double* x, int32_t* info, void* workspace,
+                       size_t ws_bytes, void* stream);
 
 /* Mixed-precision NPDM / NTDM with iterative refinement.  The matrix and rhs
  * are FP64; the elimination reads an FP32 copy of them (half the bytes per

@@ -22,11 +22,12 @@ LIB_PATH = os.path.join(HERE, "libbandsolve.so")
 
 BS_OK, BS_EINVAL, BS_ELAUNCH, BS_EWORKSPACE, BS_ENODEV = range(5)
 BS_F64, BS_F32 = 0, 1
-OP_FACTOR, OP_SOLVE, OP_SOLVE_FACTORED, OP_MNPDM, OP_SIP, OP_REFINE = range(6)
+OP_FACTOR, OP_SOLVE, OP_SOLVE_FACTORED, OP_MNPDM, OP_SIP, OP_REFINE, OP_ADI = range(7)
 
 EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "bs_set_option",
             "bs_get_option", "bs_part_variant", "band_factor", "band_solve",
-            "band_solve_refine", "band_solve_mnpdm", "sip_solve", "bs_varlen_variants",
+            "band_solve_refine", "band_solve_adi", "band_solve_mnpdm", "sip_solve",
+            "bs_varlen_variants",
             "bs_varlen_variant_shape", "bs_varlen_layout", "bs_varlen_workspace_bytes",
             "band_solve_varlen", "bs_varlen_tune")
 OPT_DIRECT_PATH, OPT_PART_PD_VARIANT, OPT_PART_TD_VARIANT, OPT_SIP_PATH = range(4)
@@ -70,6 +71,7 @@ def load():
         "band_solve": (i32, [i32, i32, i64, i64, i64, vp5, vp, vp, vp, vp, vp, sz, vp]),
         "band_solve_refine": (i32, [i32, i64, i64, i64, vp5, vp, vp, ctypes.c_double, i32,
                                     vp, vp, vp, vp, sz, vp]),
+        "band_solve_adi": (i32, [i32, i64, i64, i64, ctypes.c_double, vp, vp, vp, vp, sz, vp]),
         "band_solve_mnpdm": (i32, [i32, i64, i64, i64, vp3, i32, vp, vp, vp, vp, vp,
                                    vp, vp, sz, vp]),
         "sip_solve": (i32, [i32, i64, i64, i64, vp5, vp, vp, vp, ctypes.c_double, i32,
@@ -240,6 +242,26 @@ def refine(diags, rhs, x=None, *, tol=1e-12, max_steps=8, kind=None, batch=None,
                                workspace.numel() * workspace.element_size(), _stream(stream))
     _raise(st, "band_solve_refine")
     return x, steps, relres, info
+
+
+def solve_adi(v, r, x=None, *, kind=5, batch=None, info=None, workspace=None, stream=None):
+    """One ADI sweep assembled in the kernel: lines are the columns of the
+    [n, ld] float64 field v (see band_solve_adi).  Returns (x, info)."""
+    lib = load()
+    n = v.shape[0]
+    ld = _check2d(v, "v", n, torch.float64)
+    batch = ld if batch is None else int(batch)
+    x = torch.empty_like(v) if x is None else x
+    _check2d(x, "x", n, torch.float64)
+    info = torch.empty(batch, dtype=torch.int32, device=v.device) if info is None else info
+    nbytes = workspace_bytes(OP_ADI, kind, n, batch, BS_F64, ld)
+    workspace = _ws(nbytes, v.device) if workspace is None else workspace
+    st = lib.band_solve_adi(kind, n, batch, ld, float(r), _ptr(v), _ptr(x), _ptr(info),
+                            _ptr(workspace),
+                            0 if workspace is None else workspace.numel() * workspace.element_size(),
+                            _stream(stream))
+    _raise(st, "band_solve_adi")
+    return x, info
 
 
 def solve_mnpdm(cda, outer_row, outer_e, outer_b, rhs, x=None, *, batch=None,

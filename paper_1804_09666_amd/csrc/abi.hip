@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <cmath>
 
 #include "bandsolve.h"
 #include "bs_internal.h"
@@ -224,6 +225,11 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
       const size_t tile = bs::sip_tile_workspace_bytes(n, batch, ld);
       return (size_t)(4 * plane) * 8 + (lane > tile ? lane : tile);
     }
+    case BS_OP_ADI: {
+      if (!kind_ok(kind) || dtype != BS_F64) return bad;
+      const int idx = g_direct_path.load() == 1 ? -1 : bs::part_adi_pick(kind, part_idx(kind), n, ld);
+      return idx >= 0 ? bs::part_workspace_bytes(kind, idx, n, batch) : bad;
+    }
     case BS_OP_REFINE:
       if (!kind_ok(kind) || !bs::direct_supported(kind, BS_F32, n, ld)) return bad;
       return bs::refine_workspace_bytes(kind, n, batch, ld);
@@ -270,6 +276,24 @@ int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
   if (!have_device()) return BS_ENODEV;
   return launched(bs::launch_direct(kind, dtype, n, batch, ld, diags, rhs, x, info,
                                     workspace, st));
+}
+
+int32_t band_solve_adi(int32_t kind, int64_t n, int64_t batch, int64_t ld, double r,
+                       const double* v, double* x, int32_t* info, void* workspace,
+                       size_t ws_bytes, void* stream) {
+  if (!kind_ok(kind) || !shape_ok(n, batch, ld) || !(r >= 0.0) || !std::isfinite(r))
+    return BS_EINVAL;
+  if (!array_ok(v, BS_F64) || !array_ok(x, BS_F64) || info == nullptr || !aligned(info, 4))
+    return BS_EINVAL;
+  const size_t need = bs_workspace_bytes(BS_OP_ADI, kind, BS_F64, n, batch, ld);
+  if (need == (size_t)-1) return BS_EINVAL;
+  if (ws_bytes < need) return BS_EWORKSPACE;
+  if (need > 0 && (workspace == nullptr || !aligned(workspace, 8))) return BS_EINVAL;
+  if (!have_device()) return BS_ENODEV;
+  const int idx = bs::part_adi_pick(kind, part_idx(kind), n, ld);
+  return launched(bs::launch_part_adi(kind, idx, n, batch, ld, r, v, x, info,
+                                      static_cast<double*>(workspace),
+                                      static_cast<hipStream_t>(stream)));
 }
 
 int32_t band_solve_refine(int32_t kind, int64_t n, int64_t batch, int64_t ld,

@@ -63,6 +63,12 @@ hipError_t launch_part_mnpdm(int idx, int64_t n, int64_t batch, int64_t ld,
                              const double* const cda[3], int32_t kmax, const int32_t* orow,
                              const double* oe, const double* ob, const double* y, double* x,
                              int32_t* info, double* ws, hipStream_t st);
+// The ADI sweep assembled inside the split kernels (first two variants):
+// the variant for (n, ld) or -1, and its launch.  ws as part_workspace_bytes.
+int part_adi_pick(int kind, int idx, int64_t n, int64_t ld);
+hipError_t launch_part_adi(int kind, int idx, int64_t n, int64_t batch, int64_t ld, double r,
+                           const double* v, double* x, int32_t* info, double* ws,
+                           hipStream_t st);
 // Any length: three launches (tile maps, per-system reduction, finish).
 bool long_supported(int64_t n, int64_t ld, int dtype);
 size_t long_workspace_bytes(int kind, int64_t n, int64_t batch);

@@ -40,14 +40,18 @@ using namespace split;
 // leave, so the counters are zero again after every completed call).
 // SPARSE: the outer diagonals come from an MNPDM list (absent entries are
 // zero, so every product with them is an exact zero).
-template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false>
+// ASM: the rows are assembled from the sweep input v (passed as Y) and r
+// instead of being loaded (the ADI sweep of the PDE, see assemble_chunk).
+template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false,
+          bool ASM = false>
 __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void part_kernel(
     int64_t n, int64_t batch, int64_t ld, const TIO* __restrict__ E,
     const TIO* __restrict__ C, const TIO* __restrict__ D,
     const TIO* __restrict__ A, const TIO* __restrict__ B,
     const TIO* __restrict__ Y, TIO* __restrict__ X,
     int32_t* __restrict__ info, double* __restrict__ xch,
-    unsigned* __restrict__ cnt, int T, const int32_t* __restrict__ skip, Outer ol) {
+    unsigned* __restrict__ cnt, int T, const int32_t* __restrict__ skip, Outer ol,
+    double rcoef) {
   constexpr int NB = KIND == 5 ? 2 : 1;
   constexpr int RS = kRecSz<NB>;
   constexpr int RT = M * PW;
@@ -83,7 +87,10 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
 
   // ---- 1. load the chunk and eliminate it locally -------------------------
   double c[M], d[M], a[M], y[M], e[M], b[M];
-  load_chunk<KIND, M, TIO, !SPARSE>(n, ld, s, live, r0, 0, E, C, D, A, B, Y, e, c, d, a, b, y);
+  if constexpr (ASM)
+    assemble_chunk<KIND, M>(n, ld, s, live, r0, Y, rcoef, e, c, d, a, b, y);
+  else
+    load_chunk<KIND, M, TIO, !SPARSE>(n, ld, s, live, r0, 0, E, C, D, A, B, Y, e, c, d, a, b, y);
   bool list_bad = false;
   if constexpr (SPARSE) {
     // every lane of the system checks the whole list (strictly ascending
@@ -386,19 +393,22 @@ constexpr Variant kVariants[] = {
 // Shape of the long-system path (both kinds).
 constexpr int kLongM = 32, kLongPW = 16, kLongG = 16;
 
-template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false>
+template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false,
+          bool ASM = false>
 hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, const void* const* dg,
                       const void* y, void* x, int32_t* info, double* ws, hipStream_t st,
-                      const int32_t* skip, Outer ol = Outer{0, nullptr, nullptr, nullptr}) {
+                      const int32_t* skip, Outer ol = Outer{0, nullptr, nullptr, nullptr},
+                      double rcoef = 0.0) {
   constexpr int RT = M * PW;
   const int T = (int)((n + RT - 1) / RT);
   const int64_t groups = (batch + G - 1) / G;
   unsigned* cnt = (T > 1) ? reinterpret_cast<unsigned*>(ws) : nullptr;
   double* xch = (T > 1) ? ws + (2 * groups + 1) / 2 + 1 : nullptr;
-  hipLaunchKernelGGL((part_kernel<TIO, KIND, M, PW, G, TMAX, WPE, SPARSE>),
+  hipLaunchKernelGGL((part_kernel<TIO, KIND, M, PW, G, TMAX, WPE, SPARSE, ASM>),
                      dim3((unsigned)(groups * T)), dim3(G * PW), 0, st, n, batch, ld,
                      (const TIO*)dg[0], (const TIO*)dg[1], (const TIO*)dg[2], (const TIO*)dg[3],
-                     (const TIO*)dg[4], (const TIO*)y, (TIO*)x, info, xch, cnt, T, skip, ol);
+                     (const TIO*)dg[4], (const TIO*)y, (TIO*)x, info, xch, cnt, T, skip, ol,
+                     rcoef);
   return hipGetLastError();
 }
 
@@ -534,6 +544,31 @@ hipError_t launch_part_mnpdm(int idx, int64_t n, int64_t batch, int64_t ld,
   if (idx == 1)
     return launch_cfg<double, 5, 32, 16, 16, 8, 1, true>(n, batch, ld, dg, y, x, info, ws, st,
                                                          nullptr, ol);
+  return hipErrorInvalidValue;
+}
+
+// Assembled ADI sweep on the split kernels: the first two variants of `kind`.
+int part_adi_pick(int kind, int idx, int64_t n, int64_t ld) {
+  const int k = part_pick(kind, idx, n, ld, 0);
+  if (k == 0 || k == 1) return k;
+  for (int q = 0; q < 2; ++q)
+    if (covers(find_variant(kind, q), n, ld, 0)) return q;
+  return -1;
+}
+
+hipError_t launch_part_adi(int kind, int idx, int64_t n, int64_t batch, int64_t ld, double r,
+                           const double* v, double* x, int32_t* info, double* ws,
+                           hipStream_t st) {
+  const void* dg[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  const Outer none{0, nullptr, nullptr, nullptr};
+#define BS_PA(K, TT)                                                                        \
+  return launch_cfg<double, K, 32, 16, 16, TT, 1, false, true>(n, batch, ld, dg, v, x, info, \
+                                                               ws, st, nullptr, none, r);
+  if (kind == 5 && idx == 0) { BS_PA(5, 4) }
+  if (kind == 5 && idx == 1) { BS_PA(5, 8) }
+  if (kind == 3 && idx == 0) { BS_PA(3, 4) }
+  if (kind == 3 && idx == 1) { BS_PA(3, 8) }
+#undef BS_PA
   return hipErrorInvalidValue;
 }
 

@@ -450,6 +450,69 @@ __device__ inline void load_chunk(int64_t n, int64_t ld, int64_t s, bool live, i
   }
 }
 
+// The rows of a chunk assembled from the sweep input v instead of loaded: one
+// implicit sweep (I - tau L(k(v))) w = v of u_t = (k(u) u_x)_x, k = 1 + u^2,
+// with r = tau / h^2 and k_{i+1/2} = (k(v_i) + k(v_{i+1})) / 2:
+//   c_i = -r k_{i-1/2},  a_i = -r k_{i+1/2},  d_i = 1 + r (k_{i-1/2} + k_{i+1/2}),
+//   rhs_i = v_i  (interior rows),
+// and zero-flux boundary rows with rhs 0: first order (KIND 3) [1, -1] and
+// [-1, 1]; second order (KIND 5) [-3, 4, -1] and [1, -4, 3].  Every product
+// and sum is rounded on its own in this order, so the coefficients are those
+// of the host generator of the same sweep to the last bit.  Reads v at rows
+// r0 - 1 .. r0 + M only: 8 bytes per row instead of 48.
+template <int KIND, int M>
+__device__ inline void assemble_chunk(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
+                                      const double* __restrict__ V, double r, double (&e)[M],
+                                      double (&c)[M], double (&d)[M], double (&a)[M],
+                                      double (&b)[M], double (&y)[M]) {
+#pragma clang fp contract(off)
+  double vv[M + 2];
+#pragma unroll
+  for (int q = 0; q < M + 2; ++q) {
+    const int64_t i = r0 - 1 + q;
+    vv[q] = (live && i >= 0 && i < n)
+                ? __builtin_nontemporal_load(V + (i * ld + s))
+                : 0.0;
+  }
+  const double mr = -r;
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    const int64_t i = r0 + q;
+    e[q] = c[q] = a[q] = b[q] = y[q] = 0.0;
+    d[q] = 1.0;  // identity rows past n
+    if (!(live && i < n)) continue;
+    if (i == 0) {
+      if (KIND == 5) {
+        d[q] = -3.0;
+        a[q] = 4.0;
+        b[q] = -1.0;
+      } else {
+        d[q] = 1.0;
+        a[q] = -1.0;
+      }
+    } else if (i == n - 1) {
+      if (KIND == 5) {
+        e[q] = 1.0;
+        c[q] = -4.0;
+        d[q] = 3.0;
+      } else {
+        c[q] = -1.0;
+        d[q] = 1.0;
+      }
+    } else {
+      const double km = 1.0 + vv[q] * vv[q];
+      const double k0 = 1.0 + vv[q + 1] * vv[q + 1];
+      const double kp = 1.0 + vv[q + 2] * vv[q + 2];
+      const double hl = 0.5 * (km + k0);
+      const double hr = 0.5 * (k0 + kp);
+      c[q] = mr * hl;
+      a[q] = mr * hr;
+      d[q] = 1.0 + r * (hl + hr);
+      y[q] = vv[q + 1];
+    }
+  }
+}
+
 // The chunk's affine map: tip rows of p, V, W.
 template <int NB, int M>
 __device__ inline Map<NB> chunk_map(const double (&p)[M], const double (&v)[NB][M],
