@@ -5,8 +5,9 @@
 // One GEMM kernel serves every product, C = A B^T with both operands K-
 // contiguous (the layout of X W^T with W stored [out, in]); the backward pass
 // brings its operands into that layout with a tiled transpose.  A block
-// computes a 128 x 128 tile of C with four waves of 64 x 64 (2 x 2 MFMA
-// 32 x 32 tiles); K advances in steps of 32 staged through LDS.  Lane layout
+// computes a tile of C with four waves (2 x 2), each owning TI x TJ MFMA
+// 32 x 32 tiles; K advances in slices of 128 bytes per row, double-buffered
+// through LDS (the next slice is fetched while the matrix cores work).  Lane layout
 // of v_mfma_f32_32x32x16_bf16 / v_mfma_f32_32x32x2_f32 (checked on the
 // device): lane l holds A row (l mod 32) and B column (l mod 32) at
 // k = (l div 32) * KS/2 .. + KS/2 - 1; accumulator v of lane l is
@@ -27,7 +28,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBM = 128, kBN = 128, kBK = 32, kThreads = 256;
+constexpr int kThreads = 256;
 
 template <typename T>
 struct Mfma;
@@ -50,7 +51,11 @@ struct Mfma<float> {
 
 typedef uint32_t Vec16 __attribute__((ext_vector_type(4)));  // one 16-byte chunk
 
-template <typename T>
+// TI x TJ MFMA tiles of 32 x 32 per wave, 2 x 2 waves per block: a block
+// computes a (64 TI) x (64 TJ) tile of C.  Large wave tiles keep the LDS
+// traffic per matrix-core instruction low (each fragment read from LDS feeds
+// TJ or TI instructions).
+template <typename T, int TI, int TJ>
 __global__ __launch_bounds__(kThreads) void gemm_nt_kernel(int64_t M, int64_t N, int64_t K,
                                                            const T* __restrict__ A,
                                                            const T* __restrict__ B,
@@ -59,60 +64,93 @@ __global__ __launch_bounds__(kThreads) void gemm_nt_kernel(int64_t M, int64_t N,
                                                            float* __restrict__ C32,
                                                            T* __restrict__ CT) {
   typedef Mfma<T> MF;
-  constexpr int VEC = 16 / sizeof(T);  // elements per 16-byte chunk
-  constexpr int LDR = kBK + VEC;       // LDS row pitch: 16 bytes of padding
-  constexpr int CPR = kBK / VEC;       // chunks per tile row
-  __shared__ __attribute__((aligned(16))) T sA[kBM * LDR];
-  __shared__ __attribute__((aligned(16))) T sB[kBN * LDR];
+  constexpr int WM = 32 * TI, WN = 32 * TJ;   // wave tile
+  constexpr int BM = 2 * WM, BN = 2 * WN;     // block tile
+  constexpr int VEC = 16 / sizeof(T);         // elements per 16-byte chunk
+  constexpr int BK = 128 / sizeof(T);         // K per stage: 128 bytes of every row
+  constexpr int LDR = BK + VEC;               // LDS row pitch: 16 bytes of padding
+  constexpr int CPR = BK / VEC;               // chunks per tile row (8)
+  constexpr int CPA = BM * CPR / kThreads;    // chunks per thread, A
+  constexpr int CPB = BN * CPR / kThreads;    // chunks per thread, B
+  static_assert(CPA >= 1 && CPB >= 1, "tile");
+  // two stages: the next K slice is fetched into registers while the matrix
+  // cores work on the current one, then stored to the other stage
+  __shared__ __attribute__((aligned(16))) T sA[2][BM * LDR];
+  __shared__ __attribute__((aligned(16))) T sB[2][BN * LDR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  const int64_t m0 = (int64_t)blockIdx.y * kBM, n0 = (int64_t)blockIdx.x * kBN;
-  f32x16 acc[2][2];
+  const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
+  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  f32x16 acc[TI][TJ];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TJ; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
   const int hi = lane >> 5, lo = lane & 31;
 
-  for (int64_t k0 = 0; k0 < K; k0 += kBK) {
-    // ---- global -> LDS (zero outside the matrices; K % VEC == 0) --------
+  Vec16 ra[CPA], rb[CPB];
+  auto fetch = [&](int64_t k0) {  // zero outside the matrices; K % VEC == 0
 #pragma unroll
-    for (int q = 0; q < kBM * CPR / kThreads; ++q) {
+    for (int q = 0; q < CPA; ++q) {
       const int c = tid + q * kThreads;
       const int r = c / CPR, kc = (c % CPR) * VEC;
       const int64_t k = k0 + kc;
-      Vec16 va = {0u, 0u, 0u, 0u}, vb = {0u, 0u, 0u, 0u};
-      if (m0 + r < M && k < K) va = *reinterpret_cast<const Vec16*>(A + (m0 + r) * K + k);
-      if (n0 + r < N && k < K) vb = *reinterpret_cast<const Vec16*>(B + (n0 + r) * K + k);
-      *reinterpret_cast<Vec16*>(sA + r * LDR + kc) = va;
-      *reinterpret_cast<Vec16*>(sB + r * LDR + kc) = vb;
+      ra[q] = Vec16{0u, 0u, 0u, 0u};
+      if (m0 + r < M && k < K) ra[q] = *reinterpret_cast<const Vec16*>(A + (m0 + r) * K + k);
     }
-    __syncthreads();
-    // ---- matrix cores -----------------------------------------------------
 #pragma unroll
-    for (int kk = 0; kk < kBK; kk += MF::KS) {
-      typename MF::Frag fa[2], fb[2];
+    for (int q = 0; q < CPB; ++q) {
+      const int c = tid + q * kThreads;
+      const int r = c / CPR, kc = (c % CPR) * VEC;
+      const int64_t k = k0 + kc;
+      rb[q] = Vec16{0u, 0u, 0u, 0u};
+      if (n0 + r < N && k < K) rb[q] = *reinterpret_cast<const Vec16*>(B + (n0 + r) * K + k);
+    }
+  };
+  auto stash = [&](int st) {
+#pragma unroll
+    for (int q = 0; q < CPA; ++q) {
+      const int c = tid + q * kThreads;
+      *reinterpret_cast<Vec16*>(&sA[st][(c / CPR) * LDR + (c % CPR) * VEC]) = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < CPB; ++q) {
+      const int c = tid + q * kThreads;
+      *reinterpret_cast<Vec16*>(&sB[st][(c / CPR) * LDR + (c % CPR) * VEC]) = rb[q];
+    }
+  };
+  const int64_t nk = (K + BK - 1) / BK;
+  fetch(0);
+  stash(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int st = (int)(kt & 1);
+    if (kt + 1 < nk) fetch((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += MF::KS) {
+      typename MF::Frag fa[TI], fb[TJ];
       const int ko = kk + hi * (MF::KS / 2);
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        fa[t] = *reinterpret_cast<const typename MF::Frag*>(sA + (wm + 32 * t + lo) * LDR + ko);
-        fb[t] = *reinterpret_cast<const typename MF::Frag*>(sB + (wn + 32 * t + lo) * LDR + ko);
-      }
+      for (int t = 0; t < TI; ++t)
+        fa[t] = *reinterpret_cast<const typename MF::Frag*>(&sA[st][(wm + 32 * t + lo) * LDR + ko]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int t = 0; t < TJ; ++t)
+        fb[t] = *reinterpret_cast<const typename MF::Frag*>(&sB[st][(wn + 32 * t + lo) * LDR + ko]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = MF::run(fa[i], fb[j], acc[i][j]);
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = MF::run(fa[i], fb[j], acc[i][j]);
     }
+    if (kt + 1 < nk) stash(st ^ 1);
     __syncthreads();
   }
 
   // ---- epilogue: bias, ReLU, mask; consecutive lanes write consecutive n --
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TI; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < TJ; ++j) {
       const int64_t col = n0 + wn + 32 * j + lo;
       if (col >= N) continue;
       const float bv = bias ? bias[col] : 0.0f;
@@ -333,14 +371,25 @@ bool al16(const void* p) { return p != nullptr && (reinterpret_cast<uintptr_t>(p
 size_t esz(int32_t dtype) { return dtype == WS_BF16 ? 2 : 4; }
 bool dtype_ok(int32_t dtype) { return dtype == WS_BF16 || dtype == WS_F32; }
 
-template <typename T>
-hipError_t gemm(int64_t M, int64_t N, int64_t K, const void* A, const void* B, const float* bias,
-                int relu, const void* mask, float* C32, void* CT, hipStream_t st) {
-  const dim3 grid((unsigned)((N + kBN - 1) / kBN), (unsigned)((M + kBM - 1) / kBM));
-  hipLaunchKernelGGL(gemm_nt_kernel<T>, grid, dim3(kThreads), 0, st, M, N, K,
+template <typename T, int TI, int TJ>
+hipError_t gemm_tiles(int64_t M, int64_t N, int64_t K, const void* A, const void* B,
+                      const float* bias, int relu, const void* mask, float* C32, void* CT,
+                      hipStream_t st) {
+  constexpr int BM = 64 * TI, BN = 64 * TJ;
+  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
+  hipLaunchKernelGGL((gemm_nt_kernel<T, TI, TJ>), grid, dim3(kThreads), 0, st, M, N, K,
                      static_cast<const T*>(A), static_cast<const T*>(B), bias, relu,
                      static_cast<const T*>(mask), C32, static_cast<T*>(CT));
   return hipGetLastError();
+}
+
+// 128 x 128 blocks (2 x 2 MFMA tiles per wave).  Measured on the 262144 x 512
+// x 512 layer: 256 x 128 blocks (4 x 2 per wave, one block per CU) ran 1.3x
+// slower than these, which keep two blocks per CU.
+template <typename T>
+hipError_t gemm(int64_t M, int64_t N, int64_t K, const void* A, const void* B, const float* bias,
+                int relu, const void* mask, float* C32, void* CT, hipStream_t st) {
+  return gemm_tiles<T, 2, 2>(M, N, K, A, B, bias, relu, mask, C32, CT, st);
 }
 
 template <typename T>
@@ -485,7 +534,7 @@ int32_t ws_gemm_nt(int32_t dtype, int64_t M, int64_t N, int64_t K, const void* A
                    void* stream) {
   if (!dtype_ok(dtype) || M < 1 || N < 1 || K < 1) return BS_EINVAL;
   if (K % (int64_t)(16 / esz(dtype)) != 0) return BS_EINVAL;
-  if (M > (int64_t(1) << 31) || N > (int64_t(1) << 31) || (M + kBM - 1) / kBM > 65535)
+  if (M > (int64_t(1) << 31) || N > (int64_t(1) << 31) || (M + 127) / 128 > 65535)
     return BS_EINVAL;
   if (!al16(A) || !al16(B) || (C32 == nullptr && CT == nullptr)) return BS_EINVAL;
   const hipStream_t st = static_cast<hipStream_t>(stream);
@@ -510,7 +559,7 @@ int32_t ws_forward(int32_t dtype, int64_t P, const void* X, const float* params3
                    const void* paramsT, float* Y, void* workspace, size_t ws_bytes,
                    void* stream) {
   const size_t need = ws_workspace_bytes(WS_OP_FORWARD, dtype, P);
-  if (need == (size_t)-1 || (P + kBM - 1) / kBM > 65535) return BS_EINVAL;
+  if (need == (size_t)-1 || (P + 127) / 128 > 65535) return BS_EINVAL;
   if (!al16(X) || !al16(params32) || !al16(paramsT) || !al16(Y) || !al16(workspace))
     return BS_EINVAL;
   if (ws_bytes < need) return BS_EWORKSPACE;
@@ -525,7 +574,7 @@ int32_t ws_backward(int32_t dtype, int64_t P, const void* X, const float* params
                     const void* paramsT, const float* dY, float* grads, void* workspace,
                     size_t ws_bytes, void* stream) {
   const size_t need = ws_workspace_bytes(WS_OP_TRAIN, dtype, P);
-  if (need == (size_t)-1 || P % 8 != 0 || (P + kBM - 1) / kBM > 65535) return BS_EINVAL;
+  if (need == (size_t)-1 || P % 8 != 0 || (P + 127) / 128 > 65535) return BS_EINVAL;
   if (!al16(X) || !al16(params32) || !al16(paramsT) || !al16(dY) || !al16(grads) ||
       !al16(workspace))
     return BS_EINVAL;
