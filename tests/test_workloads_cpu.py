@@ -55,3 +55,34 @@ def test_uneven_batch_layout_host():
         assert plan.info.tiles[v] == sum(-(-x // (M * PW)) for x in gn)
     with pytest.raises(bs.BandSolveError):
         bs.Varlen(np.array([100, 7]), device="cpu")
+
+
+def test_uneven_batch_generator_structure():
+    """The device generator of uneven batches, run on the CPU: nothing outside
+    a matrix, strict diagonal dominance, and y = A x_true row by row (dense
+    products of each extracted system)."""
+    import torch
+    from paper_1804_09666_amd import workloads as wl
+    sizes = [40, 9, 0, 23] + [0] * 12 + [12, 12, 12, 8] + [0] * 12
+    t = {k: v.numpy() for k, v in wl.dominant_groups(sizes, seed=5, device="cpu").items()}
+    gn = [max(sizes[16 * g:16 * g + 16]) for g in range(2)]
+    goff = [0, 16 * gn[0]]
+    assert t["d"].size == 16 * sum(gn)
+    covered = np.zeros(t["d"].size, bool)
+    for slot, m in enumerate(sizes):
+        if m == 0:
+            continue
+        g, lane = divmod(slot, 16)
+        idx = goff[g] + lane + 16 * np.arange(m)
+        covered[idx] = True
+        A = np.zeros((m, m))
+        for off, k in ((-2, "e"), (-1, "c"), (0, "d"), (1, "a"), (2, "b")):
+            v = t[k][idx]
+            rows = np.arange(max(0, -off), min(m, m - off))
+            assert not v[np.setdiff1d(np.arange(m), rows)].any()   # slots outside the matrix are 0
+            A[rows, rows + off] = v[rows]
+        off_sum = np.abs(A).sum(1) - np.abs(np.diag(A))
+        assert (np.diag(A) >= off_sum + 1.0).all()
+        assert np.allclose(A @ t["x_true"][idx], t["y"][idx], rtol=0, atol=1e-13)
+    for k in ("e", "c", "d", "a", "b", "y", "x_true"):
+        assert not t[k][~covered].any()                              # padding holds 0
