@@ -101,9 +101,10 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
                           int64_t batch, int64_t ld);
 
 /* Process-wide tuning options (not per-call state; read at every call).
- *   BS_OPT_DIRECT_PATH     fused band_solve kernel: 0 and 2 rows of a
+ *   BS_OPT_DIRECT_PATH     fused band_solve kernel and the ILU(0) of
+ *                          band_factor and sip_solve: 0 and 2 rows of a
  *                          system split over lanes (default; one lane per
- *                          system for n < 8), 1 one lane per system (FP64)
+ *                          system for small n), 1 one lane per system
  *   BS_OPT_PART_PD_VARIANT index of the split-row PD kernel variant
  *   BS_OPT_PART_TD_VARIANT index of the split-row TD kernel variant
  *   BS_OPT_SIP_PATH        sip_solve kernel: 0 and 2 rows of a system split
@@ -137,7 +138,16 @@ int32_t bs_part_variant(int32_t kind, int32_t index, int32_t shape[4]);
  * [l1 | u0], each n*ld elements in the batch-interleaved layout (array k at
  * factors + k*n*ld).  Entries outside the band (l2 of rows 0,1, l1 of row 0,
  * u1 of row n-1) are written as 0.  info[s]: 0 or i+1 for the first bad u0_i.
- * dtype must be BS_F64. */
+ * dtype must be BS_F64.
+ * When the batch alone cannot fill the GPU, the rows of each system are cut
+ * into chunks that start a few dozen rows early, as if the matrix began
+ * there (the recurrence forgets its start geometrically on diagonally
+ * dominant systems); a second pass recomputes the first two rows of every
+ * chunk from the stored rows before it and compares bit patterns, and
+ * factorizes a system again sequentially if any differs.  Factors and info
+ * are therefore always the sequential recurrence's to the last bit; only the
+ * time depends on the matrix.  BS_OPT_DIRECT_PATH = 1 keeps one lane per
+ * system. */
 int32_t band_factor(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
                     int64_t ld, const void* const diags[5], void* factors,
                     int32_t* info, void* stream);
@@ -155,7 +165,11 @@ int32_t band_factor(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
  *   per-system reduction, finish) for longer systems.  dtype BS_F32 needs
  *   this split path (n >= 8).
  * factors != NULL: substitution with the factors of band_factor (same kind
- *   and layout): L z = rhs, U x = z.  info[s] is set to 0.
+ *   and layout): L z = rhs, U x = z.  info[s] is set to 0.  Where the batch
+ *   is small the rows of each sweep are split over lanes as in band_factor
+ *   (chunks started early, a bitwise proof at every chunk boundary, a
+ *   sequential redo where it fails: x is the sequential sweeps' to the last
+ *   bit); z then goes through the workspace (n * ceil(batch/64)*64 doubles).
  * workspace / ws_bytes: as bs_workspace_bytes(BS_OP_SOLVE or
  *   BS_OP_SOLVE_FACTORED, ...); may be NULL / 0 when that is 0.  When the
  *   rows of a system span several blocks, the blocks meet at counters in the

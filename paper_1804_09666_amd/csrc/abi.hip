@@ -212,7 +212,8 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
       if (!kind_ok(kind) || !bs::direct_supported(kind, dtype, n, ld)) return bad;
       return bs::direct_ws_bytes(kind, dtype, n, batch, ld);
     case BS_OP_SOLVE_FACTORED:
-      return kind_ok(kind) ? 0 : bad;
+      if (!kind_ok(kind) || dtype != BS_F64) return bad;
+      return g_direct_path.load() == 1 ? 0 : bs::subst_workspace_bytes(n, batch);
     case BS_OP_MNPDM: {
       const int idx = mnpdm_part_idx(n, ld);
       return idx >= 0 ? bs::part_workspace_bytes(5, idx, n, batch) : (size_t)(2 * plane) * 8;
@@ -246,9 +247,12 @@ int32_t band_factor(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
       info == nullptr || !aligned(info, 4))
     return BS_EINVAL;
   if (!have_device()) return BS_ENODEV;
-  return launched(bs::launch_factor_lane(kind, n, batch, ld, as_diags(kind, diags),
-                                         static_cast<double*>(factors), ld, info,
-                                         static_cast<hipStream_t>(stream)));
+  const bs::Diags A = as_diags(kind, diags);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  double* F = static_cast<double*>(factors);
+  return launched(g_direct_path.load() == 1
+                      ? bs::launch_factor_lane(kind, n, batch, ld, A, F, ld, info, st)
+                      : bs::launch_factor(kind, n, batch, ld, A, F, ld, info, st));
 }
 
 int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
@@ -263,11 +267,17 @@ int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
   const hipStream_t st = static_cast<hipStream_t>(stream);
   if (factors != nullptr) {
     if (dtype != BS_F64 || !array_ok(factors, dtype)) return BS_EINVAL;
+    const size_t need = bs_workspace_bytes(BS_OP_SOLVE_FACTORED, kind, dtype, n, batch, ld);
+    if (ws_bytes < need) return BS_EWORKSPACE;
+    if (need > 0 && (workspace == nullptr || !aligned(workspace, 8))) return BS_EINVAL;
     if (!have_device()) return BS_ENODEV;
-    return launched(bs::launch_subst_lane(kind, n, batch, ld, as_diags(kind, diags),
-                                          static_cast<const double*>(factors),
-                                          static_cast<const double*>(rhs),
-                                          static_cast<double*>(x), info, st));
+    const bs::Diags A = as_diags(kind, diags);
+    const double* F = static_cast<const double*>(factors);
+    const double* Y = static_cast<const double*>(rhs);
+    double* X = static_cast<double*>(x);
+    return launched(need == 0 ? bs::launch_subst_lane(kind, n, batch, ld, A, F, Y, X, info, st)
+                              : bs::launch_subst(kind, n, batch, ld, A, F, Y, X, info,
+                                                 static_cast<double*>(workspace), st));
   }
   const size_t need = bs_workspace_bytes(BS_OP_SOLVE, kind, dtype, n, batch, ld);
   if (need == (size_t)-1) return BS_EINVAL;  // no kernel for this dtype and shape
@@ -395,7 +405,10 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
   if (own) {
     // ILU(0) into the first 4 workspace planes (pitch lw)
     fld = lw;
-    if (bs::launch_factor_lane(5, n, batch, ld, A, ws, fld, info, st) != hipSuccess)
+    const hipError_t fe = g_direct_path.load() == 1
+                              ? bs::launch_factor_lane(5, n, batch, ld, A, ws, fld, info, st)
+                              : bs::launch_factor(5, n, batch, ld, A, ws, fld, info, st);
+    if (fe != hipSuccess)
       return BS_ELAUNCH;
     F = ws;
   }

@@ -31,13 +31,25 @@ hipError_t launch_mnpdm_lane(int64_t n, int64_t batch, int64_t ld, Diags A,
                              const double* oe, const double* ob,
                              const double* y, double* x, int32_t* info,
                              double* ws, hipStream_t st);
-// factors are written with pitch fld (array k at factors + k*n*fld)
+// factors are written with pitch fld (array k at factors + k*n*fld).
+// launch_factor splits the rows of a system over lanes where the batch is
+// too small to fill the GPU (bitwise the same factors and info);
+// launch_factor_lane keeps one lane per system.
+hipError_t launch_factor(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
+                         double* factors, int64_t fld, int32_t* info, hipStream_t st);
 hipError_t launch_factor_lane(int kind, int64_t n, int64_t batch, int64_t ld,
                               Diags A, double* factors, int64_t fld,
                               int32_t* info, hipStream_t st);
 hipError_t launch_subst_lane(int kind, int64_t n, int64_t batch, int64_t ld,
                              Diags A, const double* factors, const double* y,
                              double* x, int32_t* info, hipStream_t st);
+// Substitution with the rows split over lanes where the batch is small
+// (bitwise the one-lane result); z goes through ws, subst_workspace_bytes
+// long (0: one lane per system, ws unused).
+size_t subst_workspace_bytes(int64_t n, int64_t batch);
+hipError_t launch_subst(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
+                        const double* factors, const double* y, double* x, int32_t* info,
+                        double* ws, hipStream_t st);
 
 // ---- direct solvers, rows of a system split over lanes (direct_part.hip) --
 // Variant idx of a kind: M rows per lane, PW lanes per system in a block

@@ -265,6 +265,93 @@ __global__ __launch_bounds__(kLaneBlock) void mnpdm_lane_kernel(
 // Band Doolittle ILU(0): l2_i = e_i / u0_{i-2};  l1_i = (c_i - l2_i u1_{i-2})
 // / u0_{i-1};  u0_i = (d_i - l2_i u2_{i-2}) - l1_i u1_{i-1};
 // u1_i = a_i - l1_i u2_{i-1};  u2_i = b_i.
+// The carried state is (u0, u1, u2) of the two previous rows.
+struct FactorState {
+  double u0m1 = 0, u0m2 = 0, u1m1 = 0, u1m2 = 0, u2m1 = 0, u2m2 = 0;
+};
+
+// Row i of the recurrence with the rows before `lo` taken as absent (lo = 0:
+// the recurrence itself; the corner slots e_0, e_1, c_0, a_{n-1}, b_{n-2},
+// b_{n-1} are never used).  Returns u0 (the pivot) and advances the state.
+template <int KIND>
+__device__ inline void factor_row(int64_t i, int64_t lo, int64_t n, double e, double c, double d,
+                                  double a, double b, FactorState& st, double& l2, double& l1,
+                                  double& u0, double& u1) {
+  const int64_t li = i - lo;
+  double u2 = 0.0;
+  l2 = 0.0;
+  l1 = 0.0;
+  u1 = 0.0;
+  if (KIND == 5 && li >= 2) l2 = e / st.u0m2;
+  if (li == 1) l1 = c / st.u0m1;
+  if (li >= 2) l1 = (KIND == 5) ? (c - l2 * st.u1m2) / st.u0m1 : c / st.u0m1;
+  if (li == 0)
+    u0 = d;
+  else if (li == 1 || KIND == 3)
+    u0 = d - l1 * st.u1m1;
+  else
+    u0 = (d - l2 * st.u2m2) - l1 * st.u1m1;
+  if (i <= n - 2) u1 = (li == 0 || KIND == 3) ? a : a - l1 * st.u2m1;
+  if (KIND == 5 && i <= n - 3) u2 = b;
+  st.u0m2 = st.u0m1; st.u0m1 = u0;
+  st.u1m2 = st.u1m1; st.u1m1 = u1;
+  st.u2m2 = st.u2m1; st.u2m1 = u2;
+}
+
+struct FactorPlanes {
+  double* l2;  // KIND 5 only
+  double* l1;
+  double* u0;
+  double* u1;  // KIND 5 only
+};
+
+template <int KIND>
+__device__ inline FactorPlanes factor_planes(double* F, int64_t n, int64_t fld) {
+  const int64_t plane = n * fld;
+  if (KIND == 5) return {F, F + plane, F + 2 * plane, F + 3 * plane};
+  return {nullptr, F, F + plane, nullptr};
+}
+
+// Rows [lo, hi) of system s, factors written for rows >= w0; returns the
+// first row >= w0 whose pivot is zero or not finite (-1 if none).  The sweep
+// runs on past a bad pivot (the later factors are unspecified).
+template <int KIND>
+__device__ inline int64_t factor_rows(int64_t n, int64_t ld, int64_t s, int64_t lo, int64_t w0,
+                                      int64_t hi, const double* __restrict__ E,
+                                      const double* __restrict__ C, const double* __restrict__ D,
+                                      const double* __restrict__ A, const double* __restrict__ B,
+                                      FactorPlanes P, int64_t fld) {
+  double re[kPF], rc[kPF], rd[kPF], ra[kPF], rb[kPF];
+  auto fetch = [&](int q, int64_t k) {
+    const int64_t o = (lo + k) * ld + s;
+    if (KIND == 5) re[q] = E[o];
+    rc[q] = C[o];
+    rd[q] = D[o];
+    ra[q] = A[o];
+    if (KIND == 5) rb[q] = B[o];
+  };
+  FactorState st;
+  int64_t bad = -1;
+  auto use = [&](int q, int64_t k) {
+    const int64_t i = lo + k;
+    double l2, l1, u0, u1;
+    factor_row<KIND>(i, lo, n, KIND == 5 ? re[q] : 0.0, rc[q], rd[q], ra[q],
+                     KIND == 5 ? rb[q] : 0.0, st, l2, l1, u0, u1);
+    if (i >= w0) {
+      if (bad < 0 && bad_pivot(u0)) bad = i;
+      const int64_t fo = i * fld + s;
+      if (KIND == 5) {
+        P.l2[fo] = l2;
+        P.u1[fo] = u1;
+      }
+      P.l1[fo] = l1;
+      P.u0[fo] = u0;
+    }
+  };
+  stream_rows<kPF, false>(hi - lo, fetch, use);
+  return bad;
+}
+
 template <int KIND>
 __global__ __launch_bounds__(kLaneBlock) void factor_lane_kernel(
     int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
@@ -273,54 +360,181 @@ __global__ __launch_bounds__(kLaneBlock) void factor_lane_kernel(
     double* __restrict__ F, int64_t fld, int32_t* __restrict__ info) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
   if (s >= batch) return;
-  const int64_t plane = n * fld;
-  double* L2 = (KIND == 5) ? F : nullptr;
-  double* L1 = (KIND == 5) ? F + plane : F;
-  double* U0 = (KIND == 5) ? F + 2 * plane : F + plane;
-  double* U1 = (KIND == 5) ? F + 3 * plane : nullptr;
-  double re[kPF], rc[kPF], rd[kPF], ra[kPF], rb[kPF];
-  auto fetch = [&](int q, int64_t i) {
-    const int64_t o = i * ld + s;
-    if (KIND == 5) re[q] = E[o];
-    rc[q] = C[o];
-    rd[q] = D[o];
-    ra[q] = A[o];
-    if (KIND == 5) rb[q] = B[o];
-  };
-  double u0m1 = 0, u0m2 = 0, u1m1 = 0, u1m2 = 0, u2m1 = 0, u2m2 = 0;
-  int64_t bad = -1;  // first bad pivot (the sweep runs on; later factors unspecified)
-  auto use = [&](int q, int64_t i) {
-    // corner slots (e_0, e_1, c_0, a_{n-1}, b_{n-2}, b_{n-1}) are never used
-    double l2 = 0.0, l1 = 0.0, u0, u1 = 0.0, u2 = 0.0;
-    if (KIND == 5 && i >= 2) l2 = re[q] / u0m2;
-    if (i == 1) l1 = rc[q] / u0m1;
-    if (i >= 2) l1 = (KIND == 5) ? (rc[q] - l2 * u1m2) / u0m1 : rc[q] / u0m1;
-    if (i == 0)
-      u0 = rd[q];
-    else if (i == 1 || KIND == 3)
-      u0 = rd[q] - l1 * u1m1;
-    else
-      u0 = (rd[q] - l2 * u2m2) - l1 * u1m1;
-    if (bad < 0 && bad_pivot(u0)) bad = i;
-    if (i <= n - 2) u1 = (i == 0 || KIND == 3) ? ra[q] : ra[q] - l1 * u2m1;
-    if (KIND == 5 && i <= n - 3) u2 = rb[q];
-    const int64_t fo = i * fld + s;
-    if (KIND == 5) {
-      L2[fo] = l2;
-      U1[fo] = u1;
-    }
-    L1[fo] = l1;
-    U0[fo] = u0;
-    u0m2 = u0m1; u0m1 = u0;
-    u1m2 = u1m1; u1m1 = u1;
-    u2m2 = u2m1; u2m1 = u2;
-  };
-  stream_rows<kPF, false>(n, fetch, use);
+  const int64_t bad = factor_rows<KIND>(n, ld, s, 0, 0, n, E, C, D, A, B,
+                                        factor_planes<KIND>(F, n, fld), fld);
   info[s] = bad < 0 ? 0 : (int32_t)(bad + 1);
 }
 
-// Substitution with the band factors: z_i = (y_i - l1_i z_{i-1}) - l2_i z_{i-2}
-// (z kept in x), then x_i = ((z_i - u1_i x_{i+1}) - u2_i x_{i+2}) / u0_i.
+// ---- ILU(0) with the rows of a system split over lanes ------------------
+// On the systems of the ADI sweeps the pivot recurrence forgets where it
+// started: an error in the carried state shrinks by a factor of about
+// c_i a_{i-1} / u0_{i-1}^2 < 1 per row.  So the rows of a system are cut into
+// chunks of M rows; lane (s, k) starts kFactorWarm rows before its chunk as if
+// the matrix began there, runs the recurrence through those warm-up rows
+// (results dropped) and then through its own rows (written).  Once the state
+// has converged to the bit, the chunk's factors are those of the sequential
+// recurrence.  The check kernel proves that it has: for every chunk it
+// recomputes the chunk's first two rows from the stored factors of the two
+// rows before it (the sequential state, by induction from chunk 0, which
+// starts at row 0) and compares bit patterns; a system with any mismatch is
+// factorized again, sequentially, by one lane.  Either way the output is the
+// sequential recurrence's to the last bit, and so is info.
+constexpr int64_t kFactorWarm = 64;
+constexpr int64_t kFactorLanes = 65536;  // aim: one wave per SIMD
+
+__global__ void info_init_kernel(int64_t batch, int32_t* __restrict__ info) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < batch) info[s] = INT32_MAX;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kLaneBlock) void factor_chunk_kernel(
+    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
+    const double* __restrict__ C, const double* __restrict__ D,
+    const double* __restrict__ A, const double* __restrict__ B,
+    double* __restrict__ F, int64_t fld, int32_t* __restrict__ info, int64_t M) {
+  const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
+  const int64_t w0 = (int64_t)blockIdx.y * M;
+  if (s >= batch) return;
+  const int64_t lo = w0 > kFactorWarm ? w0 - kFactorWarm : 0;
+  const int64_t hi = w0 + M < n ? w0 + M : n;
+  const int64_t bad = factor_rows<KIND>(n, ld, s, lo, w0, hi, E, C, D, A, B,
+                                        factor_planes<KIND>(F, n, fld), fld);
+  if (bad >= 0) atomicMin(&info[s], (int32_t)(bad + 1));
+}
+
+__device__ inline bool same_bits(double a, double b) {
+  return __double_as_longlong(a) == __double_as_longlong(b);
+}
+
+// One lane per system: the chunk-boundary proof, then the sequential
+// fallback where it fails, then info.
+template <int KIND>
+__global__ __launch_bounds__(kLaneBlock) void factor_check_kernel(
+    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
+    const double* __restrict__ C, const double* __restrict__ D,
+    const double* __restrict__ A, const double* __restrict__ B,
+    double* __restrict__ F, int64_t fld, int32_t* __restrict__ info, int64_t M,
+    int64_t chunks) {
+  const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
+  if (s >= batch) return;
+  const FactorPlanes P = factor_planes<KIND>(F, n, fld);
+  // chunk k starts at row k M; those with k M <= kFactorWarm started at row 0
+  const int64_t k0 = kFactorWarm / M + 1;
+  bool ok = true;
+  constexpr int U = 4;  // chunks checked per round (their loads overlap)
+  for (int64_t kb = k0; kb < chunks; kb += U) {
+    bool good[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      good[q] = true;
+      const int64_t k = kb + q;
+      if (k >= chunks) continue;
+      const int64_t r = k * M;  // 2 <= r < n
+      FactorState st;
+      for (int64_t i = r - 2; i < r; ++i) {  // the stored state of rows r-2, r-1
+        const int64_t o = i * fld + s;
+        st.u0m2 = st.u0m1;
+        st.u1m2 = st.u1m1;
+        st.u2m2 = st.u2m1;
+        st.u0m1 = P.u0[o];
+        st.u1m1 = (KIND == 5) ? P.u1[o] : (i <= n - 2 ? A[i * ld + s] : 0.0);
+        st.u2m1 = (KIND == 5 && i <= n - 3) ? B[i * ld + s] : 0.0;
+      }
+      for (int64_t i = r; i < r + 2 && i < n; ++i) {
+        const int64_t o = i * ld + s, fo = i * fld + s;
+        double l2, l1, u0, u1;
+        factor_row<KIND>(i, 0, n, KIND == 5 ? E[o] : 0.0, C[o], D[o], A[o],
+                         KIND == 5 ? B[o] : 0.0, st, l2, l1, u0, u1);
+        bool eq = same_bits(l1, P.l1[fo]) && same_bits(u0, P.u0[fo]);
+        if (KIND == 5) eq = eq && same_bits(l2, P.l2[fo]) && same_bits(u1, P.u1[fo]);
+        good[q] = good[q] && eq;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) ok = ok && good[q];
+    if (!ok) break;
+  }
+  if (ok) {
+    const int32_t b = info[s];
+    info[s] = b == INT32_MAX ? 0 : b;
+  } else {
+    const int64_t bad = factor_rows<KIND>(n, ld, s, 0, 0, n, E, C, D, A, B, P, fld);
+    info[s] = bad < 0 ? 0 : (int32_t)(bad + 1);
+  }
+}
+
+// Substitution with the band factors: z_i = (y_i - l1_i z_{i-1}) - l2_i z_{i-2},
+// then x_i = ((z_i - u1_i x_{i+1}) - u2_i x_{i+2}) / u0_i.
+struct SubstPlanes {
+  const double* l2;  // KIND 5 only
+  const double* l1;
+  const double* u0;
+  const double* u1;  // KIND 5: the u1 array; KIND 3: a
+  const double* u2;  // KIND 5: b
+};
+
+template <int KIND>
+__device__ inline SubstPlanes subst_planes(const double* F, const double* Aa, const double* B,
+                                           int64_t n, int64_t ld) {
+  const int64_t plane = n * ld;
+  if (KIND == 5) return {F, F + plane, F + 2 * plane, F + 3 * plane, B};
+  return {nullptr, F, F + plane, Aa, nullptr};
+}
+
+// Forward rows [lo, hi) of system s with z_{lo-1}, z_{lo-2} taken as absent;
+// z written to Z (pitch zl) for rows >= w0.
+template <int KIND>
+__device__ inline void subst_fwd_rows(int64_t ld, int64_t s, int64_t lo, int64_t w0, int64_t hi,
+                                      SubstPlanes P, const double* __restrict__ Y,
+                                      double* __restrict__ Z, int64_t zl) {
+  double ry[kPF], rl1[kPF], rl2[kPF];
+  double zm1 = 0, zm2 = 0;
+  auto fetch = [&](int q, int64_t k) {
+    const int64_t o = (lo + k) * ld + s;
+    ry[q] = Y[o];
+    rl1[q] = P.l1[o];
+    if (KIND == 5) rl2[q] = P.l2[o];
+  };
+  auto use = [&](int q, int64_t k) {
+    double t = ry[q];
+    if (k >= 1) t = t - rl1[q] * zm1;
+    if (KIND == 5 && k >= 2) t = t - rl2[q] * zm2;
+    if (lo + k >= w0) Z[(lo + k) * zl + s] = t;
+    zm2 = zm1;
+    zm1 = t;
+  };
+  stream_rows<kPF, false>(hi - lo, fetch, use);
+}
+
+// Backward rows top-1 down to w0 of system s with x_top, x_{top+1} taken as
+// absent (top = n: the recurrence itself); x written for rows < w1.
+template <int KIND>
+__device__ inline void subst_bwd_rows(int64_t ld, int64_t s, int64_t w0, int64_t w1, int64_t top,
+                                      SubstPlanes P, const double* __restrict__ Z, int64_t zl,
+                                      double* __restrict__ X) {
+  double rz[kPF], ru1[kPF], ru2[kPF], ru0[kPF];
+  double xp1 = 0, xp2 = 0;
+  auto fetch = [&](int q, int64_t k) {
+    const int64_t i = w0 + k, o = i * ld + s;
+    rz[q] = Z[i * zl + s];
+    ru1[q] = P.u1[o];
+    if (KIND == 5) ru2[q] = P.u2[o];
+    ru0[q] = P.u0[o];
+  };
+  auto use = [&](int q, int64_t k) {
+    const int64_t i = w0 + k;
+    double t = rz[q];
+    if (i + 1 < top) t = t - ru1[q] * xp1;
+    if (KIND == 5 && i + 2 < top) t = t - ru2[q] * xp2;
+    const double xi = t / ru0[q];
+    if (i < w1) X[i * ld + s] = xi;
+    xp2 = xp1;
+    xp1 = xi;
+  };
+  stream_rows<kPF, true>(top - w0, fetch, use);
+}
+
 template <int KIND>
 __global__ __launch_bounds__(kLaneBlock) void subst_lane_kernel(
     int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
@@ -329,51 +543,113 @@ __global__ __launch_bounds__(kLaneBlock) void subst_lane_kernel(
     int32_t* __restrict__ info) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
   if (s >= batch) return;
-  const int64_t plane = n * ld;
-  const double* L2 = (KIND == 5) ? F : nullptr;
-  const double* L1 = (KIND == 5) ? F + plane : F;
-  const double* U0 = (KIND == 5) ? F + 2 * plane : F + plane;
-  const double* U1 = (KIND == 5) ? F + 3 * plane : Aa;  // TD: u1 = a
-  {
-    double ry[kPF], rl1[kPF], rl2[kPF];
-    double zm1 = 0, zm2 = 0;
-    auto fetch = [&](int q, int64_t i) {
-      const int64_t o = i * ld + s;
-      ry[q] = Y[o];
-      rl1[q] = L1[o];
-      if (KIND == 5) rl2[q] = L2[o];
-    };
-    auto use = [&](int q, int64_t i) {
-      double t = ry[q];
-      if (i >= 1) t = t - rl1[q] * zm1;
-      if (KIND == 5 && i >= 2) t = t - rl2[q] * zm2;
-      X[i * ld + s] = t;
-      zm2 = zm1;
-      zm1 = t;
-    };
-    stream_rows<kPF, false>(n, fetch, use);
+  const SubstPlanes P = subst_planes<KIND>(F, Aa, B, n, ld);
+  subst_fwd_rows<KIND>(ld, s, 0, 0, n, P, Y, X, ld);  // z kept in x
+  subst_bwd_rows<KIND>(ld, s, 0, n, n, P, X, ld, X);
+  info[s] = 0;
+}
+
+// ---- substitution with the rows of a system split over lanes ------------
+// Both sweeps are linear recurrences whose homogeneous parts shrink an error
+// in the carried pair by about |l1| (forward) and |u1 / u0| (backward) per
+// row, so they are cut into chunks exactly like the factorization: each lane
+// starts kSubstWarm rows early (forward: before its chunk; backward: after
+// it) with the pair outside taken as absent, and a proof kernel recomputes the
+// two rows at every chunk boundary from the stored rows beyond it, redoing
+// the sweep of a system sequentially where any bit differs.  z goes through
+// the workspace ([n][ws_ld] doubles), so the backward warm-up never reads a
+// row another lane has already overwritten with x.
+constexpr int64_t kSubstWarm = 128;
+constexpr int64_t kSubstLanes = 32768;
+
+template <int KIND>
+__global__ __launch_bounds__(kLaneBlock) void subst_fwd_chunk_kernel(
+    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
+    const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Y,
+    double* __restrict__ Z, int64_t zl, int64_t M) {
+  const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
+  if (s >= batch) return;
+  const int64_t w0 = (int64_t)blockIdx.y * M;
+  const int64_t lo = w0 > kSubstWarm ? w0 - kSubstWarm : 0;
+  const int64_t hi = w0 + M < n ? w0 + M : n;
+  subst_fwd_rows<KIND>(ld, s, lo, w0, hi, subst_planes<KIND>(F, Aa, B, n, ld), Y, Z, zl);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kLaneBlock) void subst_fwd_check_kernel(
+    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
+    const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Y,
+    double* __restrict__ Z, int64_t zl, int64_t M, int64_t chunks) {
+  const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
+  if (s >= batch) return;
+  const SubstPlanes P = subst_planes<KIND>(F, Aa, B, n, ld);
+  bool ok = true;
+  constexpr int U = 4;
+  for (int64_t kb = kSubstWarm / M + 1; kb < chunks && ok; kb += U) {
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int64_t k = kb + q;
+      if (k >= chunks) continue;
+      const int64_t r = k * M;  // 2 <= r < n
+      double zm2 = Z[(r - 2) * zl + s], zm1 = Z[(r - 1) * zl + s];
+      for (int64_t i = r; i < r + 2 && i < n; ++i) {
+        const int64_t o = i * ld + s;
+        double t = Y[o];
+        t = t - P.l1[o] * zm1;
+        if (KIND == 5) t = t - P.l2[o] * zm2;
+        ok = ok && same_bits(t, Z[i * zl + s]);
+        zm2 = zm1;
+        zm1 = t;
+      }
+    }
   }
-  {
-    double rz[kPF], ru1[kPF], ru2[kPF], ru0[kPF];
-    double xp1 = 0, xp2 = 0;
-    auto fetch = [&](int q, int64_t i) {
-      const int64_t o = i * ld + s;
-      rz[q] = X[o];
-      ru1[q] = U1[o];
-      if (KIND == 5) ru2[q] = B[o];
-      ru0[q] = U0[o];
-    };
-    auto use = [&](int q, int64_t i) {
-      double t = rz[q];
-      if (i + 1 < n) t = t - ru1[q] * xp1;
-      if (KIND == 5 && i + 2 < n) t = t - ru2[q] * xp2;
-      const double xi = t / ru0[q];
-      X[i * ld + s] = xi;
-      xp2 = xp1;
-      xp1 = xi;
-    };
-    stream_rows<kPF, true>(n, fetch, use);
+  if (!ok) subst_fwd_rows<KIND>(ld, s, 0, 0, n, P, Y, Z, zl);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kLaneBlock) void subst_bwd_chunk_kernel(
+    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
+    const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Z,
+    int64_t zl, double* __restrict__ X, int64_t M) {
+  const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
+  if (s >= batch) return;
+  const int64_t w0 = (int64_t)blockIdx.y * M;
+  const int64_t w1 = w0 + M < n ? w0 + M : n;
+  const int64_t top = n - w1 > kSubstWarm ? w1 + kSubstWarm : n;
+  subst_bwd_rows<KIND>(ld, s, w0, w1, top, subst_planes<KIND>(F, Aa, B, n, ld), Z, zl, X);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kLaneBlock) void subst_bwd_check_kernel(
+    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
+    const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Z,
+    int64_t zl, double* __restrict__ X, int32_t* __restrict__ info, int64_t M, int64_t chunks) {
+  const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
+  if (s >= batch) return;
+  const SubstPlanes P = subst_planes<KIND>(F, Aa, B, n, ld);
+  bool ok = true;
+  constexpr int U = 4;
+  // chunk k ends at row w1 = (k + 1) M; those with n - w1 <= kSubstWarm ran to n
+  for (int64_t kb = 0; kb < chunks - 1 && ok; kb += U) {
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+      const int64_t k = kb + q;
+      const int64_t w1 = (k + 1) * M;
+      if (k >= chunks - 1 || n - w1 <= kSubstWarm) continue;
+      double xp1 = X[w1 * ld + s], xp2 = X[(w1 + 1) * ld + s];  // w1 + 1 < n
+      for (int64_t i = w1 - 1; i >= w1 - 2; --i) {
+        const int64_t o = i * ld + s;
+        double t = Z[i * zl + s];
+        t = t - P.u1[o] * xp1;
+        if (KIND == 5) t = t - P.u2[o] * xp2;
+        const double xi = t / P.u0[o];
+        ok = ok && same_bits(xi, X[o]);
+        xp2 = xp1;
+        xp1 = xi;
+      }
+    }
   }
+  if (!ok) subst_bwd_rows<KIND>(ld, s, 0, n, n, P, Z, zl, X);
   info[s] = 0;
 }
 
@@ -412,6 +688,32 @@ hipError_t launch_mnpdm_lane(int64_t n, int64_t batch, int64_t ld, Diags A,
   return hipGetLastError();
 }
 
+hipError_t launch_factor(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
+                         double* factors, int64_t fld, int32_t* info, hipStream_t st) {
+  // chunks of at least 64 rows, enough of them for about kFactorLanes lanes
+  int64_t K = (kFactorLanes + batch - 1) / batch;
+  if (K > n / 64) K = n / 64;
+  if (K > 4096) K = 4096;  // grid y limit; far more lanes than the GPU holds
+  if (K <= 1) return launch_factor_lane(kind, n, batch, ld, A, factors, fld, info, st);
+  const int64_t M = (n + K - 1) / K;
+  K = (n + M - 1) / M;
+  hipLaunchKernelGGL(info_init_kernel, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, st,
+                     batch, info);
+  const dim3 grid((unsigned)((batch + kLaneBlock - 1) / kLaneBlock), (unsigned)K);
+  if (kind == 5) {
+    hipLaunchKernelGGL(factor_chunk_kernel<5>, grid, dim3(kLaneBlock), 0, st, n, batch, ld, A.e,
+                       A.c, A.d, A.a, A.b, factors, fld, info, M);
+    hipLaunchKernelGGL(factor_check_kernel<5>, lane_grid(batch), dim3(kLaneBlock), 0, st, n,
+                       batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, info, M, K);
+  } else {
+    hipLaunchKernelGGL(factor_chunk_kernel<3>, grid, dim3(kLaneBlock), 0, st, n, batch, ld, A.e,
+                       A.c, A.d, A.a, A.b, factors, fld, info, M);
+    hipLaunchKernelGGL(factor_check_kernel<3>, lane_grid(batch), dim3(kLaneBlock), 0, st, n,
+                       batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, info, M, K);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_factor_lane(int kind, int64_t n, int64_t batch, int64_t ld,
                               Diags A, double* factors, int64_t fld,
                               int32_t* info, hipStream_t st) {
@@ -423,6 +725,48 @@ hipError_t launch_factor_lane(int kind, int64_t n, int64_t batch, int64_t ld,
     hipLaunchKernelGGL(factor_lane_kernel<3>, lane_grid(batch),
                        dim3(kLaneBlock), 0, st, n, batch, ld, A.e, A.c, A.d,
                        A.a, A.b, factors, fld, info);
+  return hipGetLastError();
+}
+
+int64_t subst_chunks(int64_t n, int64_t batch) {
+  int64_t K = (kSubstLanes + batch - 1) / batch;
+  if (K > n / 128) K = n / 128;  // chunks of at least 128 rows
+  if (K > 4096) K = 4096;
+  return K < 1 ? 1 : K;
+}
+
+size_t subst_workspace_bytes(int64_t n, int64_t batch) {
+  return subst_chunks(n, batch) > 1 ? (size_t)(n * ws_ld(batch)) * 8 : 0;
+}
+
+hipError_t launch_subst(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
+                        const double* factors, const double* y, double* x, int32_t* info,
+                        double* ws, hipStream_t st) {
+  int64_t K = subst_chunks(n, batch);
+  if (K <= 1) return launch_subst_lane(kind, n, batch, ld, A, factors, y, x, info, st);
+  const int64_t M = (n + K - 1) / K;
+  K = (n + M - 1) / M;
+  const int64_t zl = ws_ld(batch);
+  const dim3 grid((unsigned)((batch + kLaneBlock - 1) / kLaneBlock), (unsigned)K);
+  if (kind == 5) {
+    hipLaunchKernelGGL(subst_fwd_chunk_kernel<5>, grid, dim3(kLaneBlock), 0, st, n, batch, ld,
+                       A.a, A.b, factors, y, ws, zl, M);
+    hipLaunchKernelGGL(subst_fwd_check_kernel<5>, lane_grid(batch), dim3(kLaneBlock), 0, st, n,
+                       batch, ld, A.a, A.b, factors, y, ws, zl, M, K);
+    hipLaunchKernelGGL(subst_bwd_chunk_kernel<5>, grid, dim3(kLaneBlock), 0, st, n, batch, ld,
+                       A.a, A.b, factors, ws, zl, x, M);
+    hipLaunchKernelGGL(subst_bwd_check_kernel<5>, lane_grid(batch), dim3(kLaneBlock), 0, st, n,
+                       batch, ld, A.a, A.b, factors, ws, zl, x, info, M, K);
+  } else {
+    hipLaunchKernelGGL(subst_fwd_chunk_kernel<3>, grid, dim3(kLaneBlock), 0, st, n, batch, ld,
+                       A.a, A.b, factors, y, ws, zl, M);
+    hipLaunchKernelGGL(subst_fwd_check_kernel<3>, lane_grid(batch), dim3(kLaneBlock), 0, st, n,
+                       batch, ld, A.a, A.b, factors, y, ws, zl, M, K);
+    hipLaunchKernelGGL(subst_bwd_chunk_kernel<3>, grid, dim3(kLaneBlock), 0, st, n, batch, ld,
+                       A.a, A.b, factors, ws, zl, x, M);
+    hipLaunchKernelGGL(subst_bwd_check_kernel<3>, lane_grid(batch), dim3(kLaneBlock), 0, st, n,
+                       batch, ld, A.a, A.b, factors, ws, zl, x, info, M, K);
+  }
   return hipGetLastError();
 }
 

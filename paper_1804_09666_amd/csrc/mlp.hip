@@ -79,7 +79,23 @@ __global__ __launch_bounds__(kThreads) void gemm_nt_kernel(int64_t M, int64_t N,
   __shared__ __attribute__((aligned(16))) T sB[2][BN * LDR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * WM, wn = (wave & 1) * WN;
-  const int64_t m0 = (int64_t)blockIdx.y * BM, n0 = (int64_t)blockIdx.x * BN;
+  // block -> (row tile, column tile): blocks go to the 8 XCDs round-robin, so
+  // the column tiles of one row tile are placed consecutively on one XCD and
+  // its A rows come from that XCD's L2 after the first read
+  int64_t rt, ctile;
+  {
+    const int64_t nrow = (M + BM - 1) / BM, ncol = (N + BN - 1) / BN;
+    const int64_t b = blockIdx.x;
+    if (nrow % 8 == 0) {
+      const int64_t xcd = b % 8, k = b / 8;
+      rt = (k / ncol) * 8 + xcd;
+      ctile = k % ncol;
+    } else {
+      rt = b / ncol;
+      ctile = b % ncol;
+    }
+  }
+  const int64_t m0 = rt * BM, n0 = ctile * BN;
   f32x16 acc[TI][TJ];
 #pragma unroll
   for (int i = 0; i < TI; ++i)
@@ -376,7 +392,7 @@ hipError_t gemm_tiles(int64_t M, int64_t N, int64_t K, const void* A, const void
                       const float* bias, int relu, const void* mask, float* C32, void* CT,
                       hipStream_t st) {
   constexpr int BM = 64 * TI, BN = 64 * TJ;
-  const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
+  const dim3 grid((unsigned)(((N + BN - 1) / BN) * ((M + BM - 1) / BM)));
   hipLaunchKernelGGL((gemm_nt_kernel<T, TI, TJ>), grid, dim3(kThreads), 0, st, M, N, K,
                      static_cast<const T*>(A), static_cast<const T*>(B), bias, relu,
                      static_cast<const T*>(mask), C32, static_cast<T*>(CT));

@@ -45,7 +45,16 @@ def test_workspace_query(bs):
     n, batch = 1000, 100
     lw = 128
     assert bs.workspace_bytes(bs.OP_FACTOR, 5, n, batch) == 0
-    assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 3, n, batch) == 0
+    # substitution split over lanes: z plane; one lane per system (or a batch
+    # that fills the GPU alone, or short systems): none
+    assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 3, n, batch) == n * lw * 8
+    assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 5, n, 40000) == 0
+    assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 5, 255, batch) == 0
+    bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_LANE)
+    try:
+        assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 5, n, batch) == 0
+    finally:
+        bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_AUTO)
     assert bs.workspace_bytes(bs.OP_SIP, 5, n, batch) == 5 * n * lw * 8
     # MNPDM: the split PD kernel's exchange area, or alpha and beta planes
     assert bs.workspace_bytes(bs.OP_MNPDM, 5, n, batch) == \
@@ -158,6 +167,13 @@ def test_invalid_arguments_rejected_on_host(bs):
     if need:
         assert lib.band_solve(5, 0, n, batch, ld, d5, None, y, x, info, ws, need - 1,
                               None) == bs.BS_EWORKSPACE
+    # substitution with the rows split over lanes: the z plane is required
+    need = bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 5, 1000, batch, ld=ld)
+    assert need == 1000 * 64 * 8
+    assert lib.band_solve(5, 0, 1000, batch, ld, d5, _fake(6), y, x, info, ws, need - 1,
+                          None) == bs.BS_EWORKSPACE
+    assert lib.band_solve(5, 0, 1000, batch, ld, d5, _fake(6), y, x, info, None, need,
+                          None) == E
     # FP32 storage: fused solve only, n >= 8
     assert lib.band_solve(5, 1, n, batch, ld, d5, _fake(6), y, x, info, ws, big, None) == E
     assert lib.band_solve(5, 1, 4, batch, ld, d5, None, y, x, info, ws, big, None) == E
