@@ -295,6 +295,24 @@ def other_rows(pd, td):
     f = torch.empty((4, N_ROWS, BATCH), dtype=torch.float64, device="cuda")
     ms = t_ms(lambda: bs.factor(diags_of(t, 5), batch=BATCH, out=f, info=info), reps=3)
     out["ilu0_pd"] = {"us": ms * 1e3, "algorithmic_GBps": 72 * N_ROWS * BATCH / ms / 1e6}
+    # substitution L z = y, U x = z with those factors (z through the workspace)
+    nb = bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 5, N_ROWS, BATCH)
+    wsz = torch.empty(max(nb, 8) // 8, dtype=torch.float64, device="cuda")
+    ms = t_ms(lambda: bs.solve(diags_of(t, 5), t["y"], x, batch=BATCH, factors=f, info=info,
+                               workspace=wsz), reps=3)
+    out["subst_pd"] = {"us": ms * 1e3, "algorithmic_GBps": 72 * N_ROWS * BATCH / ms / 1e6}
+    # both split over lanes by default; the one-lane sweeps give the same bits
+    xs = x.clone()
+    bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_LANE)
+    try:
+        f1 = torch.empty_like(f)
+        bs.factor(diags_of(t, 5), batch=BATCH, out=f1, info=info)
+        bs.solve(diags_of(t, 5), t["y"], x, batch=BATCH, factors=f1, info=info)
+    finally:
+        bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_AUTO)
+    out["ilu0_pd"]["bitwise_one_lane"] = bool(torch.equal(f.view(torch.int64), f1.view(torch.int64)))
+    out["subst_pd"]["bitwise_one_lane"] = bool(torch.equal(xs.view(torch.int64), x.view(torch.int64)))
+    del f1, xs, wsz
     # SIP with HB steps (s_L, s_U) = (3, 4) from zero start to 1e-10
     res = {}
 
@@ -527,7 +545,10 @@ def profile_rows():
                                             info=info))
     f = torch.empty((4, N_ROWS, BATCH), dtype=torch.float64, device="cuda")
     rep("ilu0 factor", lambda: bs.factor(D5, batch=BATCH, out=f, info=info))
-    rep("substitution", lambda: bs.solve(D5, t5["y"], x, batch=BATCH, factors=f, info=info))
+    nb = bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 5, N_ROWS, BATCH)
+    wsz = torch.empty(max(nb, 8) // 8, dtype=torch.float64, device="cuda")
+    rep("substitution", lambda: bs.solve(D5, t5["y"], x, batch=BATCH, factors=f, info=info,
+                                         workspace=wsz))
     rep("sip hb(3,4)", lambda: bs.sip(D5, t5["y"], tol=1e-10, max_iter=12, s_L=3, s_U=4,
                                       factors=f, batch=BATCH), k=1)
     rep("sip exact", lambda: bs.sip(D5, t5["y"], tol=1e-10, max_iter=3, factors=f, batch=BATCH),

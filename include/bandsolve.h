@@ -169,7 +169,8 @@ int32_t band_factor(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
  *   is small the rows of each sweep are split over lanes as in band_factor
  *   (chunks started early, a bitwise proof at every chunk boundary, a
  *   sequential redo where it fails: x is the sequential sweeps' to the last
- *   bit); z then goes through the workspace (n * ceil(batch/64)*64 doubles).
+ *   bit); z then goes through the workspace (n * ceil(batch/64)*64 doubles,
+ *   then one int32 flag per system).
  * workspace / ws_bytes: as bs_workspace_bytes(BS_OP_SOLVE or
  *   BS_OP_SOLVE_FACTORED, ...); may be NULL / 0 when that is 0.  When the
  *   rows of a system span several blocks, the blocks meet at counters in the

@@ -373,14 +373,20 @@ __global__ __launch_bounds__(kLaneBlock) void factor_lane_kernel(
 // the matrix began there, runs the recurrence through those warm-up rows
 // (results dropped) and then through its own rows (written).  Once the state
 // has converged to the bit, the chunk's factors are those of the sequential
-// recurrence.  The check kernel proves that it has: for every chunk it
+// recurrence.  The proof kernel shows that it has: for every chunk it
 // recomputes the chunk's first two rows from the stored factors of the two
 // rows before it (the sequential state, by induction from chunk 0, which
 // starts at row 0) and compares bit patterns; a system with any mismatch is
-// factorized again, sequentially, by one lane.  Either way the output is the
+// factorized again, sequentially, by one lane of the finish kernel.  Either way the output is the
 // sequential recurrence's to the last bit, and so is info.
-constexpr int64_t kFactorWarm = 64;
-constexpr int64_t kFactorLanes = 65536;  // aim: one wave per SIMD
+// On the second-order sweeps at r = 4 the state reaches the sequential one
+// to the bit within 57..64 rows (56 warm-up rows leave chunks unproven, 64
+// do not); 80 leaves room for somewhat weaker dominance.  Where a system
+// needs more, it is redone sequentially: the result is the same, only slower.
+constexpr int64_t kFactorWarm = 80;
+// lanes to aim for: the warm-up rows are read twice, so fewer, longer chunks
+// win once the GPU has a few thousand waves of them (measured)
+constexpr int64_t kFactorLanes[2] = {16384, 32768};  // PD, TD
 
 __global__ void info_init_kernel(int64_t batch, int32_t* __restrict__ info) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -407,61 +413,62 @@ __device__ inline bool same_bits(double a, double b) {
   return __double_as_longlong(a) == __double_as_longlong(b);
 }
 
-// One lane per system: the chunk-boundary proof, then the sequential
-// fallback where it fails, then info.
+// One lane per (system, chunk boundary): recompute the chunk's first two
+// rows from the stored rows before it and compare bit patterns; a mismatch
+// marks the system (info < 0).
 template <int KIND>
-__global__ __launch_bounds__(kLaneBlock) void factor_check_kernel(
+__global__ __launch_bounds__(kLaneBlock) void factor_proof_kernel(
     int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
     const double* __restrict__ C, const double* __restrict__ D,
     const double* __restrict__ A, const double* __restrict__ B,
-    double* __restrict__ F, int64_t fld, int32_t* __restrict__ info, int64_t M,
-    int64_t chunks) {
+    const double* __restrict__ F, int64_t fld, int32_t* __restrict__ info, int64_t M) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
   if (s >= batch) return;
-  const FactorPlanes P = factor_planes<KIND>(F, n, fld);
   // chunk k starts at row k M; those with k M <= kFactorWarm started at row 0
-  const int64_t k0 = kFactorWarm / M + 1;
+  const int64_t k = kFactorWarm / M + 1 + blockIdx.y;
+  const int64_t r = k * M;  // kFactorWarm < r < n
+  const FactorPlanes P = factor_planes<KIND>(const_cast<double*>(F), n, fld);
+  FactorState st;
+  for (int64_t i = r - 2; i < r; ++i) {  // the stored state of rows r-2, r-1
+    const int64_t o = i * fld + s;
+    st.u0m2 = st.u0m1;
+    st.u1m2 = st.u1m1;
+    st.u2m2 = st.u2m1;
+    st.u0m1 = P.u0[o];
+    st.u1m1 = (KIND == 5) ? P.u1[o] : (i <= n - 2 ? A[i * ld + s] : 0.0);
+    st.u2m1 = (KIND == 5 && i <= n - 3) ? B[i * ld + s] : 0.0;
+  }
   bool ok = true;
-  constexpr int U = 4;  // chunks checked per round (their loads overlap)
-  for (int64_t kb = k0; kb < chunks; kb += U) {
-    bool good[U];
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      good[q] = true;
-      const int64_t k = kb + q;
-      if (k >= chunks) continue;
-      const int64_t r = k * M;  // 2 <= r < n
-      FactorState st;
-      for (int64_t i = r - 2; i < r; ++i) {  // the stored state of rows r-2, r-1
-        const int64_t o = i * fld + s;
-        st.u0m2 = st.u0m1;
-        st.u1m2 = st.u1m1;
-        st.u2m2 = st.u2m1;
-        st.u0m1 = P.u0[o];
-        st.u1m1 = (KIND == 5) ? P.u1[o] : (i <= n - 2 ? A[i * ld + s] : 0.0);
-        st.u2m1 = (KIND == 5 && i <= n - 3) ? B[i * ld + s] : 0.0;
-      }
-      for (int64_t i = r; i < r + 2 && i < n; ++i) {
-        const int64_t o = i * ld + s, fo = i * fld + s;
-        double l2, l1, u0, u1;
-        factor_row<KIND>(i, 0, n, KIND == 5 ? E[o] : 0.0, C[o], D[o], A[o],
-                         KIND == 5 ? B[o] : 0.0, st, l2, l1, u0, u1);
-        bool eq = same_bits(l1, P.l1[fo]) && same_bits(u0, P.u0[fo]);
-        if (KIND == 5) eq = eq && same_bits(l2, P.l2[fo]) && same_bits(u1, P.u1[fo]);
-        good[q] = good[q] && eq;
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < U; ++q) ok = ok && good[q];
-    if (!ok) break;
+  for (int64_t i = r; i < r + 2 && i < n; ++i) {
+    const int64_t o = i * ld + s, fo = i * fld + s;
+    double l2, l1, u0, u1;
+    factor_row<KIND>(i, 0, n, KIND == 5 ? E[o] : 0.0, C[o], D[o], A[o], KIND == 5 ? B[o] : 0.0,
+                     st, l2, l1, u0, u1);
+    ok = ok && same_bits(l1, P.l1[fo]) && same_bits(u0, P.u0[fo]);
+    if (KIND == 5) ok = ok && same_bits(l2, P.l2[fo]) && same_bits(u1, P.u1[fo]);
   }
-  if (ok) {
-    const int32_t b = info[s];
+  if (!ok) atomicMin(&info[s], -1);
+}
+
+// One lane per system: proven systems report the first bad pivot the chunk
+// lanes saw (their rows are the sequential ones); the others are factorized
+// again, sequentially.
+template <int KIND>
+__global__ __launch_bounds__(kLaneBlock) void factor_finish_kernel(
+    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
+    const double* __restrict__ C, const double* __restrict__ D,
+    const double* __restrict__ A, const double* __restrict__ B,
+    double* __restrict__ F, int64_t fld, int32_t* __restrict__ info) {
+  const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
+  if (s >= batch) return;
+  const int32_t b = info[s];
+  if (b >= 0) {
     info[s] = b == INT32_MAX ? 0 : b;
-  } else {
-    const int64_t bad = factor_rows<KIND>(n, ld, s, 0, 0, n, E, C, D, A, B, P, fld);
-    info[s] = bad < 0 ? 0 : (int32_t)(bad + 1);
+    return;
   }
+  const int64_t bad = factor_rows<KIND>(n, ld, s, 0, 0, n, E, C, D, A, B,
+                                        factor_planes<KIND>(F, n, fld), fld);
+  info[s] = bad < 0 ? 0 : (int32_t)(bad + 1);
 }
 
 // Substitution with the band factors: z_i = (y_i - l1_i z_{i-1}) - l2_i z_{i-2},
@@ -555,55 +562,65 @@ __global__ __launch_bounds__(kLaneBlock) void subst_lane_kernel(
 // row, so they are cut into chunks exactly like the factorization: each lane
 // starts kSubstWarm rows early (forward: before its chunk; backward: after
 // it) with the pair outside taken as absent, and a proof kernel recomputes the
-// two rows at every chunk boundary from the stored rows beyond it, redoing
-// the sweep of a system sequentially where any bit differs.  z goes through
-// the workspace ([n][ws_ld] doubles), so the backward warm-up never reads a
-// row another lane has already overwritten with x.
-constexpr int64_t kSubstWarm = 128;
+// two rows at every chunk boundary from the stored rows beyond it; a fix
+// kernel redoes the sweep of a system sequentially where any bit differs.
+// z goes through the workspace ([n][ws_ld] doubles, then the flags), so the
+// backward warm-up never reads a row another lane has already overwritten
+// with x.
+// at r = 4 the sweeps need 113..128 rows (|l1| and |u1/u0| reach ~0.7)
+constexpr int64_t kSubstWarm = 160;
 constexpr int64_t kSubstLanes = 32768;
 
+// flags[s] (int32, workspace) marks a system whose proof failed; the forward
+// chunk kernel clears it, each fix kernel acts on it and clears it again.
 template <int KIND>
 __global__ __launch_bounds__(kLaneBlock) void subst_fwd_chunk_kernel(
     int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
     const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Y,
-    double* __restrict__ Z, int64_t zl, int64_t M) {
+    double* __restrict__ Z, int64_t zl, int32_t* __restrict__ flags, int64_t M) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
   if (s >= batch) return;
+  if (blockIdx.y == 0) flags[s] = 0;
   const int64_t w0 = (int64_t)blockIdx.y * M;
   const int64_t lo = w0 > kSubstWarm ? w0 - kSubstWarm : 0;
   const int64_t hi = w0 + M < n ? w0 + M : n;
   subst_fwd_rows<KIND>(ld, s, lo, w0, hi, subst_planes<KIND>(F, Aa, B, n, ld), Y, Z, zl);
 }
 
+// One lane per (system, chunk that started early): z of the chunk's first
+// two rows from the stored z of the two rows before it.
 template <int KIND>
-__global__ __launch_bounds__(kLaneBlock) void subst_fwd_check_kernel(
+__global__ __launch_bounds__(kLaneBlock) void subst_fwd_proof_kernel(
     int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
     const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Y,
-    double* __restrict__ Z, int64_t zl, int64_t M, int64_t chunks) {
+    const double* __restrict__ Z, int64_t zl, int32_t* __restrict__ flags, int64_t M) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
   if (s >= batch) return;
   const SubstPlanes P = subst_planes<KIND>(F, Aa, B, n, ld);
+  const int64_t r = (kSubstWarm / M + 1 + blockIdx.y) * M;  // kSubstWarm < r < n
+  double zm2 = Z[(r - 2) * zl + s], zm1 = Z[(r - 1) * zl + s];
   bool ok = true;
-  constexpr int U = 4;
-  for (int64_t kb = kSubstWarm / M + 1; kb < chunks && ok; kb += U) {
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      const int64_t k = kb + q;
-      if (k >= chunks) continue;
-      const int64_t r = k * M;  // 2 <= r < n
-      double zm2 = Z[(r - 2) * zl + s], zm1 = Z[(r - 1) * zl + s];
-      for (int64_t i = r; i < r + 2 && i < n; ++i) {
-        const int64_t o = i * ld + s;
-        double t = Y[o];
-        t = t - P.l1[o] * zm1;
-        if (KIND == 5) t = t - P.l2[o] * zm2;
-        ok = ok && same_bits(t, Z[i * zl + s]);
-        zm2 = zm1;
-        zm1 = t;
-      }
-    }
+  for (int64_t i = r; i < r + 2 && i < n; ++i) {
+    const int64_t o = i * ld + s;
+    double t = Y[o];
+    t = t - P.l1[o] * zm1;
+    if (KIND == 5) t = t - P.l2[o] * zm2;
+    ok = ok && same_bits(t, Z[i * zl + s]);
+    zm2 = zm1;
+    zm1 = t;
   }
-  if (!ok) subst_fwd_rows<KIND>(ld, s, 0, 0, n, P, Y, Z, zl);
+  if (!ok) flags[s] = 1;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kLaneBlock) void subst_fwd_fix_kernel(
+    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
+    const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Y,
+    double* __restrict__ Z, int64_t zl, int32_t* __restrict__ flags) {
+  const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
+  if (s >= batch || flags[s] == 0) return;
+  subst_fwd_rows<KIND>(ld, s, 0, 0, n, subst_planes<KIND>(F, Aa, B, n, ld), Y, Z, zl);
+  flags[s] = 0;
 }
 
 template <int KIND>
@@ -619,37 +636,45 @@ __global__ __launch_bounds__(kLaneBlock) void subst_bwd_chunk_kernel(
   subst_bwd_rows<KIND>(ld, s, w0, w1, top, subst_planes<KIND>(F, Aa, B, n, ld), Z, zl, X);
 }
 
+// One lane per (system, chunk that started late): x of the chunk's last two
+// rows from the stored x of the two rows after it.  Chunk k ends at row
+// (k + 1) M; those within kSubstWarm rows of n ran from n.
 template <int KIND>
-__global__ __launch_bounds__(kLaneBlock) void subst_bwd_check_kernel(
+__global__ __launch_bounds__(kLaneBlock) void subst_bwd_proof_kernel(
     int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
     const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Z,
-    int64_t zl, double* __restrict__ X, int32_t* __restrict__ info, int64_t M, int64_t chunks) {
+    int64_t zl, const double* __restrict__ X, int32_t* __restrict__ flags, int64_t M) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
   if (s >= batch) return;
   const SubstPlanes P = subst_planes<KIND>(F, Aa, B, n, ld);
+  const int64_t w1 = ((int64_t)blockIdx.y + 1) * M;  // n - w1 > kSubstWarm
+  double xp1 = X[w1 * ld + s], xp2 = X[(w1 + 1) * ld + s];
   bool ok = true;
-  constexpr int U = 4;
-  // chunk k ends at row w1 = (k + 1) M; those with n - w1 <= kSubstWarm ran to n
-  for (int64_t kb = 0; kb < chunks - 1 && ok; kb += U) {
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-      const int64_t k = kb + q;
-      const int64_t w1 = (k + 1) * M;
-      if (k >= chunks - 1 || n - w1 <= kSubstWarm) continue;
-      double xp1 = X[w1 * ld + s], xp2 = X[(w1 + 1) * ld + s];  // w1 + 1 < n
-      for (int64_t i = w1 - 1; i >= w1 - 2; --i) {
-        const int64_t o = i * ld + s;
-        double t = Z[i * zl + s];
-        t = t - P.u1[o] * xp1;
-        if (KIND == 5) t = t - P.u2[o] * xp2;
-        const double xi = t / P.u0[o];
-        ok = ok && same_bits(xi, X[o]);
-        xp2 = xp1;
-        xp1 = xi;
-      }
-    }
+  for (int64_t i = w1 - 1; i >= w1 - 2; --i) {
+    const int64_t o = i * ld + s;
+    double t = Z[i * zl + s];
+    t = t - P.u1[o] * xp1;
+    if (KIND == 5) t = t - P.u2[o] * xp2;
+    const double xi = t / P.u0[o];
+    ok = ok && same_bits(xi, X[o]);
+    xp2 = xp1;
+    xp1 = xi;
   }
-  if (!ok) subst_bwd_rows<KIND>(ld, s, 0, n, n, P, Z, zl, X);
+  if (!ok) flags[s] = 1;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kLaneBlock) void subst_bwd_fix_kernel(
+    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
+    const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Z,
+    int64_t zl, double* __restrict__ X, int32_t* __restrict__ info,
+    int32_t* __restrict__ flags) {
+  const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
+  if (s >= batch) return;
+  if (flags[s] != 0) {
+    subst_bwd_rows<KIND>(ld, s, 0, n, n, subst_planes<KIND>(F, Aa, B, n, ld), Z, zl, X);
+    flags[s] = 0;
+  }
   info[s] = 0;
 }
 
@@ -690,8 +715,9 @@ hipError_t launch_mnpdm_lane(int64_t n, int64_t batch, int64_t ld, Diags A,
 
 hipError_t launch_factor(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
                          double* factors, int64_t fld, int32_t* info, hipStream_t st) {
-  // chunks of at least 64 rows, enough of them for about kFactorLanes lanes
-  int64_t K = (kFactorLanes + batch - 1) / batch;
+  // chunks of at least 64 rows, enough of them for about `lanes` lanes
+  const int64_t lanes = kFactorLanes[kind == 5 ? 0 : 1];
+  int64_t K = (lanes + batch - 1) / batch;
   if (K > n / 64) K = n / 64;
   if (K > 4096) K = 4096;  // grid y limit; far more lanes than the GPU holds
   if (K <= 1) return launch_factor_lane(kind, n, batch, ld, A, factors, fld, info, st);
@@ -699,17 +725,24 @@ hipError_t launch_factor(int kind, int64_t n, int64_t batch, int64_t ld, Diags A
   K = (n + M - 1) / M;
   hipLaunchKernelGGL(info_init_kernel, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, st,
                      batch, info);
-  const dim3 grid((unsigned)((batch + kLaneBlock - 1) / kLaneBlock), (unsigned)K);
+  const unsigned gx = (unsigned)((batch + kLaneBlock - 1) / kLaneBlock);
+  const int64_t proofs = K - (kFactorWarm / M + 1);  // chunks that started early
   if (kind == 5) {
-    hipLaunchKernelGGL(factor_chunk_kernel<5>, grid, dim3(kLaneBlock), 0, st, n, batch, ld, A.e,
-                       A.c, A.d, A.a, A.b, factors, fld, info, M);
-    hipLaunchKernelGGL(factor_check_kernel<5>, lane_grid(batch), dim3(kLaneBlock), 0, st, n,
-                       batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, info, M, K);
+    hipLaunchKernelGGL(factor_chunk_kernel<5>, dim3(gx, (unsigned)K), dim3(kLaneBlock), 0, st, n,
+                       batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, info, M);
+    if (proofs > 0)
+      hipLaunchKernelGGL(factor_proof_kernel<5>, dim3(gx, (unsigned)proofs), dim3(kLaneBlock), 0,
+                         st, n, batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, info, M);
+    hipLaunchKernelGGL(factor_finish_kernel<5>, dim3(gx), dim3(kLaneBlock), 0, st, n, batch, ld,
+                       A.e, A.c, A.d, A.a, A.b, factors, fld, info);
   } else {
-    hipLaunchKernelGGL(factor_chunk_kernel<3>, grid, dim3(kLaneBlock), 0, st, n, batch, ld, A.e,
-                       A.c, A.d, A.a, A.b, factors, fld, info, M);
-    hipLaunchKernelGGL(factor_check_kernel<3>, lane_grid(batch), dim3(kLaneBlock), 0, st, n,
-                       batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, info, M, K);
+    hipLaunchKernelGGL(factor_chunk_kernel<3>, dim3(gx, (unsigned)K), dim3(kLaneBlock), 0, st, n,
+                       batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, info, M);
+    if (proofs > 0)
+      hipLaunchKernelGGL(factor_proof_kernel<3>, dim3(gx, (unsigned)proofs), dim3(kLaneBlock), 0,
+                         st, n, batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, info, M);
+    hipLaunchKernelGGL(factor_finish_kernel<3>, dim3(gx), dim3(kLaneBlock), 0, st, n, batch, ld,
+                       A.e, A.c, A.d, A.a, A.b, factors, fld, info);
   }
   return hipGetLastError();
 }
@@ -736,7 +769,8 @@ int64_t subst_chunks(int64_t n, int64_t batch) {
 }
 
 size_t subst_workspace_bytes(int64_t n, int64_t batch) {
-  return subst_chunks(n, batch) > 1 ? (size_t)(n * ws_ld(batch)) * 8 : 0;
+  if (subst_chunks(n, batch) <= 1) return 0;
+  return (size_t)(n * ws_ld(batch)) * 8 + (size_t)(batch * 4 + 255) / 256 * 256;
 }
 
 hipError_t launch_subst(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
@@ -747,26 +781,35 @@ hipError_t launch_subst(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
   const int64_t M = (n + K - 1) / K;
   K = (n + M - 1) / M;
   const int64_t zl = ws_ld(batch);
-  const dim3 grid((unsigned)((batch + kLaneBlock - 1) / kLaneBlock), (unsigned)K);
+  int32_t* flags = reinterpret_cast<int32_t*>(ws + n * zl);
+  const unsigned gx = (unsigned)((batch + kLaneBlock - 1) / kLaneBlock);
+  const dim3 grid(gx, (unsigned)K), lanes(kLaneBlock);
+  // forward proofs: chunks that started before row 0 of their own (k M > warm-up)
+  const int64_t fproofs = K - (kSubstWarm / M + 1);
+  // backward proofs: chunks whose end lies more than the warm-up before n
+  int64_t bproofs = 0;
+  while (bproofs < K - 1 && n - (bproofs + 1) * M > kSubstWarm) ++bproofs;
+#define BS_SUBST(KD)                                                                          \
+  hipLaunchKernelGGL(subst_fwd_chunk_kernel<KD>, grid, lanes, 0, st, n, batch, ld, A.a, A.b,   \
+                     factors, y, ws, zl, flags, M);                                           \
+  if (fproofs > 0)                                                                            \
+    hipLaunchKernelGGL(subst_fwd_proof_kernel<KD>, dim3(gx, (unsigned)fproofs), lanes, 0, st, \
+                       n, batch, ld, A.a, A.b, factors, y, ws, zl, flags, M);                 \
+  hipLaunchKernelGGL(subst_fwd_fix_kernel<KD>, dim3(gx), lanes, 0, st, n, batch, ld, A.a, A.b, \
+                     factors, y, ws, zl, flags);                                              \
+  hipLaunchKernelGGL(subst_bwd_chunk_kernel<KD>, grid, lanes, 0, st, n, batch, ld, A.a, A.b,   \
+                     factors, ws, zl, x, M);                                                  \
+  if (bproofs > 0)                                                                            \
+    hipLaunchKernelGGL(subst_bwd_proof_kernel<KD>, dim3(gx, (unsigned)bproofs), lanes, 0, st, \
+                       n, batch, ld, A.a, A.b, factors, ws, zl, x, flags, M);                 \
+  hipLaunchKernelGGL(subst_bwd_fix_kernel<KD>, dim3(gx), lanes, 0, st, n, batch, ld, A.a,      \
+                     A.b, factors, ws, zl, x, info, flags);
   if (kind == 5) {
-    hipLaunchKernelGGL(subst_fwd_chunk_kernel<5>, grid, dim3(kLaneBlock), 0, st, n, batch, ld,
-                       A.a, A.b, factors, y, ws, zl, M);
-    hipLaunchKernelGGL(subst_fwd_check_kernel<5>, lane_grid(batch), dim3(kLaneBlock), 0, st, n,
-                       batch, ld, A.a, A.b, factors, y, ws, zl, M, K);
-    hipLaunchKernelGGL(subst_bwd_chunk_kernel<5>, grid, dim3(kLaneBlock), 0, st, n, batch, ld,
-                       A.a, A.b, factors, ws, zl, x, M);
-    hipLaunchKernelGGL(subst_bwd_check_kernel<5>, lane_grid(batch), dim3(kLaneBlock), 0, st, n,
-                       batch, ld, A.a, A.b, factors, ws, zl, x, info, M, K);
+    BS_SUBST(5)
   } else {
-    hipLaunchKernelGGL(subst_fwd_chunk_kernel<3>, grid, dim3(kLaneBlock), 0, st, n, batch, ld,
-                       A.a, A.b, factors, y, ws, zl, M);
-    hipLaunchKernelGGL(subst_fwd_check_kernel<3>, lane_grid(batch), dim3(kLaneBlock), 0, st, n,
-                       batch, ld, A.a, A.b, factors, y, ws, zl, M, K);
-    hipLaunchKernelGGL(subst_bwd_chunk_kernel<3>, grid, dim3(kLaneBlock), 0, st, n, batch, ld,
-                       A.a, A.b, factors, ws, zl, x, M);
-    hipLaunchKernelGGL(subst_bwd_check_kernel<3>, lane_grid(batch), dim3(kLaneBlock), 0, st, n,
-                       batch, ld, A.a, A.b, factors, ws, zl, x, info, M, K);
+    BS_SUBST(3)
   }
+#undef BS_SUBST
   return hipGetLastError();
 }
 

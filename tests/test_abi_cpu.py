@@ -45,9 +45,9 @@ def test_workspace_query(bs):
     n, batch = 1000, 100
     lw = 128
     assert bs.workspace_bytes(bs.OP_FACTOR, 5, n, batch) == 0
-    # substitution split over lanes: z plane; one lane per system (or a batch
+    # substitution split over lanes: z plane and per-system flags; one lane per system (or a batch
     # that fills the GPU alone, or short systems): none
-    assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 3, n, batch) == n * lw * 8
+    assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 3, n, batch) == n * lw * 8 + 512  # + flags
     assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 5, n, 40000) == 0
     assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 5, 255, batch) == 0
     bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_LANE)
@@ -169,7 +169,7 @@ def test_invalid_arguments_rejected_on_host(bs):
                               None) == bs.BS_EWORKSPACE
     # substitution with the rows split over lanes: the z plane is required
     need = bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 5, 1000, batch, ld=ld)
-    assert need == 1000 * 64 * 8
+    assert need == 1000 * 64 * 8 + 256
     assert lib.band_solve(5, 0, 1000, batch, ld, d5, _fake(6), y, x, info, ws, need - 1,
                           None) == bs.BS_EWORKSPACE
     assert lib.band_solve(5, 0, 1000, batch, ld, d5, _fake(6), y, x, info, None, need,

@@ -17,9 +17,10 @@ pytestmark = pytest.mark.gpu
 KEYS = {5: ("e", "c", "d", "a", "b"), 3: ("c", "d", "a")}
 
 
-def chunk_rows(n, batch):
-    """Rows per chunk the library picks: about 65536 lanes, chunks >= 64 rows."""
-    K = min(-(-65536 // batch), n // 64)
+def chunk_rows(n, batch, kind=5):
+    """Rows per chunk the library picks: about 16384 (PD) or 32768 (TD)
+    lanes, chunks >= 64 rows."""
+    K = min(-(-(16384 if kind == 5 else 32768) // batch), n // 64)
     if K <= 1:
         return n
     return -(-n // K)
@@ -70,10 +71,10 @@ def laplacian_batch(batch, n, kind):
 
 @pytest.mark.parametrize("kind", [5, 3])
 def test_pde_sweep_bitwise(kind):
-    """The 1024 x 1024 sweep batch (96 systems of n = 1024: 16 chunks of 64)."""
+    """96 systems of the 1024 x 1024 sweep batch (chunks of 64 or more rows)."""
     pd, td, _ = wl.config1(N=1024)
     ws = {k: v[:96] for k, v in (pd if kind == 5 else td).items()}
-    say(f"pde kind={kind} n=1024 batch=96 chunk={chunk_rows(1024, 96)}")
+    say(f"pde kind={kind} n=1024 batch=96 chunk={chunk_rows(1024, 96, kind)}")
     f, info, fl, infol = factor_both(ws, kind, 96)
     assert np.array_equal(bits(f, len(info)), bits(fl, len(info))) and np.array_equal(info.cpu(), infol.cpu())
     assert (info.cpu().numpy() == 0).all()
@@ -85,7 +86,7 @@ def test_pde_sweep_bitwise(kind):
                                         (127, 200, 200), (64, 3, 3)])
 def test_dominant_shapes_bitwise(kind, n, batch, ld):
     ws = wl.dominant_batch(batch, n, kind=kind, seed=300 + n)
-    say(f"dominant kind={kind} n={n} batch={batch} ld={ld} chunk={chunk_rows(n, batch)}")
+    say(f"dominant kind={kind} n={n} batch={batch} ld={ld} chunk={chunk_rows(n, batch, kind)}")
     f, info, fl, infol = factor_both(ws, kind, batch, ld)
     assert np.array_equal(bits(f, len(info)), bits(fl, len(info))) and np.array_equal(info.cpu(), infol.cpu())
     check_against_oracle(ws, kind, f, info.cpu().numpy(), range(0, batch, max(1, batch // 5)))
@@ -100,7 +101,7 @@ def test_fallback_mixed_batch(kind):
     lap = laplacian_batch(batch, n, kind)
     ws = {k: np.where((np.arange(batch) % 3 == 0)[:, None], lap[k], dom[k])
           for k in ("e", "c", "d", "a", "b", "y")}
-    say(f"fallback kind={kind} n={n} batch={batch} chunk={chunk_rows(n, batch)}")
+    say(f"fallback kind={kind} n={n} batch={batch} chunk={chunk_rows(n, batch, kind)}")
     f, info, fl, infol = factor_both(ws, kind, batch)
     assert np.array_equal(bits(f, len(info)), bits(fl, len(info))) and np.array_equal(info.cpu(), infol.cpu())
     check_against_oracle(ws, kind, f, info.cpu().numpy(), [0, 1, 3, 4, 62, 63])
@@ -112,7 +113,7 @@ def test_bad_pivots_around_chunk_boundaries(kind):
     of the next chunk, mid-chunk and on the last row: info as the oracle's,
     every factor (also past the bad pivot) as the one-lane path's."""
     n, batch = 1024, 64
-    M = chunk_rows(n, batch)
+    M = chunk_rows(n, batch, kind)
     ws = wl.dominant_batch(batch, n, kind=kind, seed=9)
     rows = [M, M + 1, 2 * M - 3, 3 * M + M // 2, n - 1, 5 * M - 1, 2]
     for s, r in enumerate(rows):
