@@ -152,13 +152,15 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
       }
       __builtin_amdgcn_s_waitcnt(kWaitVmem);
       if (tid == 0) {
-        atomicAdd(&cnt[2 * grp], 1u);
-        const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-        while (ld_counter(&cnt[2 * grp]) < (unsigned)T) {
-          __builtin_amdgcn_s_sleep(2);
-          if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
-            s_timeout = 1;
-            break;
+        // the last tile to arrive has nothing to wait for
+        if (atomicAdd(&cnt[2 * grp], 1u) + 1 < (unsigned)T) {
+          const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+          while (ld_counter(&cnt[2 * grp]) < (unsigned)T) {
+            __builtin_amdgcn_s_sleep(2);
+            if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
+              s_timeout = 1;
+              break;
+            }
           }
         }
       }
@@ -177,14 +179,7 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
         zero_map(gm);
       }
     }
-    __syncthreads();  // every tile map read: this tile may leave
-    if (tid == 0) {
-      const unsigned gone = atomicAdd(&cnt[2 * grp + 1], 1u);
-      if (gone == (unsigned)T - 1) {  // last one out resets the meeting point
-        __hip_atomic_store(&cnt[2 * grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&cnt[2 * grp + 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
+    __syncthreads();  // every tile map read: this tile may leave (at the end)
     if constexpr (TMAX > 1) {
       tree_up<NB, TMAX, G>(gm, j, g, s_gnode, s_bad, RT, 0, n);
       double gl[NB], gr[NB];
@@ -217,6 +212,15 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
   if (j == 0 && tile == 0 && live) {
     const int b0 = s_bad[g];
     info[s] = list_bad ? kBadList : (s_timeout ? kTimeout : ((b0 == kBadNone) ? 0 : b0));
+  }
+  // Departure, off the critical path: every tile read all maps before the
+  // barrier after the exchange; the last one out resets the meeting point.
+  if (T > 1 && tid == 0) {
+    const unsigned gone = atomicAdd(&cnt[2 * grp + 1], 1u);
+    if (gone == (unsigned)T - 1) {
+      __hip_atomic_store(&cnt[2 * grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&cnt[2 * grp + 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 

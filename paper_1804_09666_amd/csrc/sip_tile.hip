@@ -210,9 +210,16 @@ __global__ __launch_bounds__(256) void bnorm_kernel(int64_t n, int64_t batch, in
        q += (int64_t)gridDim.x * 256) {
     const int64_t s = q % batch, part = q / batch;
     double m = 0.0;
-    for (int64_t i = part; i < n; i += parts) {
-      const double av = fabs(Y[i * ld + s]);
-      m = (av > m || av != av) ? av : m;
+    constexpr int U = 8;  // loads in flight per thread
+    for (int64_t i = part; i < n; i += U * parts) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t r = i + u * parts;
+        v[u] = r < n ? fabs(Y[r * ld + s]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) m = (v[u] > m || v[u] != v[u]) ? v[u] : m;
     }
     if (m != 0.0) atomic_max_nonneg(&fl.bnorm[s], m);
   }
@@ -360,8 +367,9 @@ hipError_t launch_sip_tile(int64_t n, int64_t batch, int64_t ld, Diags A, const 
 
   hipLaunchKernelGGL(init_kernel, dim3(grid_for(batch, 256)), dim3(256), 0, st, batch, fl, iters,
                      relres, info, (int)own_factors);
-  hipLaunchKernelGGL(bnorm_kernel, dim3(grid_for(n * batch, 256)), dim3(256), 0, st, n, batch,
-                     ld, y, fl);
+  // about 32 rows per thread: few atomics per system, enough blocks in flight
+  hipLaunchKernelGGL(bnorm_kernel, dim3(grid_for(batch * ((n + 31) / 32), 256)), dim3(256), 0, st,
+                     n, batch, ld, y, fl);
   hipLaunchKernelGGL(start_kernel, dim3(grid_for(batch, 256)), dim3(256), 0, st, batch, fl, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
