@@ -90,6 +90,46 @@ def timed_solves(sets, kind, steps, warmup, ws_buf, xs, info):
     return t_all0.elapsed_time(t_all1), per
 
 
+def graph_solves(sets, kind, steps, ws_buf, xs, info):
+    """The same `steps` solves captured once in a HIP graph (rotating input
+    sets baked in); one untimed replay, then one timed replay.  Returns ms."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for k in range(steps):
+                t = sets[k % len(sets)]
+                bs.solve(diags_of(t, kind), t["y"], xs[k % len(xs)], kind=kind, batch=BATCH,
+                         info=info, workspace=ws_buf, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    del g
+    return e0.elapsed_time(e1)
+
+
+def stream_ceiling(sets, reps=20):
+    """GB/s of the library's plain streaming kernel over the same six input
+    arrays and one output (the fused PD solve's bytes), rotating the sets."""
+    keys = ("e", "c", "d", "a", "b", "y")
+    k = [0]
+    outs = [torch.empty_like(sets[0]["y"]) for _ in range(2)]
+
+    def run():
+        t = sets[k[0] % len(sets)]
+        out = outs[k[0] % 2]
+        k[0] += 1
+        bs.stream_probe([t[q] for q in keys], out)
+    ms = t_ms(run, reps=reps)
+    return PD_BYTES_PER_ROW * N_ROWS * BATCH / ms / 1e6
+
+
 def traffic_from_profile():
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source; else None."""
@@ -158,6 +198,40 @@ def t_ms(fn, reps=5):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def r_sensitivity_rows(rs=(1.0, 64.0, 2047.0)):
+    """The sweep batch at other r = tau/h^2 (the condition number grows from
+    ~10 to ~1e6 with r): split-row solve time, and the sampled solutions of
+    the split kernel and of the one-lane (sequential-recurrence) kernel, whose
+    errors against the oracle the caller fills in."""
+    KEYS = ("e", "c", "d", "a", "b", "y")
+    idx = np.arange(0, BATCH, 97)
+    out, got, samples = {}, {}, {}
+    for r in rs:
+        pd = wl.config1(r=r, N=N_ROWS)[0]
+        t = to_dev(pd)
+        x = torch.empty_like(t["y"])
+        info = torch.empty(BATCH, dtype=torch.int32, device="cuda")
+        nb = bs.workspace_bytes(bs.OP_SOLVE, 5, N_ROWS, BATCH)
+        wsb = torch.zeros(max(nb, 8) // 8, dtype=torch.float64, device="cuda")
+        ms = t_ms(lambda: bs.solve(diags_of(t, 5), t["y"], x, batch=BATCH, info=info,
+                                   workspace=wsb), reps=10)
+        ok = bool((info == 0).all())
+        xs = wl.deinterleave(x.cpu().numpy(), BATCH)[idx]
+        bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_LANE)
+        try:
+            xl, il = bs.solve(diags_of(t, 5), t["y"], batch=BATCH)
+        finally:
+            bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_AUTO)
+        ok = ok and bool((il == 0).all())
+        name = f"r{r:g}"
+        out[name] = {"r": r, "split_us": ms * 1e3, "info_ok": ok}
+        got[name] = {"split": xs, "lane": wl.deinterleave(xl.cpu().numpy(), BATCH)[idx]}
+        samples["r_" + name] = {k: pd[k][idx] for k in KEYS}
+        del t, x, xl, wsb, pd
+        torch.cuda.empty_cache()
+    return out, got, samples
 
 
 def precision_rows():
@@ -718,8 +792,12 @@ def main():
     nb = bs.workspace_bytes(bs.OP_SOLVE, 5, N_ROWS, BATCH)
     ws_buf = torch.zeros(max(nb, 8) // 8, dtype=torch.float64, device="cuda")
     log(f"timing {args.steps} steps after {args.warmup} warm-up steps")
-    total_ms, per = timed_solves(sets, 5, args.steps, args.warmup, ws_buf, xs, info)
+    eager_ms, per = timed_solves(sets, 5, args.steps, args.warmup, ws_buf, xs, info)
     ok = bool((info == 0).all())
+    log("the same steps as one captured graph")
+    total_ms = graph_solves(sets, 5, args.steps, ws_buf, xs, info)
+    ok = ok and bool((info == 0).all())
+    ceiling = stream_ceiling(sets)
     idx = np.arange(0, BATCH, 97)
     x_last = wl.deinterleave(xs[(args.steps - 1) % ROTATE].cpu().numpy(), BATCH)[idx]
     ms_step = total_ms / args.steps
@@ -746,6 +824,11 @@ def main():
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
                      "traffic": traffic_from_profile()},
         "hbm_GBps_algorithmic": alg_bytes / (ms_step * 1e-3) / 1e9,
+        "timing": "one HIP graph of the timed steps (rotating 4 input sets); eager launches "
+                  "beside it",
+        "eager_ms_per_step": eager_ms / args.steps,
+        "stream_ceiling_GBps": ceiling,
+        "frac_of_stream_ceiling": achieved / ceiling,
         "kernel_us_mean": kern_ms * 1e3,
         "kernel_us_p10_p90": [float(np.percentile(per, 10) * 1e3),
                               float(np.percentile(per, 90) * 1e3)],
@@ -766,6 +849,9 @@ def main():
         log("uneven batch (10 000 systems, n log-uniform in [64, 65536])")
         line["uneven_batch"], vl_x, vl_samples = varlen_rows()
         samples.update(vl_samples)
+        log("the sweep batch at r = 1, 64, 2047")
+        line["r_sensitivity"], rs_x, rs_samples = r_sensitivity_rows()
+        samples.update(rs_samples)
     if not args.no_cpu:
         log("timing the CPU oracle")
         line["cpu_baseline"], refs = cpu_baseline(pd, samples)
@@ -776,6 +862,9 @@ def main():
         if not args.no_rows:
             line["uneven_batch"]["sampled_err_vs_oracle"] = max(
                 rel(xv, refs[k]) for k, xv in vl_x.items())
+            for name, xsamp in rs_x.items():
+                for key, xv in xsamp.items():
+                    line["r_sensitivity"][name][f"{key}_err_vs_oracle"] = rel(xv, refs["r_" + name])
             for name, xsamp in prec_x.items():
                 ref = refs["prec_" + name]
                 for key, xv in xsamp.items():

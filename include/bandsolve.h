@@ -330,6 +330,15 @@ int32_t bs_varlen_tune(int32_t kind, const bs_varlen_info* vinfo, const void* ta
                        void* workspace, size_t ws_bytes, int32_t reps, float* ms,
                        int32_t* best, void* stream);
 
+/* Measurement helper, not a solver: out[i] = in[0][i] + ... + in[nin-1][i]
+ * for i < count, as one streaming pass (16-byte non-temporal loads and
+ * stores, no dependence between elements).  With nin = 6 it moves the bytes
+ * of the fused PD solve (six arrays read, one written), so its rate is the
+ * practical HBM ceiling of that traffic pattern on the device.  Device
+ * pointers, 16-byte aligned; count even, 1 <= nin <= 6.  BS_EINVAL otherwise. */
+int32_t bs_stream_probe(int64_t count, int32_t nin, const double* const in[6], double* out,
+                        void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,7 @@ EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "bs_set_option"
             "band_solve_refine", "band_solve_adi", "band_solve_mnpdm", "sip_solve",
             "bs_varlen_variants",
             "bs_varlen_variant_shape", "bs_varlen_layout", "bs_varlen_workspace_bytes",
-            "band_solve_varlen", "bs_varlen_tune")
+            "band_solve_varlen", "bs_varlen_tune", "bs_stream_probe")
 OPT_DIRECT_PATH, OPT_PART_PD_VARIANT, OPT_PART_TD_VARIANT, OPT_SIP_PATH = range(4)
 PATH_AUTO, PATH_LANE, PATH_PART = range(3)
 
@@ -85,6 +85,7 @@ def load():
         "bs_varlen_workspace_bytes": (sz, [i32, vip, i32]),
         "band_solve_varlen": (i32, [i32, vip, vp, i32, vp5, vp, vp, vp, vp, sz, vp]),
         "bs_varlen_tune": (i32, [i32, vip, vp, vp5, vp, vp, vp, vp, sz, i32, vp, vp, vp]),
+        "bs_stream_probe": (i32, [i64, i32, ctypes.c_void_p * 6, vp, vp]),
     })
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -116,6 +117,16 @@ def part_variants(kind):
     shape = (ctypes.c_int32 * 4)()
     while load().bs_part_variant(kind, len(out), shape) == BS_OK:
         out.append(tuple(shape))
+    return out
+
+
+def stream_probe(inputs, out, stream=None):
+    """out = sum(inputs) elementwise in one streaming pass (a measurement of the
+    HBM ceiling of the solvers' traffic pattern; 1..6 FP64 inputs)."""
+    lib = load()
+    arr = (ctypes.c_void_p * 6)(*[_ptr(t) for t in inputs])
+    st = lib.bs_stream_probe(out.numel(), len(inputs), arr, _ptr(out), _stream(stream))
+    _raise(st, "bs_stream_probe")
     return out
 
 

@@ -424,4 +424,15 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
                                       hb_s_L, hb_s_U, iters, relres, info, rest, st));
 }
 
+int32_t bs_stream_probe(int64_t count, int32_t nin, const double* const in[6], double* out,
+                        void* stream) {
+  if (count < 2 || count % 2 != 0 || nin < 1 || nin > 6 || in == nullptr || out == nullptr ||
+      !aligned(out, 16))
+    return BS_EINVAL;
+  for (int k = 0; k < nin; ++k)
+    if (in[k] == nullptr || !aligned(in[k], 16)) return BS_EINVAL;
+  if (!have_device()) return BS_ENODEV;
+  return launched(bs::launch_stream_probe(count, nin, in, out, static_cast<hipStream_t>(stream)));
+}
+
 }  // extern "C"

@@ -124,4 +124,9 @@ hipError_t launch_sip_tile(int64_t n, int64_t batch, int64_t ld, Diags A, const 
                            int32_t max_iter, int32_t sL, int32_t sU, int32_t* iters,
                            double* relres, int32_t* info, void* ws, hipStream_t st);
 
+// ---- measurement (stream_probe.hip) -------------------------------------
+// out = in_0 + ... + in_{nin-1} elementwise (count even, 16-byte aligned).
+hipError_t launch_stream_probe(int64_t count, int nin, const double* const* in, double* out,
+                               hipStream_t st);
+
 }  // namespace bs

@@ -20,10 +20,10 @@
 // One launch per step.  The convergence test must see the whole residual of
 // a system, which spans many blocks, so a step reads x_k from one buffer,
 // accumulates ||b - A x_k||_inf per system, and always writes the candidate
-// x_{k+1} to the other buffer; a one-block status kernel then decides, per
-// system, whether x_k was already the answer (the candidate is dropped), the
-// step count, the status, and a device flag that makes the remaining
-// launches return at once.
+// x_{k+1} to the other buffer; the last block of the step to finish (an
+// arrival counter) then decides, per system, whether x_k was already the
+// answer (the candidate is dropped), the step count, the status, and a device
+// flag that makes the remaining launches return at once.
 #include "bs_internal.h"
 
 // Products and sums may contract into FMAs, and the upper sweeps multiply by
@@ -54,18 +54,49 @@ struct Flags {
   unsigned long long* bnorm;   // ||b||_inf (bits)
   double* relres0;
   int32_t* done;
+  unsigned* arrive;            // blocks of the step in flight that have finished
 };
+
+// Algorithm 1's loop test for system s after step k has accumulated
+// ||b - A x_k||: returns 1 to keep stepping, else records the outcome.
+__device__ inline int sip_status(int64_t s, int32_t k, int32_t max_iter, double tol, Flags fl,
+                                 int32_t* __restrict__ iters, double* __restrict__ relres,
+                                 int32_t* __restrict__ info) {
+  const double rn = as_double(__hip_atomic_exchange(&fl.accum[s], 0ull, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT));
+  const double bn = as_double(fl.bnorm[s]);
+  const double rr = rn / bn;
+  if (k == 0) fl.relres0[s] = rr;
+  int status = 1;  // 1: keep stepping
+  if (!isfinite(rr))
+    status = -2;
+  else if (!(rn >= tol * bn))
+    status = 0;
+  else if (rr > 1e3 * fmax(1.0, fl.relres0[s]))
+    status = -2;
+  else if (k == max_iter)
+    status = -1;
+  if (status == 1) return 1;
+  fl.active[s] = 0;
+  fl.fin[s] = k & 1;  // x_k is in buffer k mod 2
+  iters[s] = k;
+  relres[s] = rr;
+  info[s] = status;
+  return 0;
+}
 
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void sip_step_kernel(
     int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
     const double* __restrict__ C, const double* __restrict__ D, const double* __restrict__ A,
     const double* __restrict__ B, const double* __restrict__ F, int64_t fld,
     const double* __restrict__ Y, const double* __restrict__ Xin, double* __restrict__ Xout,
-    int KL, int KU, int HL, int RC, int T, Flags fl) {
+    int KL, int KU, int HL, int RC, int T, Flags fl, int32_t k, int32_t max_iter, double tol,
+    int32_t* __restrict__ iters, double* __restrict__ relres, int32_t* __restrict__ info) {
   if (*fl.done) return;
   __shared__ double s_lo[2][kPW][kG][2];  // first two rows of every lane
   __shared__ double s_hi[2][kPW][kG][2];  // last two rows of every lane
   __shared__ unsigned long long s_m[kG];
+  __shared__ int s_last, s_any;
 
   const int tid = threadIdx.x;
   const int g = tid % kG;
@@ -199,7 +230,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
   }
   __syncthreads();
-  if (j == 0 && live) atomicMax(&fl.accum[s], s_m[g]);
+  // ---- the last block of the step applies the test for every system ------
+  if (tid < 64) {  // wave 0: this block's maxima, then its arrival
+    unsigned long long seen = 0;
+    if (j == 0 && live) seen = atomicMax(&fl.accum[s], s_m[g]);
+    // the arrival waits for the returned maxima (one instruction for the
+    // wave): every maximum of this block is in place before it counts
+    if (tid == 0 && seen != ~0ull) {
+      const unsigned old = atomicAdd(fl.arrive, 1u);
+      s_last = old == gridDim.x - 1;
+      s_any = 0;
+    }
+  }
+  __syncthreads();
+  if (!s_last) return;
+  for (int64_t q = tid; q < batch; q += kThreads)
+    if (fl.active[q] && sip_status(q, k, max_iter, tol, fl, iters, relres, info)) s_any = 1;
+  __syncthreads();
+  if (tid == 0) {
+    __hip_atomic_store(fl.arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!s_any) *fl.done = 1;
+  }
 }
 
 // ||b||_inf per system (bits into bnorm, zeroed by init_kernel).
@@ -238,7 +289,10 @@ __global__ void init_kernel(int64_t batch, Flags fl, int32_t* iters, double* rel
     relres[s] = 0.0;
     if (!own_factors) info[s] = 0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *fl.done = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *fl.done = 0;
+    *fl.arrive = 0u;
+  }
 }
 
 // After the factorization and ||b||: which systems step at all.
@@ -252,47 +306,6 @@ __global__ void start_kernel(int64_t batch, Flags fl, int32_t* info) {
     }
     fl.active[s] = 1;
   }
-}
-
-// Step k has accumulated ||b - A x_k||: the test of Algorithm 1's loop.
-__global__ __launch_bounds__(1024) void status_kernel(int64_t batch, double tol, int32_t k,
-                                                      int32_t max_iter, Flags fl,
-                                                      int32_t* __restrict__ iters,
-                                                      double* __restrict__ relres,
-                                                      int32_t* __restrict__ info) {
-  __shared__ int s_any;
-  if (threadIdx.x == 0) s_any = 0;
-  __syncthreads();
-  if (!*fl.done) {
-    for (int64_t s = threadIdx.x; s < batch; s += blockDim.x) {
-      if (!fl.active[s]) continue;
-      const double rn = as_double(fl.accum[s]);
-      const double bn = as_double(fl.bnorm[s]);
-      fl.accum[s] = 0ull;
-      const double rr = rn / bn;
-      if (k == 0) fl.relres0[s] = rr;
-      int status = 1;  // 1: keep stepping
-      if (!isfinite(rr))
-        status = -2;
-      else if (!(rn >= tol * bn))
-        status = 0;
-      else if (rr > 1e3 * fmax(1.0, fl.relres0[s]))
-        status = -2;
-      else if (k == max_iter)
-        status = -1;
-      if (status == 1) {
-        s_any = 1;
-        continue;
-      }
-      fl.active[s] = 0;
-      fl.fin[s] = k & 1;  // x_k is in buffer k mod 2
-      iters[s] = k;
-      relres[s] = rr;
-      info[s] = status;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0 && !*fl.done && !s_any) *fl.done = 1;
 }
 
 // The answer of every system into the caller's x.
@@ -314,7 +327,7 @@ int grid_for(int64_t work, int block) {
 }
 
 struct Layout {
-  size_t x1, active, fin, accum, bnorm, relres0, done, total;
+  size_t x1, active, fin, accum, bnorm, relres0, done, arrive, total;
 };
 
 Layout layout(int64_t n, int64_t batch, int64_t ld) {
@@ -328,6 +341,7 @@ Layout layout(int64_t n, int64_t batch, int64_t ld) {
   L.bnorm = o;   o = up(o + (size_t)batch * 8);
   L.relres0 = o; o = up(o + (size_t)batch * 8);
   L.done = o;    o = up(o + 4);
+  L.arrive = o;  o = up(o + 4);
   L.total = o;
   return L;
 }
@@ -359,6 +373,7 @@ hipError_t launch_sip_tile(int64_t n, int64_t batch, int64_t ld, Diags A, const 
   fl.bnorm = reinterpret_cast<unsigned long long*>(base + L.bnorm);
   fl.relres0 = reinterpret_cast<double*>(base + L.relres0);
   fl.done = reinterpret_cast<int32_t*>(base + L.done);
+  fl.arrive = reinterpret_cast<unsigned*>(base + L.arrive);
   const int KL = (1 << sL) - 1, KU = (1 << sU) - 1;
   const int HL = 2 * KL + 2, HR = 2 * KU + 2;
   const int RC = kE - HL - HR;
@@ -378,9 +393,7 @@ hipError_t launch_sip_tile(int64_t n, int64_t batch, int64_t ld, Diags A, const 
     double* xout = (k & 1) ? x : x1;
     hipLaunchKernelGGL(sip_step_kernel, dim3((unsigned)(groups * T)), dim3(kThreads), 0, st, n,
                        batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, y, xin, xout, KL, KU, HL,
-                       RC, (int)T, fl);
-    hipLaunchKernelGGL(status_kernel, dim3(1), dim3(1024), 0, st, batch, tol, k, max_iter, fl,
-                       iters, relres, info);
+                       RC, (int)T, fl, k, max_iter, tol, iters, relres, info);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

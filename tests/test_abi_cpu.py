@@ -253,3 +253,17 @@ def test_warmstart_symbols_and_host_checks(bs):
     norm = (ctypes.c_float * 14)(*([0.0] * 7 + [1.0] * 6 + [0.0]))                    # scale 0
     assert lib.ws_features(2, 64, 4, 4, planes, norm, a, None) == E
     assert lib.ws_apply(64, 4, 3, a, b, 0.0, 1.0, c, None) == E                       # ld < batch
+
+
+def test_stream_probe_rejections_on_host(bs):
+    lib = bs.load()
+    arr = (ctypes.c_void_p * 6)(*[_fake(k) for k in range(6)])
+    out = _fake(7)
+    E = bs.BS_EINVAL
+    assert lib.bs_stream_probe(1001, 6, arr, out, None) == E      # odd count
+    assert lib.bs_stream_probe(0, 6, arr, out, None) == E
+    assert lib.bs_stream_probe(1000, 0, arr, out, None) == E
+    assert lib.bs_stream_probe(1000, 7, arr, out, None) == E
+    assert lib.bs_stream_probe(1000, 6, arr, ctypes.c_void_p(0x10008), None) == E
+    bad = (ctypes.c_void_p * 6)(*([_fake(k) for k in range(5)] + [None]))
+    assert lib.bs_stream_probe(1000, 6, bad, out, None) == E

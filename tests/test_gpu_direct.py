@@ -272,3 +272,19 @@ def test_mnpdm_random_lists(n, batch, ld, kmax, path):
         assert torch.equal(x[:, :batch], xn[:, :batch])
     xr, _ = oracle.npdm_batch(ws["e"], ws["c"], ws["d"], ws["a"], ws["b"], ws["y"])
     assert rel_err(host(x, batch), xr).max() <= TOL
+
+
+def test_stream_probe_sums():
+    """The streaming ceiling probe computes what it claims (it is timed by the
+    benchmark against the solver's traffic pattern)."""
+    g = torch.Generator(device="cuda").manual_seed(3)
+    ins = [torch.rand(2 * 12345, dtype=torch.float64, device="cuda", generator=g)
+           for _ in range(6)]
+    for k in (1, 3, 6):
+        out = torch.empty_like(ins[0])
+        bs.stream_probe(ins[:k], out)
+        ref = ins[0].clone()
+        for t in ins[1:k]:
+            ref += t
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
