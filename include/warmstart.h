@@ -76,6 +76,15 @@ int32_t ws_forward(int32_t dtype, int64_t P, const void* X, const float* params3
                    const void* paramsT, float* Y, void* workspace, size_t ws_bytes,
                    void* stream);
 
+/* Inference only, BF16 (X and paramsT in bfloat16): Y[P, 64] (FP32) =
+ * network(X[P, 448]) with one kernel that carries each tile of patches
+ * through all four layers (activations in LDS, weights read from L2), so no
+ * activation goes to memory and no workspace is needed.  The rounding points
+ * and the order of the FP32 accumulations are those of ws_forward with
+ * WS_BF16, whose result it reproduces.  All pointers 16-byte aligned. */
+int32_t ws_infer(int64_t P, const void* X, const float* params32, const void* paramsT, float* Y,
+                 void* stream);
+
 /* Gradient of a loss w.r.t. the parameters (FP32, ws_param_count()
  * elements, overwritten) given dL/dY (FP32 [P, 64]), after ws_forward on the
  * same X, parameters and workspace (WS_OP_TRAIN size).  P must be a multiple

@@ -183,6 +183,141 @@ __global__ __launch_bounds__(kThreads) void gemm_nt_kernel(int64_t M, int64_t N,
     }
 }
 
+// ---- the whole network for a tile of patches (inference) ------------------
+// One block carries 32 RT patches through all four layers.  The layer input
+// sits in LDS (bf16, [32 RT][kFLD]); each wave computes 128 of the 512 output
+// columns (RT x 4 MFMA tiles of 32 x 32) with its weight fragments read
+// straight from global memory: the 1.5 MB of weights stay in every XCD's L2,
+// and a wave fetches the fragments of four k-steps together (a whole 128-byte
+// line of each of its weight rows) while the matrix cores work on the four
+// before.  Then the block writes relu(acc + b) back over the input as bf16
+// and moves on; the last layer's 64 columns go to Y in FP32.  The MFMAs of a
+// tile accumulate k in the same order as gemm_nt_kernel, and the rounding
+// points (bf16 activations, FP32 accumulation, bias then ReLU) are the same,
+// so Y is the layered forward pass's.
+constexpr int kFRT = 3;              // row tiles of 32 patches per block
+constexpr int kFR = 32 * kFRT;       // patches per block
+constexpr int kFLD = WS_HIDDEN + 8;  // LDS row pitch in bf16 (16 bytes of padding)
+
+__global__ __launch_bounds__(kThreads, 1) void mlp_infer_kernel(int64_t P, const bf16* __restrict__ X,
+                                                                const bf16* __restrict__ W,
+                                                                const float* __restrict__ p32,
+                                                                float* __restrict__ Y) {
+  constexpr int RT = kFRT;
+  __shared__ __attribute__((aligned(16))) bf16 sH[kFR * kFLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int hi = lane >> 5, lo = lane & 31;
+  const int64_t p0 = (int64_t)blockIdx.x * kFR;
+  {  // the input tile: 448 features = 56 chunks of 16 bytes per patch
+    constexpr int CPR = WS_IN / 8;
+    for (int c = tid; c < kFR * CPR; c += kThreads) {
+      const int r = c / CPR, kc = (c % CPR) * 8;
+      Vec16 v = Vec16{0u, 0u, 0u, 0u};
+      if (p0 + r < P) v = *reinterpret_cast<const Vec16*>(X + (p0 + r) * WS_IN + kc);
+      *reinterpret_cast<Vec16*>(&sH[r * kFLD + kc]) = v;
+    }
+  }
+  __syncthreads();
+  int64_t wo = 0;  // offset of this layer's W (then b) in the parameter vector
+  for (int layer = 0; layer < 3; ++layer) {
+    const int K = layer == 0 ? WS_IN : WS_HIDDEN;  // a multiple of 64
+    const bf16* Wl = W + wo;
+    const float* bl = p32 + wo + (int64_t)WS_HIDDEN * K;
+    const int n0 = wave * 128;
+    f32x16 acc[RT][4];
+#pragma unroll
+    for (int i = 0; i < RT; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
+    const bf16* wrow[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) wrow[j] = Wl + (int64_t)(n0 + 32 * j + lo) * K + hi * 8;
+    // fragments of four k-steps (64 values of k) per buffer
+    bf16x8 fb[2][4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fb[0][q][j] = *reinterpret_cast<const bf16x8*>(wrow[j] + 16 * q);
+    for (int kg = 0; kg < K; kg += 128) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k0 = kg + 64 * h;
+        if (k0 + 64 < K) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+              fb[h ^ 1][q][j] = *reinterpret_cast<const bf16x8*>(wrow[j] + k0 + 64 + 16 * q);
+        }
+        if (k0 < K) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int k = k0 + 16 * q;
+            bf16x8 fa[RT];
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+              fa[i] = *reinterpret_cast<const bf16x8*>(&sH[(32 * i + lo) * kFLD + k + hi * 8]);
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+              for (int j = 0; j < 4; ++j)
+                acc[i][j] =
+                    __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[h][q][j], acc[i][j], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();  // every wave has read the layer input
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = n0 + 32 * j + lo;
+      const float bv = bl[col];
+#pragma unroll
+      for (int i = 0; i < RT; ++i)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = 32 * i + 8 * (v >> 2) + 4 * hi + (v & 3);
+          float val = acc[i][j][v] + bv;
+          val = val > 0.0f ? val : 0.0f;
+          sH[row * kFLD + col] = (bf16)val;
+        }
+    }
+    __syncthreads();
+    wo += (int64_t)WS_HIDDEN * K + WS_HIDDEN;
+  }
+  // output layer: (32 RT) x 64; wave w takes row tiles w, w + 4, ... and both column tiles
+  {
+    const int K = WS_HIDDEN;
+    const float* bl = p32 + wo + (int64_t)WS_OUT * K;
+    const bf16* wr0 = W + wo + (int64_t)lo * K + hi * 8;
+    const bf16* wr1 = wr0 + (int64_t)32 * K;
+    for (int ti = wave; ti < RT; ti += 4) {
+      f32x16 acc0, acc1;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc0[v] = acc1[v] = 0.0f;
+#pragma unroll 4
+      for (int k = 0; k < K; k += 16) {
+        const bf16x8 fa = *reinterpret_cast<const bf16x8*>(&sH[(32 * ti + lo) * kFLD + k + hi * 8]);
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, *reinterpret_cast<const bf16x8*>(wr0 + k),
+                                                       acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa, *reinterpret_cast<const bf16x8*>(wr1 + k),
+                                                       acc1, 0, 0, 0);
+      }
+      const float b0 = bl[lo], b1 = bl[32 + lo];
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = p0 + 32 * ti + 8 * (v >> 2) + 4 * hi + (v & 3);
+        if (row < P) {
+          Y[row * WS_OUT + lo] = acc0[v] + b0;
+          Y[row * WS_OUT + 32 + lo] = acc1[v] + b1;
+        }
+      }
+    }
+  }
+}
+
 // out[C, R] = in[R, C]^T through a 32 x 32 LDS tile.
 template <typename T>
 __global__ __launch_bounds__(256) void transpose_kernel(int64_t R, int64_t C,
@@ -584,6 +719,17 @@ int32_t ws_forward(int32_t dtype, int64_t P, const void* X, const float* params3
   hipError_t e = dtype == WS_BF16 ? forward<bf16>(P, X, params32, paramsT, Y, ws, st)
                                   : forward<float>(P, X, params32, paramsT, Y, ws, st);
   return e == hipSuccess ? BS_OK : BS_ELAUNCH;
+}
+
+int32_t ws_infer(int64_t P, const void* X, const float* params32, const void* paramsT, float* Y,
+                 void* stream) {
+  if (P < 1 || P > (int64_t(1) << 31) || (P + kFR - 1) / kFR > (int64_t(1) << 31) - 1)
+    return BS_EINVAL;
+  if (!al16(X) || !al16(params32) || !al16(paramsT) || !al16(Y)) return BS_EINVAL;
+  hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)((P + kFR - 1) / kFR)), dim3(kThreads), 0,
+                     static_cast<hipStream_t>(stream), P, static_cast<const bf16*>(X),
+                     static_cast<const bf16*>(paramsT), params32, Y);
+  return hipGetLastError() == hipSuccess ? BS_OK : BS_ELAUNCH;
 }
 
 int32_t ws_backward(int32_t dtype, int64_t P, const void* X, const float* params32,

@@ -25,7 +25,7 @@ WS_F32, WS_BF16 = 1, 2
 OP_FORWARD, OP_TRAIN = 0, 1
 PATCH, NFEAT, IN, HIDDEN, OUT = 64, 7, 448, 512, 64
 EXPORTED = ("ws_param_count", "ws_workspace_bytes", "ws_gemm_nt", "ws_convert", "ws_forward",
-            "ws_backward", "ws_mse", "ws_adam", "ws_features", "ws_apply")
+            "ws_infer", "ws_backward", "ws_mse", "ws_adam", "ws_features", "ws_apply")
 TORCH_DTYPE = {WS_F32: torch.float32, WS_BF16: torch.bfloat16}
 
 _lib = None
@@ -44,6 +44,7 @@ def load():
         "ws_gemm_nt": (i32, [i32, i64, i64, i64, vp, vp, vp, i32, vp, vp, vp, vp]),
         "ws_convert": (i32, [i32, i64, vp, vp, vp]),
         "ws_forward": (i32, [i32, i64, vp, vp, vp, vp, vp, sz, vp]),
+        "ws_infer": (i32, [i64, vp, vp, vp, vp, vp]),
         "ws_backward": (i32, [i32, i64, vp, vp, vp, vp, vp, vp, sz, vp]),
         "ws_mse": (i32, [i64, vp, vp, vp, vp, vp, vp]),
         "ws_adam": (i32, [i32, i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]),
@@ -106,6 +107,15 @@ def forward(dtype, X, p32, pT, Y=None, ws=None, stream=None):
     ws = workspace(OP_FORWARD, dtype, P, X.device) if ws is None else ws
     _ok(load().ws_forward(dtype, P, _p(X), _p(p32), _p(pT), _p(Y), _p(ws),
                           ws.numel() * ws.element_size(), _st(stream)), "ws_forward")
+    return Y
+
+
+def infer(X, p32, pT, Y=None, stream=None):
+    """Y = network(X) for BF16 X and weights in one fused kernel (no workspace;
+    the same result as forward(WS_BF16, ...))."""
+    P = X.shape[0]
+    Y = torch.empty((P, OUT), dtype=torch.float32, device=X.device) if Y is None else Y
+    _ok(load().ws_infer(P, _p(X), _p(p32), _p(pT), _p(Y), _st(stream)), "ws_infer")
     return Y
 
 
@@ -225,7 +235,10 @@ class WarmStart:
         """x0 for a batch of pentadiagonal systems (device [n, ld] float64)."""
         planes = list(diags) + [rhs, uprev]
         X = features(self.dtype, planes, self.norm, n, batch, X)
-        Y = forward(self.dtype, X, self.p32, self.pT, Y, ws)
+        if self.dtype == WS_BF16:
+            Y = infer(X, self.p32, self.pT, Y)
+        else:
+            Y = forward(self.dtype, X, self.p32, self.pT, Y, ws)
         return apply(Y, uprev, self.mu_t, self.sigma_t, n, batch, x0)
 
 

@@ -248,6 +248,9 @@ def test_warmstart_symbols_and_host_checks(bs):
     assert lib.ws_backward(2, 12, a, b, c, a, b, c, ws_need, None) == E                # P % 8
     assert lib.ws_backward(2, 16, a, b, c, a, b, c, ws_need - 1, None) == bs.BS_EWORKSPACE
     assert lib.ws_forward(2, 16, a, b, c, a, c, 0, None) == bs.BS_EWORKSPACE
+    assert lib.ws_infer(0, a, b, c, a, None) == E                                     # P < 1
+    assert lib.ws_infer(16, mis, b, c, a, None) == E
+    assert lib.ws_infer(16, a, b, None, a, None) == E
     assert lib.ws_adam(2, 10, a, None, b, c, a, 1e-3, 0.9, 0.999, 1e-8, 0, None) == E  # step 0
     planes = (ctypes.c_void_p * 7)(*[_fake(k) for k in range(7)])
     norm = (ctypes.c_float * 14)(*([0.0] * 7 + [1.0] * 6 + [0.0]))                    # scale 0

@@ -183,3 +183,23 @@ def test_learned_start_reduces_sip_iterations():
     mean = {k: float(np.mean(v)) for k, v in its.items()}
     say(f"mean SIP iterations to 1e-10: {mean}")
     assert mean["learned"] < mean["prev"] < mean["zero"]
+
+
+@pytest.mark.parametrize("P", [1, 63, 64, 200, 4096 + 17])
+def test_fused_inference_matches_layered_forward(P):
+    """The one-kernel inference against the layered matrix-core forward pass
+    (same rounding points and accumulation order) and against the oracle."""
+    p, X, _ = _problem(P, 13)
+    X = mo.bf16_round(X)
+    p32 = dev(p)
+    pT = wsm.convert(p32, wsm.WS_BF16)
+    Xt = dev(X, torch.bfloat16)
+    say(f"fused inference P={P}")
+    Yf = wsm.infer(Xt, p32, pT)
+    Yl = wsm.forward(wsm.WS_BF16, Xt, p32, pT)
+    torch.cuda.synchronize()
+    d = (Yf - Yl).abs().max().item()
+    say(f"  max |fused - layered| = {d:.3e}")
+    assert torch.equal(Yf, Yl)
+    Yo, _ = mo.forward(X, p, bf16=True)
+    assert np.abs(host(Yf) - Yo).max() <= 3e-2 * np.abs(Yo).max()
