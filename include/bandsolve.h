@@ -330,6 +330,19 @@ int32_t bs_varlen_tune(int32_t kind, const bs_varlen_info* vinfo, const void* ta
                        void* workspace, size_t ws_bytes, int32_t reps, float* ms,
                        int32_t* best, void* stream);
 
+/* Layout conversion for callers whose lines are system-contiguous (the
+ * lines along the fast axis of a row-major grid, as in the ADI sweeps of
+ * Sec. 1): bs_pack_interleave writes dst[i*ld + s] = src[s*src_pitch + i]
+ * and bs_unpack_interleave writes dst[s*dst_pitch + i] = src[i*ld + s], for
+ * i < n, s < batch (FP64, device pointers, 8-byte aligned; the padding
+ * columns s >= batch of an interleaved array are neither read nor written).
+ * BS_EINVAL for n or batch < 1, ld < batch, a pitch < n, NULL pointers or
+ * n, batch >= 2^26. */
+int32_t bs_pack_interleave(int64_t n, int64_t batch, const double* src, int64_t src_pitch,
+                           double* dst, int64_t ld, void* stream);
+int32_t bs_unpack_interleave(int64_t n, int64_t batch, const double* src, int64_t ld,
+                             double* dst, int64_t dst_pitch, void* stream);
+
 /* Measurement helper, not a solver: out[i] = in[0][i] + ... + in[nin-1][i]
  * for i < count, as one streaming pass (16-byte non-temporal loads and
  * stores, no dependence between elements).  With nin = 6 it moves the bytes

@@ -29,7 +29,8 @@ EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "bs_set_option"
             "band_solve_refine", "band_solve_adi", "band_solve_mnpdm", "sip_solve",
             "bs_varlen_variants",
             "bs_varlen_variant_shape", "bs_varlen_layout", "bs_varlen_workspace_bytes",
-            "band_solve_varlen", "bs_varlen_tune", "bs_stream_probe")
+            "band_solve_varlen", "bs_varlen_tune", "bs_pack_interleave", "bs_unpack_interleave",
+            "bs_stream_probe")
 OPT_DIRECT_PATH, OPT_PART_PD_VARIANT, OPT_PART_TD_VARIANT, OPT_SIP_PATH = range(4)
 PATH_AUTO, PATH_LANE, PATH_PART = range(3)
 
@@ -86,6 +87,8 @@ def load():
         "band_solve_varlen": (i32, [i32, vip, vp, i32, vp5, vp, vp, vp, vp, sz, vp]),
         "bs_varlen_tune": (i32, [i32, vip, vp, vp5, vp, vp, vp, vp, sz, i32, vp, vp, vp]),
         "bs_stream_probe": (i32, [i64, i32, ctypes.c_void_p * 6, vp, vp]),
+        "bs_pack_interleave": (i32, [i64, i64, vp, i64, vp, i64, vp]),
+        "bs_unpack_interleave": (i32, [i64, i64, vp, i64, vp, i64, vp]),
     })
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -117,6 +120,34 @@ def part_variants(kind):
     shape = (ctypes.c_int32 * 4)()
     while load().bs_part_variant(kind, len(out), shape) == BS_OK:
         out.append(tuple(shape))
+    return out
+
+
+def pack_interleave(lines, ld=None, out=None, stream=None):
+    """[batch, n] system-contiguous FP64 lines (row stride >= n) -> the
+    interleaved [n, ld] layout of the solvers."""
+    batch, n = lines.shape
+    if lines.dtype != torch.float64 or lines.stride(1) != 1:
+        raise ValueError("pack_interleave: float64 lines with unit column stride")
+    ld = batch if ld is None else ld
+    out = torch.empty((n, ld), dtype=torch.float64, device=lines.device) if out is None else out
+    if out.shape != (n, ld) or not out.is_contiguous():
+        raise ValueError("pack_interleave: out must be a contiguous [n, ld] tensor")
+    _raise(load().bs_pack_interleave(n, batch, _ptr(lines), lines.stride(0), _ptr(out), ld,
+                                     _stream(stream)), "bs_pack_interleave")
+    return out
+
+
+def unpack_interleave(x, batch, out=None, stream=None):
+    """The interleaved [n, ld] layout -> [batch, n] system-contiguous lines."""
+    n, ld = x.shape
+    if x.dtype != torch.float64 or not x.is_contiguous():
+        raise ValueError("unpack_interleave: a contiguous float64 [n, ld] tensor")
+    out = torch.empty((batch, n), dtype=torch.float64, device=x.device) if out is None else out
+    if out.shape[0] != batch or out.shape[1] != n or out.stride(1) != 1:
+        raise ValueError("unpack_interleave: out must be [batch, n] with unit column stride")
+    _raise(load().bs_unpack_interleave(n, batch, _ptr(x), ld, _ptr(out), out.stride(0),
+                                       _stream(stream)), "bs_unpack_interleave")
     return out
 
 

@@ -424,6 +424,30 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
                                       hb_s_L, hb_s_U, iters, relres, info, rest, st));
 }
 
+static bool layout_ok(int64_t n, int64_t batch, int64_t ld, int64_t pitch, const void* a,
+                      const void* b) {
+  constexpr int64_t kMax = int64_t(1) << 26;
+  return n >= 1 && batch >= 1 && n < kMax && batch < kMax && ld >= batch && pitch >= n &&
+         a != nullptr && b != nullptr && aligned(a, 8) && aligned(b, 8);
+}
+
+int32_t bs_pack_interleave(int64_t n, int64_t batch, const double* src, int64_t src_pitch,
+                           double* dst, int64_t ld, void* stream) {
+  if (!layout_ok(n, batch, ld, src_pitch, src, dst)) return BS_EINVAL;
+  if (!have_device()) return BS_ENODEV;
+  // src is [batch][src_pitch]: R = batch rows of n columns
+  return launched(bs::launch_transpose64(batch, n, src, src_pitch, dst, ld,
+                                         static_cast<hipStream_t>(stream)));
+}
+
+int32_t bs_unpack_interleave(int64_t n, int64_t batch, const double* src, int64_t ld,
+                             double* dst, int64_t dst_pitch, void* stream) {
+  if (!layout_ok(n, batch, ld, dst_pitch, src, dst)) return BS_EINVAL;
+  if (!have_device()) return BS_ENODEV;
+  return launched(bs::launch_transpose64(n, batch, src, ld, dst, dst_pitch,
+                                         static_cast<hipStream_t>(stream)));
+}
+
 int32_t bs_stream_probe(int64_t count, int32_t nin, const double* const in[6], double* out,
                         void* stream) {
   if (count < 2 || count % 2 != 0 || nin < 1 || nin > 6 || in == nullptr || out == nullptr ||

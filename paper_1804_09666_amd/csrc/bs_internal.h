@@ -124,6 +124,11 @@ hipError_t launch_sip_tile(int64_t n, int64_t batch, int64_t ld, Diags A, const 
                            int32_t max_iter, int32_t sL, int32_t sU, int32_t* iters,
                            double* relres, int32_t* info, void* ws, hipStream_t st);
 
+// ---- layout conversion (layout.hip) -------------------------------------
+// dst[c * dpitch + r] = src[r * spitch + c] for r < R, c < C (R, C < 2^21 * 32).
+hipError_t launch_transpose64(int64_t R, int64_t C, const double* src, int64_t spitch,
+                              double* dst, int64_t dpitch, hipStream_t st);
+
 // ---- measurement (stream_probe.hip) -------------------------------------
 // out = in_0 + ... + in_{nin-1} elementwise (count even, 16-byte aligned).
 hipError_t launch_stream_probe(int64_t count, int nin, const double* const* in, double* out,

@@ -256,13 +256,13 @@ def adi_steps(N, r=4.0, seed=wl.BASE_SEED + 4, device="cuda"):
     info = torch.empty(N, dtype=torch.int32, device=device)
     step = 0
     while True:
-        vt = u.t().contiguous()                                  # x-lines: [x, y]
+        vt = bs.pack_interleave(u)                               # x-lines: [x, y]
         sw = wl.sweep_lines_interleaved(vt, r, 2)
         diags = [sw[k] for k in ("e", "c", "d", "a", "b")]
         w, _ = bs.solve(diags, sw["y"], kind=5, batch=N, info=info)
         yield step, diags + [sw["y"], w_prev if w_prev is not None else vt], w
         w_prev = w
-        sy = wl.sweep_lines_interleaved(w.t().contiguous(), r, 2)   # y-lines: [y, x]
+        sy = wl.sweep_lines_interleaved(bs.pack_interleave(w), r, 2)   # y-lines: [y, x]
         u, _ = bs.solve([sy[k] for k in ("e", "c", "d", "a", "b")], sy["y"], kind=5, batch=N,
                         info=info)
         step += 1

@@ -270,3 +270,16 @@ def test_stream_probe_rejections_on_host(bs):
     assert lib.bs_stream_probe(1000, 6, arr, ctypes.c_void_p(0x10008), None) == E
     bad = (ctypes.c_void_p * 6)(*([_fake(k) for k in range(5)] + [None]))
     assert lib.bs_stream_probe(1000, 6, bad, out, None) == E
+
+
+def test_interleave_conversion_rejections_on_host(bs):
+    lib = bs.load()
+    a, b = _fake(1), _fake(2)
+    E = bs.BS_EINVAL
+    assert lib.bs_pack_interleave(10, 4, a, 10, b, 3, None) == E                 # ld < batch
+    assert lib.bs_pack_interleave(10, 4, a, 9, b, 4, None) == E                  # pitch < n
+    assert lib.bs_pack_interleave(0, 4, a, 10, b, 4, None) == E
+    assert lib.bs_pack_interleave(10, 4, None, 10, b, 4, None) == E
+    assert lib.bs_unpack_interleave(10, 4, a, 4, ctypes.c_void_p(0x10004), 10, None) == E
+    assert lib.bs_unpack_interleave(10, 4, a, 4, b, 9, None) == E
+    assert lib.bs_unpack_interleave(1 << 26, 4, a, 4, b, 1 << 26, None) == E

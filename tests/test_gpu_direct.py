@@ -288,3 +288,22 @@ def test_stream_probe_sums():
             ref += t
         torch.cuda.synchronize()
         assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("batch,n,ld,pitch", [(1, 1, 1, 1), (33, 70, 40, 70), (70, 33, 128, 41),
+                                              (257, 1000, 264, 1000), (2, 4099, 64, 4100)])
+def test_interleave_conversions(batch, n, ld, pitch):
+    """Device pack/unpack against the host layout helpers, bitwise; padding
+    columns and the gaps of a pitched buffer are left alone."""
+    rng = np.random.default_rng(batch * n)
+    lines = rng.normal(size=(batch, n))
+    src = torch.full((batch, pitch), np.nan, dtype=torch.float64, device="cuda")
+    src[:, :n] = torch.from_numpy(lines).cuda()
+    out = torch.full((n, ld), 7.0, dtype=torch.float64, device="cuda")
+    bs.pack_interleave(src[:, :n], ld=ld, out=out)
+    back = torch.full((batch, pitch), -3.0, dtype=torch.float64, device="cuda")
+    bs.unpack_interleave(out, batch, out=back[:, :n])
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), wl.interleave(lines, ld, fill=7.0))
+    assert np.array_equal(back[:, :n].cpu().numpy(), lines)
+    assert (back[:, n:].cpu().numpy() == -3.0).all()
