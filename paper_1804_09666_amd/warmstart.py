@@ -207,6 +207,29 @@ class WarmStart:
              self.m, self.v, lr, self.step)
         return st["loss"]
 
+    def save(self, path):
+        """Checkpoint: parameters, Adam moments and step, and the input/output
+        scaling, as one .npz (plain arrays; nothing executable)."""
+        np.savez(path, p32=self.p32.cpu().numpy(), m=self.m.cpu().numpy(),
+                 v=self.v.cpu().numpy(), step=np.int64(self.step), dtype=np.int32(self.dtype),
+                 norm=np.asarray(self.norm, dtype=np.float64),
+                 target=np.asarray([self.mu_t, self.sigma_t], dtype=np.float64))
+
+    @classmethod
+    def restore(cls, path, device="cuda"):
+        """A WarmStart from save(); training continues where it stopped."""
+        with np.load(path, allow_pickle=False) as z:
+            net = cls(int(z["dtype"]), device=device)
+            net.p32.copy_(torch.from_numpy(z["p32"]))
+            net.m.copy_(torch.from_numpy(z["m"]))
+            net.v.copy_(torch.from_numpy(z["v"]))
+            net.step = int(z["step"])
+            net.norm = [float(x) for x in z["norm"]]
+            net.mu_t, net.sigma_t = (float(x) for x in z["target"])
+        if net.dtype == WS_BF16:
+            convert(net.p32, net.dtype, out=net.pT)
+        return net
+
     def fit_scaling(self, samples, n, batch):
         """Feature means and scales and the target scaling from training
         sweeps: samples = [(planes, solution), ...] as adi_trajectory hands

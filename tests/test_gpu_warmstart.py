@@ -203,3 +203,27 @@ def test_fused_inference_matches_layered_forward(P):
     assert torch.equal(Yf, Yl)
     Yo, _ = mo.forward(X, p, bf16=True)
     assert np.abs(host(Yf) - Yo).max() <= 3e-2 * np.abs(Yo).max()
+
+
+def test_checkpoint_resume_is_exact(tmp_path):
+    """Training, a checkpoint after 5 Adam steps and 5 more steps from the
+    restored state give bitwise the parameters of 10 uninterrupted steps."""
+    rng = np.random.default_rng(21)
+    P = 256
+    X = dev(mo.bf16_round(rng.normal(size=(P, mo.DIMS[0]))), torch.bfloat16)
+    T = dev(rng.normal(size=(P, mo.DIMS[-1])))
+    a = wsm.WarmStart(wsm.WS_BF16, seed=4)
+    a.norm = [0.5] * 7 + [2.0] * 7
+    a.mu_t, a.sigma_t = 0.1, 3.0
+    for _ in range(5):
+        a.train_step(X, T, 1e-3)
+    a.save(tmp_path / "ck.npz")
+    for _ in range(5):
+        a.train_step(X, T, 1e-3)
+    b = wsm.WarmStart.restore(tmp_path / "ck.npz")
+    for _ in range(5):
+        b.train_step(X, T, 1e-3)
+    torch.cuda.synchronize()
+    assert b.step == a.step == 10 and b.norm == a.norm and (b.mu_t, b.sigma_t) == (0.1, 3.0)
+    for t in ("p32", "pT", "m", "v"):
+        assert torch.equal(getattr(a, t), getattr(b, t)), t
