@@ -54,7 +54,8 @@
  *    -3      MNPDM: the outer-entry list of the system is not strictly
  *            ascending or names a row outside 0..n-1
  *    -4      split-row band_solve: the blocks that share the system did not
- *            all arrive within about a second (x unspecified)
+ *            all arrive within BS_OPT_EXCHANGE_WAIT_US (default one second;
+ *            x unspecified)
  *    -1, -2  band_solve_refine: not converged within max_steps / residual not
  *            finite (as for SIP)
  */
@@ -110,13 +111,18 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
  *   BS_OPT_SIP_PATH        sip_solve kernel: 0 and 2 rows of a system split
  *                          over lanes where the HB steps allow it (default),
  *                          1 one lane per system
+ *   BS_OPT_EXCHANGE_WAIT_US longest wait, in microseconds (0 .. 10^7, default
+ *                          10^6), of a split-row block for the other blocks of
+ *                          its system before it gives up and the system's
+ *                          info becomes -4
  * bs_set_option returns BS_EINVAL for an unknown key or a value out of range;
  * bs_get_option returns -1 for an unknown key. */
 enum bs_option_code {
   BS_OPT_DIRECT_PATH = 0,
   BS_OPT_PART_PD_VARIANT = 1,
   BS_OPT_PART_TD_VARIANT = 2,
-  BS_OPT_SIP_PATH = 3
+  BS_OPT_SIP_PATH = 3,
+  BS_OPT_EXCHANGE_WAIT_US = 4
 };
 int32_t bs_set_option(int32_t key, int64_t value);
 int64_t bs_get_option(int32_t key);

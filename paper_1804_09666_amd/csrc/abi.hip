@@ -168,6 +168,10 @@ int32_t bs_set_option(int32_t key, int64_t value) {
       if (value < 0 || value > 2) return BS_EINVAL;
       g_sip_path = value;
       return BS_OK;
+    case BS_OPT_EXCHANGE_WAIT_US:
+      if (value < 0 || value > 10000000) return BS_EINVAL;
+      bs::set_exchange_wait_us(value);
+      return BS_OK;
     case BS_OPT_PART_PD_VARIANT:
     case BS_OPT_PART_TD_VARIANT: {
       const int kind = key == BS_OPT_PART_PD_VARIANT ? 5 : 3;
@@ -186,6 +190,7 @@ int64_t bs_get_option(int32_t key) {
     case BS_OPT_PART_PD_VARIANT: return g_pd_variant.load();
     case BS_OPT_PART_TD_VARIANT: return g_td_variant.load();
     case BS_OPT_SIP_PATH: return g_sip_path.load();
+    case BS_OPT_EXCHANGE_WAIT_US: return bs::exchange_wait_us();
     default: return -1;
   }
 }

@@ -57,6 +57,10 @@ hipError_t launch_subst(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
 // all in one launch.  dtype 0: FP64 storage, 1: FP32 storage; arithmetic is
 // FP64 in both.
 int part_variant_count(int kind);
+// Longest wait (microseconds) of a split-kernel tile for the other tiles of
+// its system before it gives up (info = -4); process-wide.
+void set_exchange_wait_us(int64_t us);
+int64_t exchange_wait_us();
 bool part_variant_shape(int kind, int idx, int out[4]);
 // The configured variant if it handles (n, ld, dtype), else the first one
 // that does; -1 if none.

@@ -26,6 +26,8 @@
 // Block -> system-group mapping is XCD-aware: consecutive system groups
 // (which share 128-byte lines of every row) go to the same XCD, so the line
 // is fetched from HBM once and served from that XCD's L2 to its neighbours.
+#include <atomic>
+
 #include "split_core.h"
 
 namespace bs {
@@ -35,9 +37,13 @@ using namespace split;
 
 // One block = G systems x PW chunks of M rows = one tile of RT = M*PW rows of
 // G systems.  T <= TMAX tiles (consecutive blocks on one XCD) cover a system;
-// they exchange their tile maps through `xch` and meet at the counter pair
-// cnt[2*grp], cnt[2*grp+1] (arrivals, departures; reset by the last tile to
-// leave, so the counters are zero again after every completed call).
+// they exchange their tile maps through `xch` and meet at the counters
+// cnt[3*grp .. 3*grp+2] (arrivals, departures, tiles that gave up waiting;
+// reset by the last tile to leave, so the counters are zero again after every
+// completed call).  A tile waits at most wait_ticks of the 100 MHz real-time
+// clock for the others; if any tile of the group gave up, the last one to
+// leave marks the group's systems info = -4 (x unspecified), whichever tile
+// wrote info first.
 // SPARSE: the outer diagonals come from an MNPDM list (absent entries are
 // zero, so every product with them is an exact zero).
 // ASM: the rows are assembled from the sweep input v (passed as Y) and r
@@ -51,7 +57,7 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
     const TIO* __restrict__ Y, TIO* __restrict__ X,
     int32_t* __restrict__ info, double* __restrict__ xch,
     unsigned* __restrict__ cnt, int T, const int32_t* __restrict__ skip, Outer ol,
-    double rcoef) {
+    double rcoef, uint64_t wait_ticks) {
   constexpr int NB = KIND == 5 ? 2 : 1;
   constexpr int RS = kRecSz<NB>;
   constexpr int RT = M * PW;
@@ -153,11 +159,11 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
       __builtin_amdgcn_s_waitcnt(kWaitVmem);
       if (tid == 0) {
         // the last tile to arrive has nothing to wait for
-        if (atomicAdd(&cnt[2 * grp], 1u) + 1 < (unsigned)T) {
+        if (atomicAdd(&cnt[3 * grp], 1u) + 1 < (unsigned)T) {
           const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-          while (ld_counter(&cnt[2 * grp]) < (unsigned)T) {
+          while (ld_counter(&cnt[3 * grp]) < (unsigned)T) {
             __builtin_amdgcn_s_sleep(2);
-            if (__builtin_amdgcn_s_memrealtime() - t0 > kWaitTicks) {
+            if (__builtin_amdgcn_s_memrealtime() - t0 > wait_ticks) {
               s_timeout = 1;
               break;
             }
@@ -209,17 +215,36 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
   // ---- 3. back down the tile's tree, then x = p - V x_L - W x_R ---------
   tree_down<NB, PW, G>(xl, xr, j, g, s_node);
   write_chunk<NB, M>(n, ld, s, live, r0, 0, p, v, w, xl, xr, X);
+  // info at the device-coherent level: the last tile to leave may overwrite
+  // it from another XCD
   if (j == 0 && tile == 0 && live) {
     const int b0 = s_bad[g];
-    info[s] = list_bad ? kBadList : (s_timeout ? kTimeout : ((b0 == kBadNone) ? 0 : b0));
+    st_coherent_i32(&info[s],
+                    list_bad ? kBadList : (s_timeout ? kTimeout : ((b0 == kBadNone) ? 0 : b0)));
   }
   // Departure, off the critical path: every tile read all maps before the
-  // barrier after the exchange; the last one out resets the meeting point.
-  if (T > 1 && tid == 0) {
-    const unsigned gone = atomicAdd(&cnt[2 * grp + 1], 1u);
-    if (gone == (unsigned)T - 1) {
-      __hip_atomic_store(&cnt[2 * grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&cnt[2 * grp + 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // barrier after the exchange.  A tile that gave up waiting says so first;
+  // the last one out marks the group if any did and resets the meeting point.
+  // Wave 0 alone (it holds the info stores and every lane with j == 0), so
+  // the other waves retire as soon as their x stores are issued.
+  if (T > 1 && tid < 64) {
+    __builtin_amdgcn_s_waitcnt(kWaitVmem);  // this wave's info stores are in place
+    unsigned last = 0;
+    if (tid == 0) {
+      unsigned gave_up = 0;
+      if (s_timeout) gave_up = atomicAdd(&cnt[3 * grp + 2], 1u) + 1;
+      // the departure is issued once the give-up count has returned
+      last = (gave_up != ~0u && atomicAdd(&cnt[3 * grp + 1], 1u) == (unsigned)T - 1) ? 1u : 0u;
+    }
+    if (__builtin_amdgcn_readfirstlane(last)) {
+      unsigned gave = 0;
+      if (tid < G) gave = ld_counter(&cnt[3 * grp + 2]);
+      if (tid < G && live && gave != 0u) st_coherent_i32(&info[s], kTimeout);
+      if (tid == 0 && gave != ~0u) {  // after the count was read
+        __hip_atomic_store(&cnt[3 * grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&cnt[3 * grp + 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&cnt[3 * grp + 2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   }
 }
@@ -397,6 +422,9 @@ constexpr Variant kVariants[] = {
 // Shape of the long-system path (both kinds).
 constexpr int kLongM = 32, kLongPW = 16, kLongG = 16;
 
+// Longest wait of a tile for the other tiles of its system, microseconds.
+std::atomic<int64_t> g_exchange_wait_us{1000000};
+
 template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false,
           bool ASM = false>
 hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, const void* const* dg,
@@ -407,12 +435,12 @@ hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, const void* const* d
   const int T = (int)((n + RT - 1) / RT);
   const int64_t groups = (batch + G - 1) / G;
   unsigned* cnt = (T > 1) ? reinterpret_cast<unsigned*>(ws) : nullptr;
-  double* xch = (T > 1) ? ws + (2 * groups + 1) / 2 + 1 : nullptr;
+  double* xch = (T > 1) ? ws + (3 * groups + 1) / 2 + 1 : nullptr;
   hipLaunchKernelGGL((part_kernel<TIO, KIND, M, PW, G, TMAX, WPE, SPARSE, ASM>),
                      dim3((unsigned)(groups * T)), dim3(G * PW), 0, st, n, batch, ld,
                      (const TIO*)dg[0], (const TIO*)dg[1], (const TIO*)dg[2], (const TIO*)dg[3],
                      (const TIO*)dg[4], (const TIO*)y, (TIO*)x, info, xch, cnt, T, skip, ol,
-                     rcoef);
+                     rcoef, (uint64_t)g_exchange_wait_us.load() * 100u);
   return hipGetLastError();
 }
 
@@ -455,6 +483,9 @@ const Variant* find_variant(int kind, int idx) {
 }
 
 }  // namespace
+
+void set_exchange_wait_us(int64_t us) { g_exchange_wait_us = us; }
+int64_t exchange_wait_us() { return g_exchange_wait_us.load(); }
 
 int part_variant_count(int kind) {
   int k = 0;
@@ -502,7 +533,7 @@ size_t part_workspace_bytes(int kind, int idx, int64_t n, int64_t batch) {
   const int64_t groups = (batch + v->G - 1) / v->G;
   const int64_t rs = (kind == 5 ? 20 : 6) + 1;
   if (T <= 1) return 0;
-  return (size_t)(((2 * groups + 1) / 2 + 1) + groups * T * v->G * rs) * 8;
+  return (size_t)(((3 * groups + 1) / 2 + 1) + groups * T * v->G * rs) * 8;
 }
 
 hipError_t launch_part(int kind, int idx, int dtype, int64_t n, int64_t batch, int64_t ld,

@@ -380,7 +380,9 @@ struct Outer {
   const double* b;
 };
 constexpr int kTimeout = -4;
-constexpr uint64_t kWaitTicks = 100000000;  // 1 s of the 100 MHz real-time counter
+__device__ inline void st_coherent_i32(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Loads the M rows of a chunk (first row r0) of system s into registers:
 // identity rows past n, zero couplings outside the matrix.  Byte offsets fit

@@ -41,6 +41,17 @@ def test_status_strings_and_version(bs):
     assert bs.load().bs_version() >= 100
 
 
+def test_exchange_wait_option(bs):
+    assert bs.get_option(bs.OPT_EXCHANGE_WAIT_US) == 1000000
+    with pytest.raises(bs.BandSolveError):
+        bs.set_option(bs.OPT_EXCHANGE_WAIT_US, -1)
+    with pytest.raises(bs.BandSolveError):
+        bs.set_option(bs.OPT_EXCHANGE_WAIT_US, 10000001)
+    bs.set_option(bs.OPT_EXCHANGE_WAIT_US, 0)
+    assert bs.get_option(bs.OPT_EXCHANGE_WAIT_US) == 0
+    bs.set_option(bs.OPT_EXCHANGE_WAIT_US, 1000000)
+
+
 def test_workspace_query(bs):
     n, batch = 1000, 100
     lw = 128
@@ -78,12 +89,12 @@ def test_workspace_query(bs):
         assert bs.workspace_bytes(bs.OP_SOLVE, 3, 2048, batch) == 2048 * lw * 8
     finally:
         bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_AUTO)
-    # split rows: small exchange area (counters + tile maps) only
+    # split rows: small exchange area (three counters per group + tile maps) only
     M, PW, G, TMAX = bs.part_variants(5)[0]
     T = -(-2048 // (M * PW))
     groups = -(-batch // G)
     assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch) == \
-        ((2 * groups + 1) // 2 + 1 + groups * T * G * 21) * 8
+        ((3 * groups + 1) // 2 + 1 + groups * T * G * 21) * 8
     assert bs.workspace_bytes(bs.OP_SOLVE, 5, M * PW, batch) == 0
     # n beyond every single-launch variant: the three-launch path keeps one
     # record per tile (tile map + first bad row, outer pairs, fold node)
