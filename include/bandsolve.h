@@ -275,9 +275,9 @@ int32_t band_solve_mnpdm(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
  * (0, -1, -2 or a pivot row + 1) are written per system.  dtype BS_F64.
  * Kernels: with HB for both factors (s_L, s_U >= 0, 2^s < n, and
  *   2^s_L + 2^s_U <= 96) the rows of a system are split over many lanes and
- *   every step is one launch over all rows plus a one-block status launch:
- *   max_iter + 1 step launches are enqueued, and those after the last system
- *   has stopped return at once.  Otherwise (exact substitution, Algorithm 1
+ *   every step is one launch over all rows, whose last block to finish applies
+ *   the stopping test: max_iter + 1 step launches are enqueued, and those
+ *   after the last system has stopped return at once.  Otherwise (exact substitution, Algorithm 1
  *   as written) one lane walks each system in one persistent launch.
  * workspace: bs_workspace_bytes(BS_OP_SIP, ...) bytes, 256-byte aligned; its
  *   contents need no initialisation.  x and rhs must not alias. */
