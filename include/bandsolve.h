@@ -181,9 +181,11 @@ int32_t band_factor(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
  *   BS_OP_SOLVE_FACTORED, ...); may be NULL / 0 when that is 0.  When the
  *   rows of a system span several blocks, the blocks meet at counters in the
  *   workspace: its contents must be zero before its first use with
- *   band_solve, and every completed call leaves them zero again (after an
- *   info of -4 -- blocks of a system that failed to meet -- zero it again).
- *   Calls that share one workspace must not run concurrently. */
+ *   band_solve, and every completed call leaves them zero again, also after
+ *   an info of -4 (blocks that gave up waiting still leave, and the last one
+ *   resets the counters; zero the workspace again only if a call was
+ *   interrupted).  Calls that share one workspace must not run concurrently.
+ *   The factored substitution uses its workspace for z and needs no zeroing. */
 int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
                    int64_t ld, const void* const diags[5], const void* factors,
                    const void* rhs, void* x, int32_t* info, void* workspace,
