@@ -37,7 +37,13 @@ def _load(count: bool = False):
     path = build_oracle.LIB_COUNT if count else build_oracle.LIB
     if not os.path.exists(path):
         build_oracle.build(force=False)
-    lib = ctypes.CDLL(path)
+    _LIBS[key] = bind(ctypes.CDLL(path))
+    return _LIBS[key]
+
+
+def bind(lib):
+    """Declare the C signatures on a loaded oracle library (also used by the
+    tests that load deliberately broken copies of it)."""
     sig = {
         "orc_npdm": (_int, [_i64] + [_dp] * 8),
         "orc_ntdm": (_int, [_i64] + [_dp] * 6),
@@ -64,7 +70,6 @@ def _load(count: bool = False):
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    _LIBS[key] = lib
     return lib
 
 
