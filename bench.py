@@ -795,7 +795,7 @@ def main():
         pmc_run()
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: this library has no multi-GPU path "
               "(systems of a sweep would be sharded across GPUs; see the design notes)",
               file=sys.stderr)
         sys.exit(2)

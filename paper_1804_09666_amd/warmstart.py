@@ -2,7 +2,7 @@
 
 Binding of the warm-start part of libbandsolve (argument marshalling only:
 features, network, loss, Adam and the start vector all run in its kernels),
-plus the driver that trains the network on solutions of earlier ADI sweeps
+plus the loop that trains the network on solutions of earlier ADI sweeps
 and uses it.
 
 Algorithm 1 of Veneva & Ayriyan (arXiv:1804.09666, Sec. 2) starts from a
