@@ -26,9 +26,13 @@
 // flag that makes the remaining launches return at once.
 #include "bs_internal.h"
 
-// Products and sums may contract into FMAs, and the upper sweeps multiply by
-// 1/u0 (one division per row and step) instead of dividing in every sweep;
-// both change only the rounding of the iterates.
+// Products and sums may contract into FMAs, the upper sweeps multiply by 1/u0
+// (one division per row and step) instead of dividing in every sweep, and the
+// sweeps are evaluated in the plain Jacobi form, which is the same polynomial
+// with the diagonal terms cancelled:
+//   lower: y_t = v - l1 y_{t-1}[i-1] - l2 y_{t-1}[i-2]            (2 FMAs per row)
+//   upper: z_t = (w - u1 z_{t-1}[i+1] - u2 z_{t-1}[i+2]) / u0     (2 FMAs, 1 product)
+// All three change only the rounding of the iterates.
 
 namespace bs {
 namespace {
@@ -188,10 +192,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     for (int r = kM - 1; r >= 0; --r) {
       const double y_m1 = r >= 1 ? y[r - 1] : ym1;
       const double y_m2 = r >= 2 ? y[r - 2] : (r == 1 ? ym1 : ym2);
-      double ty = y[r];
-      ty = ty + l1[r] * y_m1;
-      ty = ty + l2[r] * y_m2;
-      y[r] = y[r] + (v[r] - ty);
+      double ty = v[r];
+      ty = ty - l1[r] * y_m1;
+      ty = ty - l2[r] * y_m2;
+      y[r] = ty;
     }
   }
 
@@ -213,10 +217,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     for (int r = 0; r < kM; ++r) {
       const double z_p1 = r + 1 < kM ? z[r + 1] : zp1;
       const double z_p2 = r + 2 < kM ? z[r + 2] : (r + 2 == kM ? zp1 : zp2);
-      double ty = u0[r] * z[r];
-      ty = ty + u1[r] * z_p1;
-      ty = ty + b[r] * z_p2;
-      z[r] = z[r] + (y[r] - ty) * ru[r];
+      double ty = y[r];
+      ty = ty - u1[r] * z_p1;
+      ty = ty - b[r] * z_p2;
+      z[r] = ty * ru[r];
     }
   }
 
