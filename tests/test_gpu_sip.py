@@ -117,6 +117,30 @@ def test_split_rows_full_sweep_batch():
     assert rel_err(x, xd).max() <= 1e-7
 
 
+def test_split_rows_learned_start_workload_size():
+    """The learned-start workload's solve: 4096 second-order sweep systems of
+    n = 4096 (r = 4), HB (3, 3), zero start, to 1e-10.  Status and residual
+    of every system; iteration counts and x of a sample against the oracle."""
+    N = 4096
+    sw = wl.sweep_lines(wl.smooth_lines(N, N, seed=404), 4.0, 2)
+    t = to_device(sw, N)
+    say(f"tile SIP n={N} batch={N} sL=3 sU=3")
+    x, it, rr, info = bs.sip(diags_of(t), t["y"], tol=1e-10, max_iter=100, s_L=3, s_U=3,
+                             batch=N)
+    torch.cuda.synchronize()
+    it, rr, info = it.cpu().numpy(), rr.cpu().numpy(), info.cpu().numpy()
+    say(f"  iters {np.bincount(it).tolist()}")
+    assert (info == 0).all() and (rr < 1e-10).all()
+    pick = [0, 1, 777, 2048, N - 1]
+    sub = {k: v[pick] for k, v in sw.items()}
+    xo, ito, rro, sto = oracle.sip_batch(sub["e"], sub["c"], sub["d"], sub["a"], sub["b"],
+                                         sub["y"], tol=1e-10, max_iter=100, s_L=3, s_U=3)
+    assert (sto == 0).all() and np.abs(it[pick] - ito).max() <= 1
+    xs = x[:, pick].cpu().numpy().T
+    xd, _ = oracle.npdm_batch(sub["e"], sub["c"], sub["d"], sub["a"], sub["b"], sub["y"])
+    assert rel_err(xs, xd).max() <= 1e-7
+
+
 def test_split_rows_bad_pivot_and_max_iter_zero():
     ws = wl.dominant_batch(4, 600, seed=13)
     ws["d"][2, 0] = 0.0     # ILU(0) pivot u0_0 = 0: no step, x untouched

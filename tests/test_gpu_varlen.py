@@ -115,3 +115,46 @@ def test_autotuner_and_graph_replay():
         got = plan.unpack(x.cpu().numpy())
         assert all(np.array_equal(a, b) for a, b in zip(got, ref)), rep
         assert (info.cpu().numpy()[plan.slot] == 0).all()
+
+
+def test_full_size_uneven_batch():
+    """The uneven-batch workload at full size: 10 000 dominant PD systems with
+    n log-uniform in [64, 65536] (about 1e8 rows), generated on the device,
+    solved with the tile shape the autotuner picks (the measured launch).
+    Every system against its manufactured solution (dominant, so the error
+    is a few ulps of max|x|), sampled systems against the oracle."""
+    sizes = wl.config2_sizes()
+    plan = bs.Varlen(sizes)
+    dev = wl.dominant_groups(plan.slot_sizes)
+    say(f"uneven batch full size: {plan.count} systems, {int(sizes.sum())} rows, "
+        f"{plan.elems} stored elements")
+    diags = [dev[k] for k in ("e", "c", "d", "a", "b")]
+    x = torch.zeros_like(dev["y"])
+    info = torch.empty(plan.slots, dtype=torch.int32, device="cuda")
+    ws = plan.workspace(5)
+    best, ms = plan.tune(5, diags, dev["y"], x, info, ws, reps=2)
+    x.zero_()
+    plan.solve(5, diags, dev["y"], x, info, variant=best, workspace=ws)
+    torch.cuda.synchronize()
+    say(f"  autotuner picked variant {best} ({ms})")
+    assert (info.cpu().numpy()[plan.slot] == 0).all()
+    # per-slot max |x - x_true| and max |x_true| (positions outside every
+    # system hold 0 in x_true and are never written, so they add nothing)
+    sn = torch.as_tensor(plan.slot_sizes, device="cuda")
+    gn = sn.view(-1, 16).max(dim=1).values
+    gid = torch.repeat_interleave(torch.arange(gn.numel(), device="cuda"), gn * 16)
+    slot = gid * 16 + torch.arange(plan.elems, device="cuda") % 16
+    err = torch.zeros(plan.slots, dtype=torch.float64, device="cuda")
+    err.scatter_reduce_(0, slot, (x - dev["x_true"]).abs(), "amax")
+    scale = torch.zeros(plan.slots, dtype=torch.float64, device="cuda")
+    scale.scatter_reduce_(0, slot, dev["x_true"].abs(), "amax")
+    rel = (err / scale.clamp_min(1e-300)).cpu().numpy()[plan.slot]
+    say(f"  max rel err vs manufactured solution over all systems {rel.max():.2e}")
+    assert rel.max() <= TOL
+    pick = [int(np.argmin(sizes)), int(np.argmax(sizes)), 17, 4242, 9999]
+    for i in pick:
+        pos = torch.as_tensor(plan.offset[i] + 16 * np.arange(sizes[i]), device="cuda")
+        sysd = {k: dev[k].index_select(0, pos).cpu().numpy() for k in KEYS}
+        r = solve_oracle(sysd, 5)
+        got = x.index_select(0, pos).cpu().numpy()
+        assert np.abs(got - r).max() <= TOL * np.abs(r).max(), i

@@ -205,6 +205,30 @@ def test_fused_inference_matches_layered_forward(P):
     assert np.abs(host(Yf) - Yo).max() <= 3e-2 * np.abs(Yo).max()
 
 
+def test_fused_inference_full_size():
+    """The learned-start workload's inference size: 262 144 patches (the
+    64-row patches of 4096 systems of n = 4096), the launch the warm-start
+    measurement makes.  Bitwise the layered forward pass on every patch, and
+    the oracle on a sample of 512 patches."""
+    P = 4096 * 4096 // 64
+    p, _, _ = _problem(1, 17)
+    g = torch.Generator(device="cuda").manual_seed(17)
+    Xt = torch.randn(P, mo.DIMS[0], generator=g, device="cuda").to(torch.bfloat16)
+    p32 = dev(p)
+    pT = wsm.convert(p32, wsm.WS_BF16)
+    say(f"fused inference P={P}")
+    Yf = wsm.infer(Xt, p32, pT)
+    Yl = wsm.forward(wsm.WS_BF16, Xt, p32, pT)
+    torch.cuda.synchronize()
+    assert torch.equal(Yf, Yl)
+    pick = torch.from_numpy(np.random.default_rng(17).choice(P, 512, replace=False)).cuda()
+    Xs = Xt.index_select(0, pick).float().cpu().numpy().astype(np.float64)
+    Yo, _ = mo.forward(Xs, p, bf16=True)
+    got = host(Yf.index_select(0, pick))
+    say(f"  sampled max |fused - oracle| = {np.abs(got - Yo).max():.3e} (scale {np.abs(Yo).max():.3e})")
+    assert np.abs(got - Yo).max() <= 3e-2 * np.abs(Yo).max()
+
+
 def test_checkpoint_resume_is_exact(tmp_path):
     """Training, a checkpoint after 5 Adam steps and 5 more steps from the
     restored state give bitwise the parameters of 10 uninterrupted steps."""
