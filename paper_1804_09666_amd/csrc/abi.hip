@@ -165,7 +165,7 @@ int32_t bs_set_option(int32_t key, int64_t value) {
       g_direct_path = value;
       return BS_OK;
     case BS_OPT_SIP_PATH:
-      if (value < 0 || value > 2) return BS_EINVAL;
+      if (value < 0 || value > 3) return BS_EINVAL;
       g_sip_path = value;
       return BS_OK;
     case BS_OPT_EXCHANGE_WAIT_US:
@@ -226,7 +226,7 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
     case BS_OP_SIP: {
       // ILU(0) factors (4 planes, batch-interleaved with pitch ws_ld), then
       // either one plane for the forward pass (one lane per system) or the
-      // second x buffer and per-system state (rows split over lanes)
+      // two more x buffers and per-system state (rows split over lanes)
       const size_t lane = (size_t)plane * 8;
       const size_t tile = bs::sip_tile_workspace_bytes(n, batch, ld);
       return (size_t)(4 * plane) * 8 + (lane > tile ? lane : tile);
@@ -418,11 +418,13 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
     F = ws;
   }
   double* rest = ws + 4 * n * lw;  // 256-byte aligned: lw is a multiple of 64
-  if (g_sip_path.load() != 1 && bs::sip_tile_supported(n, hb_s_L, hb_s_U))
+  const int64_t path = g_sip_path.load();
+  if (path != 1 && bs::sip_tile_supported(n, hb_s_L, hb_s_U))
     return launched(bs::launch_sip_tile(n, batch, ld, A, F, fld, own,
                                         static_cast<const double*>(rhs),
                                         static_cast<double*>(x), tol, max_iter, hb_s_L,
-                                        hb_s_U, iters, relres, info, rest, st));
+                                        hb_s_U, iters, relres, info, rest, path == 3 ? 1 : 2,
+                                        st));
   return launched(bs::launch_sip_lane(n, batch, ld, A, F, fld,
                                       static_cast<const double*>(rhs),
                                       static_cast<double*>(x), tol, max_iter,

@@ -122,11 +122,13 @@ hipError_t launch_sip_lane(int64_t n, int64_t batch, int64_t ld, Diags A,
 bool sip_tile_supported(int64_t n, int32_t sL, int32_t sU);
 size_t sip_tile_workspace_bytes(int64_t n, int64_t batch, int64_t ld);
 // own_factors: the factors were just computed by launch_factor_lane, whose
-// info marks systems that cannot step.
+// info marks systems that cannot step.  steps_per_launch: 2 takes two steps
+// per launch where the halos allow it, 1 one step per launch.
 hipError_t launch_sip_tile(int64_t n, int64_t batch, int64_t ld, Diags A, const double* factors,
                            int64_t fld, bool own_factors, const double* y, double* x, double tol,
                            int32_t max_iter, int32_t sL, int32_t sU, int32_t* iters,
-                           double* relres, int32_t* info, void* ws, hipStream_t st);
+                           double* relres, int32_t* info, void* ws, int steps_per_launch,
+                           hipStream_t st);
 
 // ---- layout conversion (layout.hip) -------------------------------------
 // dst[c * dpitch + r] = src[r * spitch + c] for r < R, c < C (R, C < 2^21 * 32).

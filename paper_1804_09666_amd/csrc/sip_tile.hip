@@ -37,11 +37,13 @@
 namespace bs {
 namespace {
 
-constexpr int kG = 16;              // systems per block: one 128-byte segment per row
-constexpr int kPW = 32;             // lanes per system in a block
-constexpr int kM = 8;               // rows per lane
-constexpr int kE = kM * kPW;        // rows of a tile including its halos
-constexpr int kThreads = kG * kPW;  // 512
+constexpr int kG = 16;   // systems per block: one 128-byte segment per row
+constexpr int kE = 256;  // rows of a tile including its halos
+// Tile shapes (rows per lane KM x lanes per system KPW = kE):
+//   one step per launch:  8 x 32, 512 threads at two waves per SIMD;
+//   two steps per launch: 16 x 16, 256 threads at one wave per SIMD (the rows
+//     of A and the right-hand side stay live through the first step).
+constexpr int kZero = 3;  // fin: the answer is x = 0 (b = 0)
 
 __device__ inline void atomic_max_nonneg(unsigned long long* p, double v) {
   atomicMax(p, (unsigned long long)__double_as_longlong(v));  // v >= 0 or NaN
@@ -52,22 +54,21 @@ __device__ inline double as_double(unsigned long long u) {
 
 // Per-system state in the workspace.
 struct Flags {
-  int32_t* active;             // 1 while the system still steps
-  int32_t* fin;                // final x: 0 caller's buffer, 1 second buffer, 2 zero
-  unsigned long long* accum;   // ||r_k||_inf of the step in flight (bits)
-  unsigned long long* bnorm;   // ||b||_inf (bits)
+  int32_t* active;               // 1 while the system still steps
+  int32_t* fin;                  // buffer holding the answer (0 = caller's x), or kZero
+  unsigned long long* accum[2];  // ||r_k||_inf, ||r_{k+1}||_inf of the launch in flight (bits)
+  unsigned long long* bnorm;     // ||b||_inf (bits)
   double* relres0;
   int32_t* done;
-  unsigned* arrive;            // blocks of the step in flight that have finished
+  unsigned* arrive;              // blocks of the launch in flight that have finished
 };
 
-// Algorithm 1's loop test for system s after step k has accumulated
-// ||b - A x_k||: returns 1 to keep stepping, else records the outcome.
-__device__ inline int sip_status(int64_t s, int32_t k, int32_t max_iter, double tol, Flags fl,
-                                 int32_t* __restrict__ iters, double* __restrict__ relres,
-                                 int32_t* __restrict__ info) {
-  const double rn = as_double(__hip_atomic_exchange(&fl.accum[s], 0ull, __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT));
+// Algorithm 1's loop test for system s at step count k with rn = ||b - A x_k||:
+// returns 1 to keep stepping, else records the outcome (x_k, in buffer
+// `buf`, is the answer).
+__device__ inline int sip_test(int64_t s, int32_t k, double rn, int buf, int32_t max_iter,
+                               double tol, Flags fl, int32_t* __restrict__ iters,
+                               double* __restrict__ relres, int32_t* __restrict__ info) {
   const double bn = as_double(fl.bnorm[s]);
   const double rr = rn / bn;
   if (k == 0) fl.relres0[s] = rr;
@@ -82,24 +83,138 @@ __device__ inline int sip_status(int64_t s, int32_t k, int32_t max_iter, double 
     status = -1;
   if (status == 1) return 1;
   fl.active[s] = 0;
-  fl.fin[s] = k & 1;  // x_k is in buffer k mod 2
+  fl.fin[s] = buf;
   iters[s] = k;
   relres[s] = rr;
   info[s] = status;
   return 0;
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void sip_step_kernel(
+__device__ inline double take(unsigned long long* acc, int64_t s) {
+  return as_double(__hip_atomic_exchange(&acc[s], 0ull, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// First and last two rows of every lane, double-buffered by sweep parity.
+template <int KPW>
+struct Halo {
+  double lo[2][KPW][kG][2];
+  double hi[2][KPW][kG][2];
+};
+
+// v = w - A x over the lane's rows (the first and last two rows of the tile
+// see zero outside it); returns max |v| over tile rows [c0, c1) inside the
+// matrix.  Starts with a barrier-protected exchange of x's tip rows.
+template <int KM, int KPW>
+__device__ inline double residual(const double (&x)[KM], const double (&e)[KM],
+                                  const double (&c)[KM], const double (&d)[KM],
+                                  const double (&a)[KM], const double (&b)[KM],
+                                  const double (&w)[KM], double (&v)[KM], Halo<KPW>& H, int j,
+                                  int g, int64_t ext0, int c0, int c1, int64_t n) {
+  H.lo[0][j][g][0] = x[0];
+  H.lo[0][j][g][1] = x[1];
+  H.hi[0][j][g][0] = x[KM - 2];
+  H.hi[0][j][g][1] = x[KM - 1];
+  __syncthreads();
+  const double xm2 = j > 0 ? H.hi[0][j - 1][g][0] : 0.0;
+  const double xm1 = j > 0 ? H.hi[0][j - 1][g][1] : 0.0;
+  const double xp1 = j < KPW - 1 ? H.lo[0][j + 1][g][0] : 0.0;
+  const double xp2 = j < KPW - 1 ? H.lo[0][j + 1][g][1] : 0.0;
+  double m = 0.0;
+#pragma unroll
+  for (int r = 0; r < KM; ++r) {
+    const double x_m2 = r >= 2 ? x[r - 2] : (r == 1 ? xm1 : xm2);
+    const double x_m1 = r >= 1 ? x[r - 1] : xm1;
+    const double x_p1 = r + 1 < KM ? x[r + 1] : xp1;
+    const double x_p2 = r + 2 < KM ? x[r + 2] : (r + 2 == KM ? xp1 : xp2);
+    double ax = d[r] * x[r];
+    ax = ax + e[r] * x_m2;
+    ax = ax + c[r] * x_m1;
+    ax = ax + a[r] * x_p1;
+    ax = ax + b[r] * x_p2;
+    v[r] = w[r] - ax;
+    const int q = j * KM + r;  // row within the extended tile
+    if (q >= c0 && q < c1 && ext0 + r < n) {
+      const double ar = fabs(v[r]);
+      m = (ar > m || ar != ar) ? ar : m;
+    }
+  }
+  return m;
+}
+
+// y = X_L v: K_L lower sweeps, rows descending within the lane.
+template <int KM, int KPW>
+__device__ inline void lower_sweeps(int KL, const double (&v)[KM], const double (&l1)[KM],
+                                    const double (&l2)[KM], double (&y)[KM], Halo<KPW>& H, int j,
+                                    int g) {
+#pragma unroll
+  for (int r = 0; r < KM; ++r) y[r] = v[r];
+  for (int t = 1; t <= KL; ++t) {
+    const int p = t & 1;
+    H.hi[p][j][g][0] = y[KM - 2];
+    H.hi[p][j][g][1] = y[KM - 1];
+    __syncthreads();
+    const double ym2 = j > 0 ? H.hi[p][j - 1][g][0] : 0.0;
+    const double ym1 = j > 0 ? H.hi[p][j - 1][g][1] : 0.0;
+#pragma unroll
+    for (int r = KM - 1; r >= 0; --r) {
+      const double y_m1 = r >= 1 ? y[r - 1] : ym1;
+      const double y_m2 = r >= 2 ? y[r - 2] : (r == 1 ? ym1 : ym2);
+      double ty = v[r];
+      ty = ty - l1[r] * y_m1;
+      ty = ty - l2[r] * y_m2;
+      y[r] = ty;
+    }
+  }
+}
+
+// z = X_U w: K_U upper sweeps, rows ascending within the lane (ru = 1/u0).
+template <int KM, int KPW>
+__device__ inline void upper_sweeps(int KU, const double (&w)[KM], const double (&u1)[KM],
+                                    const double (&u2)[KM], const double (&ru)[KM],
+                                    double (&z)[KM], Halo<KPW>& H, int j, int g) {
+#pragma unroll
+  for (int r = 0; r < KM; ++r) z[r] = w[r] * ru[r];
+  for (int t = 1; t <= KU; ++t) {
+    const int p = t & 1;
+    H.lo[p][j][g][0] = z[0];
+    H.lo[p][j][g][1] = z[1];
+    __syncthreads();
+    const double zp1 = j < KPW - 1 ? H.lo[p][j + 1][g][0] : 0.0;
+    const double zp2 = j < KPW - 1 ? H.lo[p][j + 1][g][1] : 0.0;
+#pragma unroll
+    for (int r = 0; r < KM; ++r) {
+      const double z_p1 = r + 1 < KM ? z[r + 1] : zp1;
+      const double z_p2 = r + 2 < KM ? z[r + 2] : (r + 2 == KM ? zp1 : zp2);
+      double ty = w[r];
+      ty = ty - u1[r] * z_p1;
+      ty = ty - u2[r] * z_p2;
+      z[r] = ty * ru[r];
+    }
+  }
+}
+
+// NS steps of Algorithm 1 (NS = 1 or 2) for every system in one launch.
+// Launch k reads x_k from buffer k mod (NS + 1) and writes x_{k+1} (and
+// x_{k+2}) to the next buffers; the tile has halos of NS * HL rows before and
+// NS * HR after its RC core rows, which is what NS steps need for every core
+// row to get exactly the value of steps over the whole system.
+// The last block of the launch to finish (an arrival counter) applies the
+// test at k, then at k + 1, for every system still stepping.
+template <int KM, int KPW, int NS, int WPE>
+__global__ __launch_bounds__(kG * KPW) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void sip_step_kernel(
     int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
     const double* __restrict__ C, const double* __restrict__ D, const double* __restrict__ A,
     const double* __restrict__ B, const double* __restrict__ F, int64_t fld,
-    const double* __restrict__ Y, const double* __restrict__ Xin, double* __restrict__ Xout,
-    int KL, int KU, int HL, int RC, int T, Flags fl, int32_t k, int32_t max_iter, double tol,
-    int32_t* __restrict__ iters, double* __restrict__ relres, int32_t* __restrict__ info) {
+    const double* __restrict__ Y, const double* __restrict__ Xin, double* __restrict__ Xo1,
+    double* __restrict__ Xo2, int KL, int KU, int HL, int RC, int T, Flags fl, int32_t k,
+    int32_t max_iter, double tol, int32_t* __restrict__ iters, double* __restrict__ relres,
+    int32_t* __restrict__ info) {
+  static_assert(KM * KPW == kE && KM >= 4 && (NS == 1 || NS == 2), "shape");
+  constexpr int kThreads = kG * KPW;
   if (*fl.done) return;
-  __shared__ double s_lo[2][kPW][kG][2];  // first two rows of every lane
-  __shared__ double s_hi[2][kPW][kG][2];  // last two rows of every lane
-  __shared__ unsigned long long s_m[kG];
+  __shared__ Halo<KPW> H;
+  __shared__ unsigned long long s_m[NS][kG];
   __shared__ int s_last, s_any;
 
   const int tid = threadIdx.x;
@@ -109,9 +224,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   {  // the T tiles of a system group sit on one XCD: halo rows come from its L2
     const int64_t b = blockIdx.x, nblk = gridDim.x;
     if (nblk % (8 * T) == 0) {
-      const int64_t k = b / 8, per_xcd = nblk / 8 / T;
-      grp = (b % 8) * per_xcd + k / T;
-      tile = k % T;
+      const int64_t q = b / 8, per_xcd = nblk / 8 / T;
+      grp = (b % 8) * per_xcd + q / T;
+      tile = q % T;
     } else {
       grp = b / T;
       tile = b % T;
@@ -119,20 +234,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   }
   const int64_t s = grp * kG + g;
   const bool live = s < batch && fl.active[s] != 0;
-  const int64_t ext0 = tile * RC - HL + (int64_t)j * kM;  // global row of this lane's row 0
+  const int c0 = NS * HL, c1 = NS * HL + RC;            // core rows of the tile
+  const int64_t ext0 = tile * RC - c0 + (int64_t)j * KM;  // global row of this lane's row 0
   const int64_t plane = n * fld;
-  if (tid < kG) s_m[tid] = 0ull;
-
-  double x[kM], e[kM], c[kM], d[kM], a[kM], b[kM], v[kM], l1[kM], l2[kM], u0[kM], u1[kM];
+  if (tid < kG) {
 #pragma unroll
-  for (int r = 0; r < kM; ++r) {
+    for (int u = 0; u < NS; ++u) s_m[u][tid] = 0ull;
+  }
+
+  double x[KM], e[KM], c[KM], d[KM], a[KM], b[KM], w[KM], l1[KM], l2[KM], u0[KM], u1[KM];
+#pragma unroll
+  for (int r = 0; r < KM; ++r) {
     const int64_t i = ext0 + r;
     const bool in = live && i >= 0 && i < n;
     const int64_t o = in ? i * ld + s : 0;
     const int64_t fo = in ? i * fld + s : 0;
     x[r] = in ? Xin[o] : 0.0;
     d[r] = in ? D[o] : 1.0;
-    v[r] = in ? Y[o] : 0.0;
+    w[r] = in ? Y[o] : 0.0;
     c[r] = (in && i >= 1) ? C[o] : 0.0;
     a[r] = (in && i <= n - 2) ? A[o] : 0.0;
     e[r] = (in && i >= 2) ? E[o] : 0.0;
@@ -142,104 +261,40 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
     u0[r] = in ? F[2 * plane + fo] : 1.0;
     u1[r] = (in && i <= n - 2) ? F[3 * plane + fo] : 0.0;
   }
-
-  // ---- residual r = b - A x over the extended range (v holds r) -----------
-  s_lo[0][j][g][0] = x[0];
-  s_lo[0][j][g][1] = x[1];
-  s_hi[0][j][g][0] = x[kM - 2];
-  s_hi[0][j][g][1] = x[kM - 1];
-  __syncthreads();
-  {
-    const double xm2 = j > 0 ? s_hi[0][j - 1][g][0] : 0.0;
-    const double xm1 = j > 0 ? s_hi[0][j - 1][g][1] : 0.0;
-    const double xp1 = j < kPW - 1 ? s_lo[0][j + 1][g][0] : 0.0;
-    const double xp2 = j < kPW - 1 ? s_lo[0][j + 1][g][1] : 0.0;
-    double m = 0.0;
+  double ru[KM];
 #pragma unroll
-    for (int r = 0; r < kM; ++r) {
-      const double x_m2 = r >= 2 ? x[r - 2] : (r == 1 ? xm1 : xm2);
-      const double x_m1 = r >= 1 ? x[r - 1] : xm1;
-      const double x_p1 = r + 1 < kM ? x[r + 1] : xp1;
-      const double x_p2 = r + 2 < kM ? x[r + 2] : (r + 2 == kM ? xp1 : xp2);
-      double ax = d[r] * x[r];
-      ax = ax + e[r] * x_m2;
-      ax = ax + c[r] * x_m1;
-      ax = ax + a[r] * x_p1;
-      ax = ax + b[r] * x_p2;
-      v[r] = v[r] - ax;
-      const int64_t q = (int64_t)j * kM + r;  // row within the extended tile
-      const int64_t i = ext0 + r;
-      if (q >= HL && q < HL + RC && i < n) {
-        const double ar = fabs(v[r]);
-        m = (ar > m || ar != ar) ? ar : m;
+  for (int r = 0; r < KM; ++r) ru[r] = 1.0 / u0[r];
+
+  double v[KM], y[KM], z[KM];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    if (u > 0) __syncthreads();  // every read of the previous step's exchanges is done
+    const double m = residual<KM, KPW>(x, e, c, d, a, b, w, v, H, j, g, ext0, c0, c1, n);
+    if (live && m != 0.0) atomicMax(&s_m[u][g], (unsigned long long)__double_as_longlong(m));
+    lower_sweeps<KM, KPW>(KL, v, l1, l2, y, H, j, g);
+    upper_sweeps<KM, KPW>(KU, y, u1, b, ru, z, H, j, g);
+#pragma unroll
+    for (int r = 0; r < KM; ++r) x[r] = x[r] + z[r];
+    if (live) {  // x_{k+u+1} at the core rows
+      double* __restrict__ Xo = u == 0 ? Xo1 : Xo2;
+#pragma unroll
+      for (int r = 0; r < KM; ++r) {
+        const int q = j * KM + r;
+        const int64_t i = ext0 + r;
+        if (q >= c0 && q < c1 && i < n) Xo[i * ld + s] = x[r];
       }
     }
-    if (live && m != 0.0) atomicMax(&s_m[g], (unsigned long long)__double_as_longlong(m));
-  }
-
-  // ---- y = X_L r: K_L lower sweeps, rows descending within the lane ------
-  double y[kM];
-#pragma unroll
-  for (int r = 0; r < kM; ++r) y[r] = v[r];
-  for (int t = 1; t <= KL; ++t) {
-    const int p = t & 1;
-    s_hi[p][j][g][0] = y[kM - 2];
-    s_hi[p][j][g][1] = y[kM - 1];
-    __syncthreads();
-    const double ym2 = j > 0 ? s_hi[p][j - 1][g][0] : 0.0;
-    const double ym1 = j > 0 ? s_hi[p][j - 1][g][1] : 0.0;
-#pragma unroll
-    for (int r = kM - 1; r >= 0; --r) {
-      const double y_m1 = r >= 1 ? y[r - 1] : ym1;
-      const double y_m2 = r >= 2 ? y[r - 2] : (r == 1 ? ym1 : ym2);
-      double ty = v[r];
-      ty = ty - l1[r] * y_m1;
-      ty = ty - l2[r] * y_m2;
-      y[r] = ty;
-    }
-  }
-
-  // ---- z = X_U y: K_U upper sweeps, rows ascending within the lane -------
-  double z[kM], ru[kM];
-#pragma unroll
-  for (int r = 0; r < kM; ++r) {
-    ru[r] = 1.0 / u0[r];
-    z[r] = y[r] * ru[r];
-  }
-  for (int t = 1; t <= KU; ++t) {
-    const int p = t & 1;
-    s_lo[p][j][g][0] = z[0];
-    s_lo[p][j][g][1] = z[1];
-    __syncthreads();
-    const double zp1 = j < kPW - 1 ? s_lo[p][j + 1][g][0] : 0.0;
-    const double zp2 = j < kPW - 1 ? s_lo[p][j + 1][g][1] : 0.0;
-#pragma unroll
-    for (int r = 0; r < kM; ++r) {
-      const double z_p1 = r + 1 < kM ? z[r + 1] : zp1;
-      const double z_p2 = r + 2 < kM ? z[r + 2] : (r + 2 == kM ? zp1 : zp2);
-      double ty = y[r];
-      ty = ty - u1[r] * z_p1;
-      ty = ty - b[r] * z_p2;
-      z[r] = ty * ru[r];
-    }
-  }
-
-  // ---- candidate x_{k+1} for the core rows; residual norm of x_k ---------
-  if (live) {
-#pragma unroll
-    for (int r = 0; r < kM; ++r) {
-      const int64_t q = (int64_t)j * kM + r;
-      const int64_t i = ext0 + r;
-      if (q >= HL && q < HL + RC && i < n) Xout[i * ld + s] = x[r] + z[r];
-    }
   }
   __syncthreads();
-  // ---- the last block of the step applies the test for every system ------
+  // ---- the last block of the launch applies the tests for every system ---
   if (tid < 64) {  // wave 0: this block's maxima, then its arrival
     unsigned long long seen = 0;
-    if (j == 0 && live) seen = atomicMax(&fl.accum[s], s_m[g]);
+    if (j == 0 && live) {
+      seen = atomicMax(&fl.accum[0][s], s_m[0][g]);
+      if (NS == 2) seen |= atomicMax(&fl.accum[1][s], s_m[NS - 1][g]);
+    }
     // the arrival waits for the returned maxima (one instruction for the
-    // wave): every maximum of this block is in place before it counts
+    // wave each): every maximum of this block is in place before it counts
     if (tid == 0 && seen != ~0ull) {
       const unsigned old = atomicAdd(fl.arrive, 1u);
       s_last = old == gridDim.x - 1;
@@ -248,8 +303,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 2))
   }
   __syncthreads();
   if (!s_last) return;
-  for (int64_t q = tid; q < batch; q += kThreads)
-    if (fl.active[q] && sip_status(q, k, max_iter, tol, fl, iters, relres, info)) s_any = 1;
+  for (int64_t q = tid; q < batch; q += kThreads) {
+    if (!fl.active[q]) continue;
+    const double r0 = take(fl.accum[0], q);
+    const double r1 = NS == 2 ? take(fl.accum[1], q) : 0.0;
+    // x_j sits in buffer j mod (NS + 1); a system that passes the test at k
+    // has k < max_iter, so k + 1 is a step it may still take
+    int keep = sip_test(q, k, r0, k % (NS + 1), max_iter, tol, fl, iters, relres, info);
+    if (NS == 2 && keep)
+      keep = sip_test(q, k + 1, r1, (k + 1) % (NS + 1), max_iter, tol, fl, iters, relres, info);
+    if (keep) s_any = 1;
+  }
   __syncthreads();
   if (tid == 0) {
     __hip_atomic_store(fl.arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -285,7 +349,8 @@ __global__ void init_kernel(int64_t batch, Flags fl, int32_t* iters, double* rel
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < batch;
        s += (int64_t)gridDim.x * blockDim.x) {
     fl.bnorm[s] = 0ull;
-    fl.accum[s] = 0ull;
+    fl.accum[0][s] = 0ull;
+    fl.accum[1][s] = 0ull;
     fl.active[s] = 0;
     fl.fin[s] = 0;
     fl.relres0[s] = 0.0;
@@ -305,23 +370,25 @@ __global__ void start_kernel(int64_t batch, Flags fl, int32_t* info) {
        s += (int64_t)gridDim.x * blockDim.x) {
     if (info[s] != 0) continue;  // unusable ILU(0) pivot: no step, x untouched
     if (fl.bnorm[s] == 0ull) {
-      fl.fin[s] = 2;  // b = 0: x = 0, no step
+      fl.fin[s] = kZero;  // b = 0: x = 0, no step
       continue;
     }
     fl.active[s] = 1;
   }
 }
 
-// The answer of every system into the caller's x.
+// The answer of every system into the caller's x (buffer 0).
 __global__ __launch_bounds__(256) void finish_kernel(int64_t n, int64_t batch, int64_t ld,
                                                      const double* __restrict__ X1,
+                                                     const double* __restrict__ X2,
                                                      double* __restrict__ X, Flags fl) {
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n * batch;
        q += (int64_t)gridDim.x * 256) {
     const int64_t s = q % batch, i = q / batch;
     const int f = fl.fin[s];
     if (f == 1) X[i * ld + s] = X1[i * ld + s];
-    else if (f == 2) X[i * ld + s] = 0.0;
+    else if (f == 2) X[i * ld + s] = X2[i * ld + s];
+    else if (f == kZero) X[i * ld + s] = 0.0;
   }
 }
 
@@ -331,7 +398,7 @@ int grid_for(int64_t work, int block) {
 }
 
 struct Layout {
-  size_t x1, active, fin, accum, bnorm, relres0, done, arrive, total;
+  size_t x1, x2, active, fin, accum0, accum1, bnorm, relres0, done, arrive, total;
 };
 
 Layout layout(int64_t n, int64_t batch, int64_t ld) {
@@ -339,9 +406,11 @@ Layout layout(int64_t n, int64_t batch, int64_t ld) {
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
   size_t o = 0;
   L.x1 = o;      o = up(o + (size_t)(n * ld) * 8);
+  L.x2 = o;      o = up(o + (size_t)(n * ld) * 8);
   L.active = o;  o = up(o + (size_t)batch * 4);
   L.fin = o;     o = up(o + (size_t)batch * 4);
-  L.accum = o;   o = up(o + (size_t)batch * 8);
+  L.accum0 = o;  o = up(o + (size_t)batch * 8);
+  L.accum1 = o;  o = up(o + (size_t)batch * 8);
   L.bnorm = o;   o = up(o + (size_t)batch * 8);
   L.relres0 = o; o = up(o + (size_t)batch * 8);
   L.done = o;    o = up(o + 4);
@@ -366,21 +435,26 @@ size_t sip_tile_workspace_bytes(int64_t n, int64_t batch, int64_t ld) {
 hipError_t launch_sip_tile(int64_t n, int64_t batch, int64_t ld, Diags A, const double* factors,
                            int64_t fld, bool own_factors, const double* y, double* x, double tol,
                            int32_t max_iter, int32_t sL, int32_t sU, int32_t* iters,
-                           double* relres, int32_t* info, void* ws, hipStream_t st) {
+                           double* relres, int32_t* info, void* ws, int steps_per_launch,
+                           hipStream_t st) {
   const Layout L = layout(n, batch, ld);
   char* base = static_cast<char*>(ws);
-  double* x1 = reinterpret_cast<double*>(base + L.x1);
+  double* buf[3] = {x, reinterpret_cast<double*>(base + L.x1),
+                    reinterpret_cast<double*>(base + L.x2)};
   Flags fl;
   fl.active = reinterpret_cast<int32_t*>(base + L.active);
   fl.fin = reinterpret_cast<int32_t*>(base + L.fin);
-  fl.accum = reinterpret_cast<unsigned long long*>(base + L.accum);
+  fl.accum[0] = reinterpret_cast<unsigned long long*>(base + L.accum0);
+  fl.accum[1] = reinterpret_cast<unsigned long long*>(base + L.accum1);
   fl.bnorm = reinterpret_cast<unsigned long long*>(base + L.bnorm);
   fl.relres0 = reinterpret_cast<double*>(base + L.relres0);
   fl.done = reinterpret_cast<int32_t*>(base + L.done);
   fl.arrive = reinterpret_cast<unsigned*>(base + L.arrive);
   const int KL = (1 << sL) - 1, KU = (1 << sU) - 1;
   const int HL = 2 * KL + 2, HR = 2 * KU + 2;
-  const int RC = kE - HL - HR;
+  // two steps per launch where their halos leave a core of 64 rows or more
+  const int NS = (steps_per_launch >= 2 && kE - 2 * (HL + HR) >= 64) ? 2 : 1;
+  const int RC = kE - NS * (HL + HR);
   const int64_t T = (n + RC - 1) / RC;
   const int64_t groups = (batch + kG - 1) / kG;
 
@@ -392,17 +466,23 @@ hipError_t launch_sip_tile(int64_t n, int64_t batch, int64_t ld, Diags A, const 
   hipLaunchKernelGGL(start_kernel, dim3(grid_for(batch, 256)), dim3(256), 0, st, batch, fl, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  for (int32_t k = 0; k <= max_iter; ++k) {
-    const double* xin = (k & 1) ? x1 : x;
-    double* xout = (k & 1) ? x : x1;
-    hipLaunchKernelGGL(sip_step_kernel, dim3((unsigned)(groups * T)), dim3(kThreads), 0, st, n,
-                       batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, y, xin, xout, KL, KU, HL,
-                       RC, (int)T, fl, k, max_iter, tol, iters, relres, info);
+  for (int32_t k = 0; k <= max_iter; k += NS) {
+    const double* xin = buf[k % (NS + 1)];
+    double* xo1 = buf[(k + 1) % (NS + 1)];
+    double* xo2 = buf[(k + 2) % (NS + 1)];
+    if (NS == 2)
+      hipLaunchKernelGGL((sip_step_kernel<8, 32, 2, 2>), dim3((unsigned)(groups * T)), dim3(kG * 32),
+                         0, st, n, batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, y, xin, xo1,
+                         xo2, KL, KU, HL, RC, (int)T, fl, k, max_iter, tol, iters, relres, info);
+    else
+      hipLaunchKernelGGL((sip_step_kernel<8, 32, 1, 2>), dim3((unsigned)(groups * T)), dim3(kG * 32),
+                         0, st, n, batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, y, xin, xo1,
+                         nullptr, KL, KU, HL, RC, (int)T, fl, k, max_iter, tol, iters, relres, info);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(finish_kernel, dim3(grid_for(n * batch, 256)), dim3(256), 0, st, n, batch,
-                     ld, x1, x, fl);
+                     ld, buf[1], buf[2], x, fl);
   return hipGetLastError();
 }
 

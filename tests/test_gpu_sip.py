@@ -11,13 +11,14 @@ from gpu_util import diags_of, host, rel_err, say, to_device
 
 pytestmark = pytest.mark.gpu
 
-SIP_PATHS = {"lane": 1, "tile": 2}
+SIP_PATHS = {"lane": 1, "tile": 2, "tile1": 3}
 
 
-@pytest.fixture(params=["lane", "tile"])
+@pytest.fixture(params=["lane", "tile", "tile1"])
 def sip_path(request):
     """Run the test with one lane per system and with the rows of a system
-    split over lanes (the latter only where both factors take HB steps)."""
+    split over lanes (the latter only where both factors take HB steps), two
+    steps per launch (where the halos fit) and one."""
     bs.set_option(bs.OPT_SIP_PATH, SIP_PATHS[request.param])
     yield request.param
     bs.set_option(bs.OPT_SIP_PATH, 0)
@@ -139,6 +140,47 @@ def test_split_rows_learned_start_workload_size():
     xs = x[:, pick].cpu().numpy().T
     xd, _ = oracle.npdm_batch(sub["e"], sub["c"], sub["d"], sub["a"], sub["b"], sub["y"])
     assert rel_err(xs, xd).max() <= 1e-7
+
+
+@pytest.mark.parametrize("case,sL,sU", [("sweep", 3, 4), ("sweep", 2, 2), ("ragged", 3, 3),
+                                         ("ragged", 4, 4), ("ragged", 1, 5)])
+def test_two_steps_per_launch_same_iterates(case, sL, sU):
+    """Two steps per launch (tests at k and k + 1 in one launch) against one
+    step per launch: bitwise the same x, iteration counts, residuals and
+    status, for max_iter of either parity (the last launch then has a step
+    to spare) and with systems that stop at different counts.  (1, 5) has
+    halos too wide for two steps: both options take the one-step kernel."""
+    if case == "sweep":
+        pd, _, _ = wl.config1(N=1024)
+        ws, batch, ld = {k: v[:200] for k, v in pd.items()}, 200, 256
+    else:
+        ws, batch, ld = wl.dominant_batch(37, 3001, seed=77), 37, 40
+        ws["y"][5] = 0.0                    # b = 0: x = 0, no step
+        ws["d"][9, 0] = 0.0                 # ILU(0) pivot u0_0 = 0: no step
+        ws["y"][11] *= 1e-300               # stops at a different count
+    t = to_device(ws, batch, ld=ld)
+    x0 = torch.from_numpy(wl.interleave(np.full((batch, ws["d"].shape[1]), 0.5), ld)).cuda()
+    for max_iter in (0, 1, 2, 5, 6, 100):
+        out = {}
+        for name, path in (("two", 2), ("one", 3)):
+            bs.set_option(bs.OPT_SIP_PATH, path)
+            try:
+                out[name] = bs.sip(diags_of(t), t["y"], x0.clone(), tol=1e-11,
+                                   max_iter=max_iter, s_L=sL, s_U=sU, batch=batch)
+            finally:
+                bs.set_option(bs.OPT_SIP_PATH, 0)
+        torch.cuda.synchronize()
+        (x2, it2, rr2, i2), (x1, it1, rr1, i1) = out["two"], out["one"]
+        say(f"{case} s=({sL},{sU}) max_iter={max_iter}: iters {it2.min().item()}..{it2.max().item()} "
+            f"status {sorted(set(i2.cpu().tolist()))}")
+        assert torch.equal(it2, it1) and torch.equal(i2, i1)
+        assert torch.equal(rr2.view(torch.int64), rr1.view(torch.int64))
+        assert torch.equal(x2[:, :batch].contiguous().view(torch.int64),
+                           x1[:, :batch].contiguous().view(torch.int64))
+        i = i2.cpu().numpy()
+        assert (it2.cpu().numpy() <= max_iter).all()
+        if case == "ragged":
+            assert i[9] == 1 and i[5] == 0 and it2[5].item() == 0
 
 
 def test_split_rows_bad_pivot_and_max_iter_zero():
