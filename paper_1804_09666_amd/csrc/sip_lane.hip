@@ -48,37 +48,13 @@ __global__ __launch_bounds__(kSipBlock) void sip_lane_kernel(
   const bool exactL = ML <= 0, exactU = MU <= 0;
   const bool literal = exactL && exactU;
 
-  // ||b||_inf; a zero right-hand side has the solution x = 0 and needs no step
+  // ||b||_inf and the usability of the ILU(0) pivots are gathered in the first
+  // forward pass (it reads y and u0 anyway): a zero right-hand side has the
+  // solution x = 0 and needs no step; a zero or non-finite u0 would make every
+  // step undefined.  That pass's other results are then dropped.
   double bnorm = 0.0;
-  {
-    double ry[16];
-    stream_rows<16, false>(
-        n, [&](int q, int64_t i) { ry[q] = Y[i * ld + s]; },
-        [&](int q, int64_t) { bnorm = fmax(bnorm, fabs(ry[q])); });
-  }
-  if (bnorm == 0.0) {
-    for (int64_t i = 0; i < n; ++i) X[i * ld + s] = 0.0;
-    iters[s] = 0;
-    relres[s] = 0.0;
-    info[s] = 0;
-    return;
-  }
-  // ILU(0) pivots must be usable (a zero u0 would make every step undefined)
-  {
-    int64_t bad = -1;
-    double ru[16];
-    stream_rows<16, false>(
-        n, [&](int q, int64_t i) { ru[q] = U0[i * fld + s]; },
-        [&](int q, int64_t i) {
-          if (bad < 0 && bad_pivot(ru[q])) bad = i;
-        });
-    if (bad >= 0) {
-      iters[s] = 0;
-      relres[s] = NAN;
-      info[s] = (int32_t)(bad + 1);
-      return;
-    }
-  }
+  int64_t bad = -1;
+  bool first = true;
 
   double relres0 = -1.0, rr = 0.0;
   int32_t k = 0, status = -1;
@@ -127,6 +103,10 @@ __global__ __launch_bounds__(kSipBlock) void sip_lane_kernel(
       if (i + 1 < n) ax = ax + ai * xp1;
       if (i + 2 < n) ax = ax + bi * xp2;
       const double yi = ry[q];
+      if (first) {
+        bnorm = fmax(bnorm, fabs(yi));
+        if (bad < 0 && bad_pivot(ru0[q])) bad = i;
+      }
       const double r = yi - ax;
       const double ar = fabs(r);
       if (!isfinite(ar)) nonfinite = true;
@@ -177,6 +157,22 @@ __global__ __launch_bounds__(kSipBlock) void sip_lane_kernel(
       xp1 = xp2;
     };
     stream_rows<PFF, false>(n, fetch, use);
+    if (first) {
+      first = false;
+      if (bnorm == 0.0) {
+        for (int64_t i = 0; i < n; ++i) X[i * ld + s] = 0.0;
+        iters[s] = 0;
+        relres[s] = 0.0;
+        info[s] = 0;
+        return;
+      }
+      if (bad >= 0) {
+        iters[s] = 0;
+        relres[s] = NAN;
+        info[s] = (int32_t)(bad + 1);
+        return;
+      }
+    }
     rr = nonfinite ? NAN : rmax / bnorm;
     if (relres0 < 0.0) relres0 = rr;
     if (!isfinite(rr)) { status = -2; break; }
