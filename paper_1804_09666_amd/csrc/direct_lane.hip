@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kLaneBlock) void factor_lane_kernel(
 constexpr int64_t kFactorWarm = 80;
 // lanes to aim for: the warm-up rows are read twice, so fewer, longer chunks
 // win once the GPU has a few thousand waves of them (measured)
-constexpr int64_t kFactorLanes[2] = {16384, 32768};  // PD, TD
+constexpr int64_t kFactorLanes[2] = {32768, 32768};  // PD, TD
 
 __global__ void info_init_kernel(int64_t batch, int32_t* __restrict__ info) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

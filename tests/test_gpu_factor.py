@@ -18,9 +18,9 @@ KEYS = {5: ("e", "c", "d", "a", "b"), 3: ("c", "d", "a")}
 
 
 def chunk_rows(n, batch, kind=5):
-    """Rows per chunk the library picks: about 16384 (PD) or 32768 (TD)
-    lanes, chunks >= 64 rows."""
-    K = min(-(-(16384 if kind == 5 else 32768) // batch), n // 64)
+    """Rows per chunk the library picks: about 32768 lanes, chunks >= 64
+    rows."""
+    K = min(-(-32768 // batch), n // 64)
     if K <= 1:
         return n
     return -(-n // K)
