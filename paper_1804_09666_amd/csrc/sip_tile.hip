@@ -10,20 +10,22 @@
 // Every sweep is row-parallel and L, U have bandwidth 2, so row i of the
 // result depends on x only at rows i - 2 K_L - 2 .. i + 2 K_U + 2.  A block
 // therefore owns a tile of "core" rows plus halos of HL = 2 K_L + 2 rows
-// before and HR = 2 K_U + 2 rows after it, computes the residual and all the
-// sweeps for the whole extended range in registers (one LDS exchange of two
-// boundary values per sweep between neighbouring lanes), and writes x for its
-// core rows only.  The result at every core row is the one a sweep over the
-// whole system produces, with the same operations; the tiling does not change
-// it.
+// before and HR = 2 K_U + 2 rows after it per step, computes the residual and
+// all the sweeps for the whole extended range in registers (one LDS exchange
+// of two boundary values per sweep between neighbouring lanes), and writes x
+// for its core rows only.  The result at every core row is the one a sweep
+// over the whole system produces, with the same operations; the tiling does
+// not change it.
 //
-// One launch per step.  The convergence test must see the whole residual of
-// a system, which spans many blocks, so a step reads x_k from one buffer,
-// accumulates ||b - A x_k||_inf per system, and always writes the candidate
-// x_{k+1} to the other buffer; the last block of the step to finish (an
-// arrival counter) then decides, per system, whether x_k was already the
-// answer (the candidate is dropped), the step count, the status, and a device
-// flag that makes the remaining launches return at once.
+// One launch takes two steps (halos 2 HL and 2 HR; the rows of A, b and the
+// factors are loaded once for both), or one where the doubled halos leave
+// too small a core.  The convergence test must see the whole residual of a
+// system, which spans many blocks, so a launch reads x_k from one buffer,
+// accumulates ||b - A x_k||_inf (and ||b - A x_{k+1}||_inf) per system, and
+// always writes the candidates x_{k+1} (and x_{k+2}) to the next buffers; the
+// last block of the launch to finish (an arrival counter) then decides, per
+// system, which iterate is the answer, the step count, the status, and a
+// device flag that makes the remaining launches return at once.
 #include "bs_internal.h"
 
 // Products and sums may contract into FMAs, the upper sweeps multiply by 1/u0
