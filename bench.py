@@ -846,6 +846,7 @@ def main():
         "stream_ceiling_GBps": ceiling,
         "frac_of_stream_ceiling": achieved / ceiling,
         "kernel_us_mean": kern_ms * 1e3,
+        "kernel_us_median": float(np.median(per) * 1e3),
         "kernel_us_p10_p90": [float(np.percentile(per, 10) * 1e3),
                               float(np.percentile(per, 90) * 1e3)],
         "info_ok": ok,
