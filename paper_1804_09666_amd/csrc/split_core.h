@@ -69,13 +69,17 @@ __device__ inline bool inv(const double (&M)[1][1], double (&R)[1][1]) {
   return M[0][0] != 0.0 && isfinite(R[0][0]);
 }
 // 1/x from the hardware reciprocal estimate and two Newton steps (full
-// double precision up to an ulp; the interface blocks are far from the
-// subnormal range).
+// double precision up to an ulp; pivots and interface blocks are far from the
+// subnormal range).  The chunk recurrences divide by every pivot in a chain
+// of dependent operations, and this is half as long as IEEE division; a zero
+// or non-finite pivot is reported from the pivot itself.
 __device__ inline double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
+  const double r0 = __builtin_amdgcn_rcp(x);
+  double r = fma(r0, fma(-x, r0, 1.0), r0);
   r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
+  // the estimate alone is exact for the special cases (+-0 -> +-inf,
+  // +-inf -> +-0, as 1/x), where the Newton steps would give NaN
+  return (x != 0.0 && isfinite(x)) ? r : r0;
 }
 __device__ inline bool inv(const double (&M)[2][2], double (&R)[2][2]) {
   const double det = fma(M[0][0], M[1][1], -M[0][1] * M[1][0]);
@@ -201,7 +205,7 @@ __device__ inline void chunk_pd(const double (&e)[M], const double (&c)[M],
       mu = fma(-al[r - 1], ga, fma(-be[r - 2], e[r], d[r]));
     }
     if (bad == M && bad_pivot(mu)) bad = r;
-    const double rc = 1.0 / mu;
+    const double rc = recip(mu);  // off the IEEE division's longer chain
     if (r == 0)
       al[0] = a[0] * rc;
     else if (r <= M - 2)
@@ -256,7 +260,7 @@ __device__ inline void chunk_td(const double (&c)[M], const double (&d)[M],
   for (int r = 0; r < M; ++r) {
     const double mu = (r == 0) ? d[0] : fma(-al[r - 1], c[r], d[r]);
     if (bad == M && bad_pivot(mu)) bad = r;
-    const double rc = 1.0 / mu;
+    const double rc = recip(mu);  // off the IEEE division's longer chain
     al[r] = (r <= M - 2) ? a[r] * rc : 0.0;
     if (r == 0) {
       p[0] = y[0] * rc;
