@@ -183,6 +183,44 @@ def test_two_steps_per_launch_same_iterates(case, sL, sU):
             assert i[9] == 1 and i[5] == 0 and it2[5].item() == 0
 
 
+@pytest.mark.parametrize("sL,sU", [(3, 4), (1, 6)])
+def test_split_rows_graph_replay(sL, sU):
+    """One captured sip_solve (factorization, norms, every step launch and the
+    final copy; two steps per launch for (3, 4), one for (1, 6)) replayed three times, with eager solves on other data in
+    between: every replay bitwise the eager result (the arrival counter, the
+    done flag and the accumulators start clean each time)."""
+    ws = wl.dominant_batch(48, 2500, seed=31)
+    other = wl.dominant_batch(48, 2500, seed=32)
+    t, t2 = to_device(ws, 48, ld=64), to_device(other, 48, ld=64)
+    nbytes = bs.workspace_bytes(bs.OP_SIP, 5, 2500, 48, ld=64)
+    wsb = torch.zeros((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(t["y"])
+    x_ref, it_ref, rr_ref, i_ref = bs.sip(diags_of(t), t["y"], torch.zeros_like(t["y"]), tol=1e-11,
+                                          max_iter=60, s_L=sL, s_U=sU, batch=48)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            out = bs.sip(diags_of(t), t["y"], x=x, tol=1e-11, max_iter=60, s_L=sL, s_U=sU,
+                         batch=48, workspace=wsb, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        x.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        _, it, rr, info = out
+        say(f"graph replay {rep} s=({sL},{sU}): iters {it.min().item()}..{it.max().item()}")
+        assert torch.equal(x[:, :48].contiguous().view(torch.int64),
+                           x_ref[:, :48].contiguous().view(torch.int64))
+        assert torch.equal(it, it_ref) and torch.equal(info, i_ref)
+        assert torch.equal(rr.view(torch.int64), rr_ref.view(torch.int64))
+        # eager work on other data in between (its own workspace)
+        bs.sip(diags_of(t2), t2["y"], tol=1e-11, max_iter=60, s_L=sL, s_U=sU, batch=48)
+        torch.cuda.synchronize()
+
+
 def test_split_rows_bad_pivot_and_max_iter_zero():
     ws = wl.dominant_batch(4, 600, seed=13)
     ws["d"][2, 0] = 0.0     # ILU(0) pivot u0_0 = 0: no step, x untouched
