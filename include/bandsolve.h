@@ -109,10 +109,11 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
  *   BS_OPT_PART_PD_VARIANT index of the split-row PD kernel variant
  *   BS_OPT_PART_TD_VARIANT index of the split-row TD kernel variant
  *   BS_OPT_SIP_PATH        sip_solve kernel: 0 and 2 rows of a system split
- *                          over lanes where the HB steps allow it, two steps
- *                          per launch where their halos fit (default), 1 one
- *                          lane per system, 3 rows split over lanes with one
- *                          step per launch (same iterates as 0)
+ *                          over lanes where the HB steps allow it, up to three
+ *                          steps per launch where their halos fit (default),
+ *                          1 one lane per system, 3 (4) rows split over lanes
+ *                          with one step (at most two steps) per launch (same
+ *                          iterates as 0)
  *   BS_OPT_EXCHANGE_WAIT_US longest wait, in microseconds (0 .. 10^7, default
  *                          10^6), of a split-row block for the other blocks of
  *                          its system before it gives up and the system's
@@ -279,11 +280,12 @@ int32_t band_solve_mnpdm(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
  * (0, -1, -2 or a pivot row + 1) are written per system.  dtype BS_F64.
  * Kernels: with HB for both factors (s_L, s_U >= 0, 2^s < n, and
  *   2^s_L + 2^s_U <= 96) the rows of a system are split over many lanes and
- *   every launch takes two steps over all rows (one step when
- *   2^s_L + 2^s_U > 48), whose last block to finish applies the stopping test
- *   at both step counts: about (max_iter + 1) / 2 launches are enqueued, and
- *   those after the last system has stopped return at once.  The iterates do
- *   not depend on the steps per launch.  Otherwise (exact substitution, Algorithm 1
+ *   every launch takes three steps over all rows where 2^s_L + 2^s_U <= 16,
+ *   two where it is <= 48, else one; its last block to finish applies the
+ *   stopping test at each step count in turn: about (max_iter + 1) / 3 (or
+ *   / 2, / 1) launches are enqueued, and those after the last system has
+ *   stopped return at once.  The iterates do not depend on the steps per
+ *   launch.  Otherwise (exact substitution, Algorithm 1
  *   as written) one lane walks each system in one persistent launch.
  * workspace: bs_workspace_bytes(BS_OP_SIP, ...) bytes, 256-byte aligned; its
  *   contents need no initialisation.  x and rhs must not alias. */

@@ -165,7 +165,7 @@ int32_t bs_set_option(int32_t key, int64_t value) {
       g_direct_path = value;
       return BS_OK;
     case BS_OPT_SIP_PATH:
-      if (value < 0 || value > 3) return BS_EINVAL;
+      if (value < 0 || value > 4) return BS_EINVAL;
       g_sip_path = value;
       return BS_OK;
     case BS_OPT_EXCHANGE_WAIT_US:
@@ -423,8 +423,8 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
     return launched(bs::launch_sip_tile(n, batch, ld, A, F, fld, own,
                                         static_cast<const double*>(rhs),
                                         static_cast<double*>(x), tol, max_iter, hb_s_L,
-                                        hb_s_U, iters, relres, info, rest, path == 3 ? 1 : 2,
-                                        st));
+                                        hb_s_U, iters, relres, info, rest,
+                                        path == 3 ? 1 : (path == 4 ? 2 : 3), st));
   return launched(bs::launch_sip_lane(n, batch, ld, A, F, fld,
                                       static_cast<const double*>(rhs),
                                       static_cast<double*>(x), tol, max_iter,

@@ -45,7 +45,8 @@ constexpr int kE = 256;  // rows of a tile including its halos
 //   one step per launch:  8 x 32, 512 threads at two waves per SIMD;
 //   two steps per launch: 16 x 16, 256 threads at one wave per SIMD (the rows
 //     of A and the right-hand side stay live through the first step).
-constexpr int kZero = 3;  // fin: the answer is x = 0 (b = 0)
+constexpr int kMaxSteps = 3;  // steps per launch at most
+constexpr int kZero = 7;      // fin: the answer is x = 0 (b = 0)
 
 __device__ inline void atomic_max_nonneg(unsigned long long* p, double v) {
   atomicMax(p, (unsigned long long)__double_as_longlong(v));  // v >= 0 or NaN
@@ -58,7 +59,7 @@ __device__ inline double as_double(unsigned long long u) {
 struct Flags {
   int32_t* active;               // 1 while the system still steps
   int32_t* fin;                  // buffer holding the answer (0 = caller's x), or kZero
-  unsigned long long* accum[2];  // ||r_k||_inf, ||r_{k+1}||_inf of the launch in flight (bits)
+  unsigned long long* accum[kMaxSteps];  // ||r_k||_inf, ||r_{k+1}||_inf, ... of the launch in flight (bits)
   unsigned long long* bnorm;     // ||b||_inf (bits)
   double* relres0;
   int32_t* done;
@@ -196,23 +197,28 @@ __device__ inline void upper_sweeps(int KU, const double (&w)[KM], const double 
   }
 }
 
-// NS steps of Algorithm 1 (NS = 1 or 2) for every system in one launch.
-// Launch k reads x_k from buffer k mod (NS + 1) and writes x_{k+1} (and
-// x_{k+2}) to the next buffers; the tile has halos of NS * HL rows before and
-// NS * HR after its RC core rows, which is what NS steps need for every core
-// row to get exactly the value of steps over the whole system.
+// The buffers a launch writes x_{k+1}, ..., x_{k+NS} to.
+struct Outs {
+  double* p[kMaxSteps];
+};
+
+// NS steps of Algorithm 1 (1 <= NS <= 3) for every system in one launch.
+// Launch k reads x_k from buffer k mod (NS + 1) and writes x_{k+1}, ...,
+// x_{k+NS} to the next buffers; the tile has halos of NS * HL rows before
+// and NS * HR after its RC core rows, which is what NS steps need for every
+// core row to get exactly the value of steps over the whole system.
 // The last block of the launch to finish (an arrival counter) applies the
-// test at k, then at k + 1, for every system still stepping.
+// test at k, k + 1, ... in turn for every system still stepping.
 template <int KM, int KPW, int NS, int WPE>
 __global__ __launch_bounds__(kG * KPW) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void sip_step_kernel(
     int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
     const double* __restrict__ C, const double* __restrict__ D, const double* __restrict__ A,
     const double* __restrict__ B, const double* __restrict__ F, int64_t fld,
-    const double* __restrict__ Y, const double* __restrict__ Xin, double* __restrict__ Xo1,
-    double* __restrict__ Xo2, int KL, int KU, int HL, int RC, int T, Flags fl, int32_t k,
+    const double* __restrict__ Y, const double* __restrict__ Xin, Outs xo,
+    int KL, int KU, int HL, int RC, int T, Flags fl, int32_t k,
     int32_t max_iter, double tol, int32_t* __restrict__ iters, double* __restrict__ relres,
     int32_t* __restrict__ info) {
-  static_assert(KM * KPW == kE && KM >= 4 && (NS == 1 || NS == 2), "shape");
+  static_assert(KM * KPW == kE && KM >= 4 && NS >= 1 && NS <= kMaxSteps, "shape");
   constexpr int kThreads = kG * KPW;
   if (*fl.done) return;
   __shared__ Halo<KPW> H;
@@ -278,7 +284,7 @@ __global__ __launch_bounds__(kG * KPW) __attribute__((amdgpu_waves_per_eu(WPE, W
 #pragma unroll
     for (int r = 0; r < KM; ++r) x[r] = x[r] + z[r];
     if (live) {  // x_{k+u+1} at the core rows
-      double* __restrict__ Xo = u == 0 ? Xo1 : Xo2;
+      double* __restrict__ Xo = xo.p[u];
 #pragma unroll
       for (int r = 0; r < KM; ++r) {
         const int q = j * KM + r;
@@ -292,8 +298,8 @@ __global__ __launch_bounds__(kG * KPW) __attribute__((amdgpu_waves_per_eu(WPE, W
   if (tid < 64) {  // wave 0: this block's maxima, then its arrival
     unsigned long long seen = 0;
     if (j == 0 && live) {
-      seen = atomicMax(&fl.accum[0][s], s_m[0][g]);
-      if (NS == 2) seen |= atomicMax(&fl.accum[1][s], s_m[NS - 1][g]);
+#pragma unroll
+      for (int u = 0; u < NS; ++u) seen |= atomicMax(&fl.accum[u][s], s_m[u][g]);
     }
     // the arrival waits for the returned maxima (one instruction for the
     // wave each): every maximum of this block is in place before it counts
@@ -307,13 +313,17 @@ __global__ __launch_bounds__(kG * KPW) __attribute__((amdgpu_waves_per_eu(WPE, W
   if (!s_last) return;
   for (int64_t q = tid; q < batch; q += kThreads) {
     if (!fl.active[q]) continue;
-    const double r0 = take(fl.accum[0], q);
-    const double r1 = NS == 2 ? take(fl.accum[1], q) : 0.0;
-    // x_j sits in buffer j mod (NS + 1); a system that passes the test at k
-    // has k < max_iter, so k + 1 is a step it may still take
-    int keep = sip_test(q, k, r0, k % (NS + 1), max_iter, tol, fl, iters, relres, info);
-    if (NS == 2 && keep)
-      keep = sip_test(q, k + 1, r1, (k + 1) % (NS + 1), max_iter, tol, fl, iters, relres, info);
+    double r[NS];
+#pragma unroll
+    for (int u = 0; u < NS; ++u) r[u] = take(fl.accum[u], q);
+    // x_j sits in buffer j mod (NS + 1); a system that passes the test at
+    // k + u has k + u < max_iter, so k + u + 1 is a step it may still take
+    int keep = 1;
+#pragma unroll
+    for (int u = 0; u < NS; ++u)
+      if (keep)
+        keep = sip_test(q, k + u, r[u], (k + u) % (NS + 1), max_iter, tol, fl, iters, relres,
+                        info);
     if (keep) s_any = 1;
   }
   __syncthreads();
@@ -351,8 +361,8 @@ __global__ void init_kernel(int64_t batch, Flags fl, int32_t* iters, double* rel
   for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < batch;
        s += (int64_t)gridDim.x * blockDim.x) {
     fl.bnorm[s] = 0ull;
-    fl.accum[0][s] = 0ull;
-    fl.accum[1][s] = 0ull;
+#pragma unroll
+    for (int u = 0; u < kMaxSteps; ++u) fl.accum[u][s] = 0ull;
     fl.active[s] = 0;
     fl.fin[s] = 0;
     fl.relres0[s] = 0.0;
@@ -381,15 +391,13 @@ __global__ void start_kernel(int64_t batch, Flags fl, int32_t* info) {
 
 // The answer of every system into the caller's x (buffer 0).
 __global__ __launch_bounds__(256) void finish_kernel(int64_t n, int64_t batch, int64_t ld,
-                                                     const double* __restrict__ X1,
-                                                     const double* __restrict__ X2,
-                                                     double* __restrict__ X, Flags fl) {
+                                                     Outs more, double* __restrict__ X,
+                                                     Flags fl) {
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n * batch;
        q += (int64_t)gridDim.x * 256) {
     const int64_t s = q % batch, i = q / batch;
-    const int f = fl.fin[s];
-    if (f == 1) X[i * ld + s] = X1[i * ld + s];
-    else if (f == 2) X[i * ld + s] = X2[i * ld + s];
+    const int f = fl.fin[s];  // buffers 1.. are more.p[0..]
+    if (f >= 1 && f <= kMaxSteps) X[i * ld + s] = more.p[f - 1][i * ld + s];
     else if (f == kZero) X[i * ld + s] = 0.0;
   }
 }
@@ -400,19 +408,23 @@ int grid_for(int64_t work, int block) {
 }
 
 struct Layout {
-  size_t x1, x2, active, fin, accum0, accum1, bnorm, relres0, done, arrive, total;
+  size_t x[kMaxSteps], active, fin, accum[kMaxSteps], bnorm, relres0, done, arrive, total;
 };
 
 Layout layout(int64_t n, int64_t batch, int64_t ld) {
   Layout L;
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
   size_t o = 0;
-  L.x1 = o;      o = up(o + (size_t)(n * ld) * 8);
-  L.x2 = o;      o = up(o + (size_t)(n * ld) * 8);
+  for (int u = 0; u < kMaxSteps; ++u) {  // x buffers 1..kMaxSteps
+    L.x[u] = o;
+    o = up(o + (size_t)(n * ld) * 8);
+  }
   L.active = o;  o = up(o + (size_t)batch * 4);
   L.fin = o;     o = up(o + (size_t)batch * 4);
-  L.accum0 = o;  o = up(o + (size_t)batch * 8);
-  L.accum1 = o;  o = up(o + (size_t)batch * 8);
+  for (int u = 0; u < kMaxSteps; ++u) {
+    L.accum[u] = o;
+    o = up(o + (size_t)batch * 8);
+  }
   L.bnorm = o;   o = up(o + (size_t)batch * 8);
   L.relres0 = o; o = up(o + (size_t)batch * 8);
   L.done = o;    o = up(o + 4);
@@ -441,21 +453,27 @@ hipError_t launch_sip_tile(int64_t n, int64_t batch, int64_t ld, Diags A, const 
                            hipStream_t st) {
   const Layout L = layout(n, batch, ld);
   char* base = static_cast<char*>(ws);
-  double* buf[3] = {x, reinterpret_cast<double*>(base + L.x1),
-                    reinterpret_cast<double*>(base + L.x2)};
+  double* buf[kMaxSteps + 1] = {x};
+  Outs more;
+  for (int u = 0; u < kMaxSteps; ++u) more.p[u] = buf[u + 1] = reinterpret_cast<double*>(base + L.x[u]);
   Flags fl;
   fl.active = reinterpret_cast<int32_t*>(base + L.active);
   fl.fin = reinterpret_cast<int32_t*>(base + L.fin);
-  fl.accum[0] = reinterpret_cast<unsigned long long*>(base + L.accum0);
-  fl.accum[1] = reinterpret_cast<unsigned long long*>(base + L.accum1);
+  for (int u = 0; u < kMaxSteps; ++u)
+    fl.accum[u] = reinterpret_cast<unsigned long long*>(base + L.accum[u]);
   fl.bnorm = reinterpret_cast<unsigned long long*>(base + L.bnorm);
   fl.relres0 = reinterpret_cast<double*>(base + L.relres0);
   fl.done = reinterpret_cast<int32_t*>(base + L.done);
   fl.arrive = reinterpret_cast<unsigned*>(base + L.arrive);
   const int KL = (1 << sL) - 1, KU = (1 << sU) - 1;
   const int HL = 2 * KL + 2, HR = 2 * KU + 2;
-  // two steps per launch where their halos leave a core of 64 rows or more
-  const int NS = (steps_per_launch >= 2 && kE - 2 * (HL + HR) >= 64) ? 2 : 1;
+  // three steps per launch where their halos leave a core of 160 rows or
+  // more, two where they leave 64, else one
+  int NS = 1;
+  if (steps_per_launch >= 3 && kE - 3 * (HL + HR) >= 160)
+    NS = 3;
+  else if (steps_per_launch >= 2 && kE - 2 * (HL + HR) >= 64)
+    NS = 2;
   const int RC = kE - NS * (HL + HR);
   const int64_t T = (n + RC - 1) / RC;
   const int64_t groups = (batch + kG - 1) / kG;
@@ -468,23 +486,28 @@ hipError_t launch_sip_tile(int64_t n, int64_t batch, int64_t ld, Diags A, const 
   hipLaunchKernelGGL(start_kernel, dim3(grid_for(batch, 256)), dim3(256), 0, st, batch, fl, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  const dim3 grid((unsigned)(groups * T)), block(kG * 32);
   for (int32_t k = 0; k <= max_iter; k += NS) {
     const double* xin = buf[k % (NS + 1)];
-    double* xo1 = buf[(k + 1) % (NS + 1)];
-    double* xo2 = buf[(k + 2) % (NS + 1)];
-    if (NS == 2)
-      hipLaunchKernelGGL((sip_step_kernel<8, 32, 2, 2>), dim3((unsigned)(groups * T)), dim3(kG * 32),
-                         0, st, n, batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, y, xin, xo1,
-                         xo2, KL, KU, HL, RC, (int)T, fl, k, max_iter, tol, iters, relres, info);
+    Outs xo{};
+    for (int u = 0; u < NS; ++u) xo.p[u] = buf[(k + 1 + u) % (NS + 1)];
+    if (NS == 3)
+      hipLaunchKernelGGL((sip_step_kernel<8, 32, 3, 2>), grid, block, 0, st, n, batch, ld, A.e,
+                         A.c, A.d, A.a, A.b, factors, fld, y, xin, xo, KL, KU, HL, RC, (int)T, fl,
+                         k, max_iter, tol, iters, relres, info);
+    else if (NS == 2)
+      hipLaunchKernelGGL((sip_step_kernel<8, 32, 2, 2>), grid, block, 0, st, n, batch, ld, A.e,
+                         A.c, A.d, A.a, A.b, factors, fld, y, xin, xo, KL, KU, HL, RC, (int)T, fl,
+                         k, max_iter, tol, iters, relres, info);
     else
-      hipLaunchKernelGGL((sip_step_kernel<8, 32, 1, 2>), dim3((unsigned)(groups * T)), dim3(kG * 32),
-                         0, st, n, batch, ld, A.e, A.c, A.d, A.a, A.b, factors, fld, y, xin, xo1,
-                         nullptr, KL, KU, HL, RC, (int)T, fl, k, max_iter, tol, iters, relres, info);
+      hipLaunchKernelGGL((sip_step_kernel<8, 32, 1, 2>), grid, block, 0, st, n, batch, ld, A.e,
+                         A.c, A.d, A.a, A.b, factors, fld, y, xin, xo, KL, KU, HL, RC, (int)T, fl,
+                         k, max_iter, tol, iters, relres, info);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(finish_kernel, dim3(grid_for(n * batch, 256)), dim3(256), 0, st, n, batch,
-                     ld, buf[1], buf[2], x, fl);
+                     ld, more, x, fl);
   return hipGetLastError();
 }
 

@@ -66,10 +66,10 @@ def test_workspace_query(bs):
         assert bs.workspace_bytes(bs.OP_SOLVE_FACTORED, 5, n, batch) == 0
     finally:
         bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_AUTO)
-    # SIP: four factor planes (pitch lw), then two more x buffers (pitch ld = batch) and the
-    # per-system state (2 int32 and 4 double arrays, a flag and a counter, each 256-byte aligned)
+    # SIP: four factor planes (pitch lw), then three more x buffers (pitch ld = batch) and the
+    # per-system state (2 int32 and 5 double arrays, a flag and a counter, each 256-byte aligned)
     assert bs.workspace_bytes(bs.OP_SIP, 5, n, batch) == \
-        4 * n * lw * 8 + 2 * n * batch * 8 + 2 * 512 + 4 * 1024 + 2 * 256
+        4 * n * lw * 8 + 3 * n * batch * 8 + 2 * 512 + 5 * 1024 + 2 * 256
     # MNPDM: the split PD kernel's exchange area, or alpha and beta planes
     assert bs.workspace_bytes(bs.OP_MNPDM, 5, n, batch) == \
         bs.workspace_bytes(bs.OP_SOLVE, 5, n, batch)
@@ -139,7 +139,7 @@ def test_options(bs):
     with pytest.raises(bs.BandSolveError):
         bs.set_option(99, 1)
     with pytest.raises(bs.BandSolveError):
-        bs.set_option(bs.OPT_SIP_PATH, 4)
+        bs.set_option(bs.OPT_SIP_PATH, 5)
     assert bs.get_option(bs.OPT_SIP_PATH) == 0
     bs.set_option(bs.OPT_SIP_PATH, 3)
     assert bs.get_option(bs.OPT_SIP_PATH) == 3

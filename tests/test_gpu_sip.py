@@ -144,12 +144,12 @@ def test_split_rows_learned_start_workload_size():
 
 @pytest.mark.parametrize("case,sL,sU", [("sweep", 3, 4), ("sweep", 2, 2), ("ragged", 3, 3),
                                          ("ragged", 4, 4), ("ragged", 1, 5)])
-def test_two_steps_per_launch_same_iterates(case, sL, sU):
-    """Two steps per launch (tests at k and k + 1 in one launch) against one
-    step per launch: bitwise the same x, iteration counts, residuals and
-    status, for max_iter of either parity (the last launch then has a step
-    to spare) and with systems that stop at different counts.  (1, 5) has
-    halos too wide for two steps: both options take the one-step kernel."""
+def test_several_steps_per_launch_same_iterates(case, sL, sU):
+    """Several steps per launch (three for (2, 2) and (3, 3), two for the
+    others: tests at k, k + 1, ... in one launch) against one step per
+    launch: bitwise the same x, iteration counts, residuals and status, for
+    max_iter of every residue (the last launch then has steps to spare) and
+    with systems that stop at different counts."""
     if case == "sweep":
         pd, _, _ = wl.config1(N=1024)
         ws, batch, ld = {k: v[:200] for k, v in pd.items()}, 200, 256
@@ -160,7 +160,7 @@ def test_two_steps_per_launch_same_iterates(case, sL, sU):
         ws["y"][11] *= 1e-300               # stops at a different count
     t = to_device(ws, batch, ld=ld)
     x0 = torch.from_numpy(wl.interleave(np.full((batch, ws["d"].shape[1]), 0.5), ld)).cuda()
-    for max_iter in (0, 1, 2, 5, 6, 100):
+    for max_iter in (0, 1, 2, 3, 5, 6, 7, 100):
         out = {}
         for name, path in (("two", 2), ("one", 3)):
             bs.set_option(bs.OPT_SIP_PATH, path)
