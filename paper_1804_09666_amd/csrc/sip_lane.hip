@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kSipBlock) void sip_lane_kernel(
     double wm1 = 0.0, wm2 = 0.0;  // exact L solve: w_{i-1}, w_{i-2}
     // Algorithm 1 as written: K = LU - A on the fly from factor rows i-1, i-2
     double u0m1 = 0, u0m2 = 0, u1m1 = 0, u1m2 = 0, u2m1 = 0, u2m2 = 0;
-    constexpr int PFF = MMAX >= 64 ? 1 : 4;  // 11 loads + 1 store per row; registers at 64 stages
+    constexpr int PFF = MMAX >= 64 ? 1 : 5;  // 11 loads + 1 store per row: 60 memory operations in flight; registers at 64 stages
     double rx2[PFF], re[PFF], rc[PFF], rd[PFF], ra[PFF], rb[PFF], ry[PFF], rl2[PFF], rl1[PFF],
         ru0[PFF], ru1[PFF];
     auto fetch = [&](int q, int64_t i) {
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kSipBlock) void sip_lane_kernel(
 #pragma unroll
     for (int t = 0; t < MMAX; ++t) pu1[t] = pu2[t] = 0.0;
     double qp1 = 0.0, qp2 = 0.0;  // exact U solve: q_{i+1}, q_{i+2}
-    constexpr int PFB = MMAX >= 64 ? 1 : 8;  // 5 loads + 1 store per row
+    constexpr int PFB = MMAX >= 64 ? 1 : 10;  // 5 loads + 1 store per row: 60 in flight
     double bv[PFB], bu0[PFB], bu1[PFB], bu2[PFB], bx[PFB];
     auto fetchb = [&](int q, int64_t i) {
       const int64_t o = i * ld + s;
