@@ -298,7 +298,7 @@ __global__ __launch_bounds__(G * PW) void long_tile_kernel(
   __syncthreads();
   if (!FINISH && bad < M && row_base + r0 + bad < n)
     atomicMin(&s_bad[g], (int)(row_base + r0 + bad + 1));
-  tree_up<NB, PW, G>(mp, j, g, s_node, s_bad, M, row_base, n);
+  tree_up<NB, PW, G, true>(mp, j, g, s_node, s_bad, M, row_base, n);
   const int64_t rec = (grp * T + tile) * G + g;
   if constexpr (!FINISH) {
     if (j == 0) {
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(G * PW) void long_tile_kernel(
       }
     }
     __syncthreads();
-    tree_down<NB, PW, G>(xl, xr, j, g, s_node);
+    tree_down<NB, PW, G, true>(xl, xr, j, g, s_node);
     write_chunk<NB, M>(n, ld, s, live, r0, row_base, p, v, w, xl, xr, X + shift);
   }
 }

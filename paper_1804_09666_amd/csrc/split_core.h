@@ -285,7 +285,28 @@ __device__ inline void chunk_td(const double (&c)[M], const double (&d)[M],
 // left child merges and overwrites it with the node record, and on the way
 // down the left child replaces the record with the right child's outer pairs.
 // leaf_rows: rows per leaf, row0: first row of leaf 0 (for breakdown rows).
-template <int NB, int NL, int G>
+// With LANES, levels whose two children sit in one wave (leaf = lane / G
+// within a wave of 64 lanes: 2 * half * G divides 64) pass the right child's
+// record with cross-lane moves instead of LDS and a block barrier.  Measured,
+// this pays for the small tridiagonal records and the one-wave trees (G = 1),
+// and in the long-system and uneven-batch tile kernels; in the single-launch
+// split kernel a pentadiagonal record (20 doubles, 40 moves per level) costs
+// as much as the LDS round trip it replaces, so that one keeps LDS.
+template <int G>
+__device__ constexpr bool in_wave(int half) {
+  return 2 * half * G <= 64 && 64 % (2 * half * G) == 0;
+}
+template <typename R>
+__device__ inline R shfl_down_rec(const R& r, int delta) {
+  R out;
+  const double* src = reinterpret_cast<const double*>(&r);
+  double* dst = reinterpret_cast<double*>(&out);
+#pragma unroll
+  for (int q = 0; q < (int)(sizeof(R) / sizeof(double)); ++q) dst[q] = __shfl_down(src[q], delta, 64);
+  return out;
+}
+
+template <int NB, int NL, int G, bool LANES = (NB == 1 || G == 1)>
 __device__ inline void tree_up(Map<NB>& mp, int leaf, int g, double* s_node,
                                int* s_bad, int64_t leaf_rows, int64_t row0, int64_t n) {
   constexpr int RS = kRecSz<NB>;
@@ -297,17 +318,21 @@ __device__ inline void tree_up(Map<NB>& mp, int leaf, int g, double* s_node,
     const int stride = 1 << lvl, half = stride >> 1;
     const int k = leaf >> lvl;
     double* slot = s_node + ((node_off + k) * G + g) * RS;
-    if (active && (leaf & (stride - 1)) == half) store_rec(mp, slot);
-    __syncthreads();
+    Map<NB> rb;
+    if (LANES && in_wave<G>(half)) {  // uniform: every lane takes part in the moves
+      rb = shfl_down_rec(mp, half * G);
+    } else {
+      if (active && (leaf & (stride - 1)) == half) store_rec(mp, slot);
+      __syncthreads();
+      if (active && (leaf & (stride - 1)) == 0) load_rec(rb, slot);
+    }
     if (active && (leaf & (stride - 1)) == 0) {
-      Map<NB> rb;
-      load_rec(rb, slot);
       Node<NB> nd;
       if (!merge<NB>(mp, rb, mp, nd)) {
         const int64_t row = row0 + (int64_t)(leaf + half) * leaf_rows - NB;
         if (row < n) atomicMin(&s_bad[g], (int)(row + 1));
       }
-      store_rec(nd, slot);
+      store_rec(nd, slot);  // read back by this lane on the way down
     }
     node_off += NL >> lvl;
   }
@@ -316,7 +341,7 @@ __device__ inline void tree_up(Map<NB>& mp, int leaf, int g, double* s_node,
 // Walk back down: on entry the lanes with leaf == 0 hold the outer pairs of
 // the whole range; on exit every lane with leaf < NL holds its leaf's pairs.
 // The caller puts a barrier between tree_up and tree_down.
-template <int NB, int NL, int G>
+template <int NB, int NL, int G, bool LANES = (NB == 1 || G == 1)>
 __device__ inline void tree_down(double (&xl)[NB], double (&xr)[NB], int leaf, int g,
                                  double* s_node) {
   constexpr int RS = kRecSz<NB>;
@@ -329,10 +354,13 @@ __device__ inline void tree_down(double (&xl)[NB], double (&xr)[NB], int leaf, i
     const int k = leaf >> lvl;
     node_off -= NL >> lvl;
     double* slot = s_node + ((node_off + k) * G + g) * RS;
+    double ba[NB], xr0[NB];  // the right part's pairs: x_L = B_A, x_R unchanged
+#pragma unroll
+    for (int q = 0; q < NB; ++q) ba[q] = xr0[q] = 0.0;
     if (active && (leaf & (stride - 1)) == 0) {
       Node<NB> nd;
       load_rec(nd, slot);
-      double ba[NB], tb[NB], t1[NB], t2[NB];
+      double tb[NB], t1[NB], t2[NB];
       mv<NB>(nd.G1, xl, t1);
       mv<NB>(nd.G2, xr, t2);
 #pragma unroll
@@ -343,17 +371,35 @@ __device__ inline void tree_down(double (&xl)[NB], double (&xr)[NB], int leaf, i
       for (int q = 0; q < NB; ++q) tb[q] = nd.h0[q] + t1[q] + t2[q];
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        slot[q] = ba[q];        // right part: x_L = B_A, x_R unchanged
-        slot[NB + q] = xr[q];
-        xr[q] = tb[q];          // left part: x_R = T_B
+        xr0[q] = xr[q];
+        xr[q] = tb[q];  // left part: x_R = T_B
       }
     }
-    __syncthreads();
-    if (active && (leaf & (stride - 1)) == half) {
+    if (LANES && in_wave<G>(half)) {  // uniform: every lane takes part in the moves
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        xl[q] = slot[q];
-        xr[q] = slot[NB + q];
+        const double bl = __shfl_up(ba[q], half * G, 64);
+        const double br = __shfl_up(xr0[q], half * G, 64);
+        if (active && (leaf & (stride - 1)) == half) {
+          xl[q] = bl;
+          xr[q] = br;
+        }
+      }
+    } else {
+      if (active && (leaf & (stride - 1)) == 0) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          slot[q] = ba[q];
+          slot[NB + q] = xr0[q];
+        }
+      }
+      __syncthreads();
+      if (active && (leaf & (stride - 1)) == half) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          xl[q] = slot[q];
+          xr[q] = slot[NB + q];
+        }
       }
     }
   }

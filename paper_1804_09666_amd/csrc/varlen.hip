@@ -100,7 +100,7 @@ __global__ __launch_bounds__(kVG * PW) void varlen_tile_kernel(
   __syncthreads();
   if (!FINISH && bad < M && row_base + r0 + bad < ns)
     atomicMin(&s_bad[g], (int)(row_base + r0 + bad + 1));
-  tree_up<NB, PW, G>(mp, j, g, s_node, s_bad, M, row_base, ng);
+  tree_up<NB, PW, G, true>(mp, j, g, s_node, s_bad, M, row_base, ng);
   const int64_t rec = (tab.tpre[grp] + tile) * G + g;
   if constexpr (!FINISH) {
     if (j == 0) {
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kVG * PW) void varlen_tile_kernel(
       }
     }
     __syncthreads();
-    tree_down<NB, PW, G>(xl, xr, j, g, s_node);
+    tree_down<NB, PW, G, true>(xl, xr, j, g, s_node);
     write_chunk<NB, M>(ns, G, g, live, r0, row_base, p, v, w, xl, xr, X + shift);
   }
 }
