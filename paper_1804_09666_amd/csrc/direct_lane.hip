@@ -568,7 +568,7 @@ __global__ __launch_bounds__(kLaneBlock) void subst_lane_kernel(
 // backward warm-up never reads a row another lane has already overwritten
 // with x.
 // at r = 4 the sweeps need 113..128 rows (|l1| and |u1/u0| reach ~0.7)
-constexpr int64_t kSubstWarm = 160;
+constexpr int64_t kSubstWarm = 128;
 constexpr int64_t kSubstLanes = 32768;
 
 // flags[s] (int32, workspace) marks a system whose proof failed; the forward
