@@ -228,6 +228,32 @@ def test_mnpdm_matches_npdm_and_oracle(path):
     assert i2[5] == -3 and (np.delete(i2, 5) == 0).all()
 
 
+def test_mnpdm_full_sweep_batch():
+    """MNPDM on the 2048 x 2048 sweep batch as the benchmark runs it (c, d, a
+    and the two outer entries of every system, K = 2): bitwise the split NPDM
+    on every system, and the oracle's MNPDM on a sample."""
+    pd, _, _ = wl.config1()
+    batch, n = 2048, 2048
+    t = to_device(pd, batch)
+    rows = np.full((2, batch), -1, dtype=np.int32)
+    oe, ob = np.zeros((2, batch)), np.zeros((2, batch))
+    rows[0], ob[0] = 0, pd["b"][:, 0]
+    rows[1], oe[1] = n - 1, pd["e"][:, n - 1]
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    say("MNPDM n=2048 batch=2048 K=2")
+    x, info = bs.solve_mnpdm([t["c"], t["d"], t["a"]], dev(rows), dev(oe), dev(ob), t["y"],
+                             batch=batch)
+    xn, infon = bs.solve(diags_of(t), t["y"], batch=batch)
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all() and (infon.cpu().numpy() == 0).all()
+    assert torch.equal(x.view(torch.int64), xn.view(torch.int64))
+    xh = host(x, batch)
+    for s in (0, 1, 1023, 2046, 2047):
+        xo, io = oracle.mnpdm(pd["c"][s], pd["d"][s], pd["a"][s], [0, n - 1],
+                              [0.0, pd["e"][s][n - 1]], [pd["b"][s][0], 0.0], pd["y"][s])
+        assert io == 0 and rel_err(xh[s:s + 1], xo[None]).max() <= TOL
+
+
 @pytest.mark.parametrize("n,batch,ld,kmax", [(2048, 100, 128, 5), (3001, 33, 40, 9),
                                              (5000, 7, 8, 4), (300, 64, 64, 0)])
 def test_mnpdm_random_lists(n, batch, ld, kmax, path):
