@@ -61,18 +61,21 @@ def test_fp32_storage_parity(kind, n, batch, ld):
 
 
 def test_fp32_pde_lines_and_in_place():
-    """Second-order (non-dominant boundary) PDE rows in FP32 storage; x may
-    alias rhs."""
-    pd, td, _ = wl.config1(N=1024, seed=41)
+    """Second-order (non-dominant boundary) PDE rows in FP32 storage on the
+    full 2048 x 2048 sweep batch the benchmark times, every element of every
+    system; x may alias rhs."""
+    pd, td, _ = wl.config1()
     for kind, ws in ((5, fp32_rounded(pd)), (3, fp32_rounded(td))):
-        t = to_device(ws, 1024, dtype=torch.float32)
+        t = to_device(ws, 2048, dtype=torch.float32)
         y = t["y"].clone()
-        x, info = bs.solve(diags_of(t, kind), y, y, kind=kind, batch=1024)
+        x, info = bs.solve(diags_of(t, kind), y, y, kind=kind, batch=2048)
         torch.cuda.synchronize()
         xr, _ = oracle_direct(ws, kind)
         assert (info.cpu().numpy() == 0).all()
         bar = U32 * np.abs(xr) + 2 * TOL * np.abs(xr).max(axis=1, keepdims=True)
-        assert (np.abs(host(x, 1024) - xr) <= bar).all()
+        worst = (np.abs(host(x, 2048) - xr) / bar).max()
+        say(f"fp32 sweep batch kind={kind}: max |x - x_orc| / bar = {worst:.3f}")
+        assert worst <= 1.0
 
 
 # ---------------------------------------------------- long systems, FP64 ---
