@@ -203,3 +203,32 @@ def test_substitution_split_bitwise(kind, case, n, batch):
         xo, _ = oracle.band_lu_solve(l2[s], l1[s], u0[s], u1[s] if kind == 5 else ws["a"][s],
                                      b, ws["y"][s])
         assert np.abs(xh[s] - xo).max() <= 1e-12 * np.abs(xo).max()
+
+
+def test_factor_and_substitution_full_sweep_batch():
+    """ILU(0) and the substitution split over lanes on the 2048 x 2048 sweep
+    batch the benchmark times: factors, info and x bitwise the one-lane
+    kernels on every system, and the oracle's factors (bitwise) and LU solve
+    on a sample."""
+    pd, _, _ = wl.config1()
+    n, batch = 2048, 2048
+    say(f"full sweep batch factor + substitution chunk={chunk_rows(n, batch)}")
+    t = to_device(pd, batch)
+    f, info = bs.factor(diags_of(t), batch=batch)
+    x, xinfo = bs.solve(diags_of(t), t["y"], batch=batch, factors=f)
+    bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_LANE)
+    try:
+        fl, infol = bs.factor(diags_of(t), batch=batch)
+        xl, _ = bs.solve(diags_of(t), t["y"], batch=batch, factors=fl)
+    finally:
+        bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_AUTO)
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy() == 0).all() and (xinfo.cpu().numpy() == 0).all()
+    assert np.array_equal(bits(f, batch), bits(fl, batch)) and torch.equal(info, infol)
+    assert np.array_equal(bits(x, batch), bits(xl, batch))
+    check_against_oracle(pd, 5, f, info.cpu().numpy(), (0, 777, 2047))
+    fh = [host(f[k], batch) for k in range(4)]
+    xh = host(x, batch)
+    for s in (0, 777, 2047):
+        xo, _ = oracle.band_lu_solve(fh[0][s], fh[1][s], fh[2][s], fh[3][s], pd["b"][s], pd["y"][s])
+        assert np.abs(xh[s] - xo).max() <= 1e-12 * np.abs(xo).max()
