@@ -221,6 +221,26 @@ def test_split_rows_graph_replay(sL, sU):
         torch.cuda.synchronize()
 
 
+def test_exact_substitution_full_sweep_batch():
+    """Algorithm 1 as printed (exact triangular solves, one lane per system)
+    on the 2048 x 2048 sweep batch: with the band's exact ILU(0) it stops
+    after one step; iterations, status and x of a sample against the
+    oracle's run of the same algorithm."""
+    pd, _, _ = wl.config1()
+    t = to_device(pd, 2048)
+    say("exact SIP n=2048 batch=2048")
+    x, it, rr, info = bs.sip(diags_of(t), t["y"], tol=1e-12, max_iter=5, batch=2048)
+    torch.cuda.synchronize()
+    it, rr, info = it.cpu().numpy(), rr.cpu().numpy(), info.cpu().numpy()
+    assert (info == 0).all() and (it == 1).all() and (rr < 1e-12).all()
+    pick = [0, 1, 1000, 2047]
+    sub = {k: v[pick] for k, v in pd.items()}
+    xo, ito, rro, sto = oracle.sip_batch(sub["e"], sub["c"], sub["d"], sub["a"], sub["b"],
+                                         sub["y"], tol=1e-12, max_iter=5)
+    assert (sto == 0).all() and (ito == it[pick]).all()
+    assert rel_err(x[:, pick].cpu().numpy().T, xo).max() <= 1e-12
+
+
 def test_split_rows_bad_pivot_and_max_iter_zero():
     ws = wl.dominant_batch(4, 600, seed=13)
     ws["d"][2, 0] = 0.0     # ILU(0) pivot u0_0 = 0: no step, x untouched
