@@ -53,9 +53,10 @@
  *            1e3 * max(1, relative residual of x0))
  *    -3      MNPDM: the outer-entry list of the system is not strictly
  *            ascending or names a row outside 0..n-1
- *    -4      split-row band_solve: the blocks that share the system did not
- *            all arrive within BS_OPT_EXCHANGE_WAIT_US (default one second;
- *            x unspecified)
+ *    -4      split-row band_solve with x aliasing rhs: the blocks that share
+ *            the system did not all arrive within BS_OPT_EXCHANGE_WAIT_US
+ *            (default one second; x unspecified; without aliasing the rows
+ *            of the blocks that gave up are solved sequentially instead)
  *    -1, -2  band_solve_refine: not converged within max_steps / residual not
  *            finite (as for SIP)
  */
@@ -109,8 +110,9 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
  *   BS_OPT_PART_PD_VARIANT index of the split-row PD kernel variant
  *   BS_OPT_PART_TD_VARIANT index of the split-row TD kernel variant
  *   BS_OPT_SIP_PATH        sip_solve kernel: 0 and 2 rows of a system split
- *                          over lanes where the HB steps allow it, up to three
- *                          steps per launch where their halos fit (default),
+ *                          over lanes where the HB steps allow it (up to three
+ *                          steps per launch where their halos fit) or both
+ *                          solves are exact (default),
  *                          1 one lane per system, 3 (4) rows split over lanes
  *                          with one step (at most two steps) per launch (same
  *                          iterates as 0)
@@ -167,12 +169,26 @@ int32_t band_factor(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
  *   (alpha, beta); info[s] reports the first bad pivot.  With one lane per
  *   system (option BS_OPT_DIRECT_PATH = 1) the arithmetic is that of the
  *   sequential recurrence.  By default the rows of a system are split over
- *   many lanes (partitioned elimination with a reduced interface system),
- *   which changes the rounding but not the result beyond it (info then
- *   reports the first bad pivot of the elimination performed): one launch for
- *   n up to M*PW*TMAX of the configured variant, three launches (tile maps,
- *   per-system reduction, finish) for longer systems.  dtype BS_F32 needs
- *   this split path (n >= 8).
+ *   many lanes (a partitioned elimination: chunks of rows eliminated on
+ *   their own, then a reduced system on the chunk interfaces), which
+ *   changes the rounding only: one launch for n up to M*PW*TMAX of the
+ *   configured variant, three launches (tile maps, per-system reduction,
+ *   finish) and a redo launch for longer systems.  dtype BS_F32 needs this
+ *   split path (n >= 8).
+ *   Breakdown on the split path: a system whose partitioned elimination
+ *   meets a pivot or a 2x2 interface block that is not finite or not larger
+ *   than 2^-12 times the magnitude of the terms it is formed from (a local
+ *   pivot: the sum |e|+|c|+|d|+|a|+|b| of its row) is solved again by the
+ *   sequential recurrence, in the same call; its x and info are then the
+ *   sequential method's to the last bit (for BS_F32 storage: in FP64 on the
+ *   stored values, x rounded once).  So a zero or tiny diagonal at the start
+ *   of a chunk, where the sequential pivot is regular, gives info = 0, and a
+ *   sequential pivot that cancels inside a chunk (where the chunk's own
+ *   recurrence has forgotten its start and meets it too) gives the
+ *   sequential info.  A sequential pivot that vanishes in one of the first
+ *   rows of a chunk other than the first is not met by the partitioned
+ *   elimination, which solves the system (regular there) and reports 0;
+ *   BS_OPT_DIRECT_PATH = 1 reports such breakdowns as NPDM does.
  * factors != NULL: substitution with the factors of band_factor (same kind
  *   and layout): L z = rhs, U x = z.  info[s] is set to 0.  Where the batch
  *   is small the rows of each sweep are split over lanes as in band_factor
@@ -184,10 +200,16 @@ int32_t band_factor(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
  *   BS_OP_SOLVE_FACTORED, ...); may be NULL / 0 when that is 0.  When the
  *   rows of a system span several blocks, the blocks meet at counters in the
  *   workspace: its contents must be zero before its first use with
- *   band_solve, and every completed call leaves them zero again, also after
- *   an info of -4 (blocks that gave up waiting still leave, and the last one
- *   resets the counters; zero the workspace again only if a call was
- *   interrupted).  Calls that share one workspace must not run concurrently.
+ *   band_solve, and every completed call leaves them zero again (blocks
+ *   that gave up waiting still leave, and the last one resets the counters;
+ *   zero the workspace again only if a call was interrupted).  A block that
+ *   gives up writes no x; the last block of its system then solves that
+ *   block's rows with the sequential recurrence, unless x aliases rhs (the
+ *   other blocks have overwritten rhs rows): info -4, x unspecified.  The
+ *   workspace also holds the planes of the sequential redo (3 for kind 5, 2
+ *   for kind 3, n * ceil(batch/64)*64 doubles each), touched only by systems
+ *   that are redone.  Calls that share one workspace must not run
+ *   concurrently.
  *   The factored substitution uses its workspace for z and needs no zeroing. */
 int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
                    int64_t ld, const void* const diags[5], const void* factors,
@@ -285,10 +307,16 @@ int32_t band_solve_mnpdm(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
  *   stopping test at each step count in turn: about (max_iter + 1) / 3 (or
  *   / 2, / 1) launches are enqueued, and those after the last system has
  *   stopped return at once.  The iterates do not depend on the steps per
- *   launch.  Otherwise (exact substitution, Algorithm 1
- *   as written) one lane walks each system in one persistent launch.
+ *   launch.  With exact solves for both factors (Algorithm 1 as printed)
+ *   and a batch too small to fill the GPU with one lane per system, each
+ *   step is a row-parallel pass (residual, its norm, K x + b; the last block
+ *   applies the test) and the split substitution of band_solve with
+ *   factors: max_iter steps are enqueued, those after the last system has
+ *   stopped return at once, and iterates, counts, residuals and statuses
+ *   are bitwise those of one lane per system.  Otherwise one lane walks each
+ *   system in one persistent launch.
  * workspace: bs_workspace_bytes(BS_OP_SIP, ...) bytes, 256-byte aligned; its
- *   contents need no initialisation.  x and rhs must not alias. */
+ *   contents need no initialisation.  x and rhs must not alias (BS_EINVAL). */
 int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
                   const void* const diags[5], const void* factors,
                   const void* rhs, void* x, double tol, int32_t max_iter,
@@ -313,6 +341,7 @@ typedef struct {
   int64_t elems;       /* elements every per-row array must hold               */
   int64_t tiles[4];    /* tiles of the whole batch for each variant (unused 0) */
   size_t table_bytes;  /* bytes of the device table                            */
+  int64_t nmax;        /* longest system                                       */
 } bs_varlen_info;
 
 int32_t bs_varlen_variants(void);

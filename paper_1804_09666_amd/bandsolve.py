@@ -39,7 +39,8 @@ PATH_AUTO, PATH_LANE, PATH_PART = range(3)
 class VarlenInfo(ctypes.Structure):
     """bs_varlen_info of include/bandsolve.h."""
     _fields_ = [("count", ctypes.c_int64), ("groups", ctypes.c_int64), ("elems", ctypes.c_int64),
-                ("tiles", ctypes.c_int64 * 4), ("table_bytes", ctypes.c_size_t)]
+                ("tiles", ctypes.c_int64 * 4), ("table_bytes", ctypes.c_size_t),
+                ("nmax", ctypes.c_int64)]
 
 
 class BandSolveError(RuntimeError):

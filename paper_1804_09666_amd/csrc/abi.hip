@@ -225,11 +225,16 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
     }
     case BS_OP_SIP: {
       // ILU(0) factors (4 planes, batch-interleaved with pitch ws_ld), then
-      // either one plane for the forward pass (one lane per system) or the
-      // two more x buffers and per-system state (rows split over lanes)
-      const size_t lane = (size_t)plane * 8;
+      // one plane for the forward pass (one lane per system), the x buffers
+      // and per-system state of the HB tile path, or the K x + b plane, the
+      // substitution's z plane and per-system state of the exact path,
+      // whichever is largest
+      size_t rest = (size_t)plane * 8;
       const size_t tile = bs::sip_tile_workspace_bytes(n, batch, ld);
-      return (size_t)(4 * plane) * 8 + (lane > tile ? lane : tile);
+      const size_t exact = bs::sip_exact_supported(n, batch) ? bs::sip_exact_workspace_bytes(n, batch) : 0;
+      rest = rest > tile ? rest : tile;
+      rest = rest > exact ? rest : exact;
+      return (size_t)(4 * plane) * 8 + rest;
     }
     case BS_OP_ADI: {
       if (!kind_ok(kind) || dtype != BS_F64) return bad;
@@ -390,6 +395,7 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
       info == nullptr || !aligned(info, 4))
     return BS_EINVAL;
   if (!(tol > 0.0) || max_iter < 0) return BS_EINVAL;
+  if (x == rhs) return BS_EINVAL;  // rhs is read at every step
   auto s_ok = [n](int32_t s) {
     if (s < 0 || s <= 6) return true;
     return s < 62 && (int64_t(1) << s) >= n;
@@ -419,6 +425,14 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
   }
   double* rest = ws + 4 * n * lw;  // 256-byte aligned: lw is a multiple of 64
   const int64_t path = g_sip_path.load();
+  // HB with 2^s >= n is the exact inverse: both factors exact is Algorithm 1
+  // as printed
+  auto exact = [n](int32_t s) { return s < 0 || (s < 62 && (int64_t(1) << s) >= n); };
+  if (path != 1 && exact(hb_s_L) && exact(hb_s_U) && bs::sip_exact_supported(n, batch))
+    return launched(bs::launch_sip_exact(n, batch, ld, A, F, fld,
+                                         static_cast<const double*>(rhs),
+                                         static_cast<double*>(x), tol, max_iter, iters, relres,
+                                         info, rest, st));
   if (path != 1 && bs::sip_tile_supported(n, hb_s_L, hb_s_U))
     return launched(bs::launch_sip_tile(n, batch, ld, A, F, fld, own,
                                         static_cast<const double*>(rhs),

@@ -47,6 +47,16 @@ hipError_t launch_subst_lane(int kind, int64_t n, int64_t batch, int64_t ld,
 // (bitwise the one-lane result); z goes through ws, subst_workspace_bytes
 // long (0: one lane per system, ws unused).
 size_t subst_workspace_bytes(int64_t n, int64_t batch);
+// Chunks per system of the split substitution (1: one lane per system).
+int64_t subst_chunks(int64_t n, int64_t batch);
+// The split substitution (subst_chunks > 1) of the systems with active[s] != 0
+// (all when NULL): rhs y with pitch yl, factors with pitch fld, x with pitch
+// ld; z and the proof flags in ws (subst_workspace_bytes); every launch
+// returns at once when done != NULL and *done != 0; info (nullable) = 0.
+hipError_t launch_subst_masked(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
+                               const double* factors, int64_t fld, const double* y, int64_t yl,
+                               double* x, int32_t* info, double* ws, const int32_t* active,
+                               const int32_t* done, hipStream_t st);
 hipError_t launch_subst(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
                         const double* factors, const double* y, double* x, int32_t* info,
                         double* ws, hipStream_t st);
@@ -115,6 +125,17 @@ hipError_t launch_sip_lane(int64_t n, int64_t batch, int64_t ld, Diags A,
                            double tol, int32_t max_iter, int32_t sL,
                            int32_t sU, int32_t* iters, double* relres,
                            int32_t* info, double* v_ws, hipStream_t st);
+
+// ---- SIP as Algorithm 1 (exact substitutions), rows split (sip_exact.hip) --
+// Row-parallel residual and K x + b, the stopping test in the last block,
+// the split substitution; bitwise the one-lane kernel.  Needs
+// subst_chunks(n, batch) > 1.
+bool sip_exact_supported(int64_t n, int64_t batch);
+size_t sip_exact_workspace_bytes(int64_t n, int64_t batch);
+hipError_t launch_sip_exact(int64_t n, int64_t batch, int64_t ld, Diags A, const double* factors,
+                            int64_t fld, const double* y, double* x, double tol,
+                            int32_t max_iter, int32_t* iters, double* relres, int32_t* info,
+                            void* ws, hipStream_t st);
 
 // ---- SIP with HB steps, rows split over lanes (sip_tile.hip) -------------
 // Both s_L, s_U >= 0, HB not exact (2^s <= n) and halos that leave a tile

@@ -12,6 +12,7 @@
 // FMAs, so their results are the sequential recurrence's to the last bit.
 #include "bs_internal.h"
 #include "lane_stream.h"
+#include "seq_core.h"
 
 #pragma clang fp contract(off)
 
@@ -24,143 +25,31 @@ __device__ inline bool bad_pivot(double m) { return !(m != 0.0) || !isfinite(m);
 
 constexpr int kPF = 8;  // rows in flight per lane (x <= 8 memory operations < 64)
 
-// NPDM: gamma_i = c_i - alpha_{i-2} e_i;  mu_i = (d_i - beta_{i-2} e_i) -
-// alpha_{i-1} gamma_i;  alpha_i = (a_i - beta_{i-1} gamma_i) / mu_i;
-// beta_i = b_i / mu_i;  z_i = ((y_i - z_{i-2} e_i) - z_{i-1} gamma_i) / mu_i;
-// x_i = (z_i - alpha_i x_{i+1}) - beta_i x_{i+2}.
-template <typename T>
-__global__ __launch_bounds__(kLaneBlock) void npdm_lane_kernel(
-    int64_t n, int64_t batch, int64_t ld, const T* __restrict__ E,
-    const T* __restrict__ C, const T* __restrict__ D, const T* __restrict__ A,
-    const T* __restrict__ B, const T* __restrict__ Y, T* __restrict__ X,
-    int32_t* __restrict__ info, T* __restrict__ ws, int64_t lw) {
+// NPDM and NTDM (Thomas): the sequential sweeps of seq_core.h, one lane per
+// system.  alpha (and beta) go through the workspace planes, z through x.
+template <int KIND>
+__global__ __launch_bounds__(kLaneBlock) void direct_lane_kernel(
+    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
+    const double* __restrict__ C, const double* __restrict__ D, const double* __restrict__ A,
+    const double* __restrict__ B, const double* __restrict__ Y, double* __restrict__ X,
+    int32_t* __restrict__ info, double* __restrict__ ws, int64_t lw) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
   if (s >= batch) return;
-  T* al = ws;
-  T* be = ws + n * lw;
-  T am1 = 0, am2 = 0, bm1 = 0, bm2 = 0, zm1 = 0, zm2 = 0;
-  int64_t bad = -1;  // first bad pivot (the sweeps run on; x is then unspecified)
-  {
-    T re[kPF], rc[kPF], rd[kPF], ra[kPF], rb[kPF], ry[kPF];
-    auto fetch = [&](int q, int64_t i) {
-      const int64_t o = i * ld + s;
-      re[q] = E[o];
-      rc[q] = C[o];
-      rd[q] = D[o];
-      ra[q] = A[o];
-      rb[q] = B[o];
-      ry[q] = Y[o];
-    };
-    auto use = [&](int q, int64_t i) {
-      const int64_t o = i * ld + s;
-      T gamma = 0, mu;
-      if (i == 0) {
-        mu = rd[q];
-      } else if (i == 1) {
-        gamma = rc[q];
-        mu = rd[q] - am1 * gamma;
-      } else {
-        gamma = rc[q] - am2 * re[q];
-        mu = (rd[q] - bm2 * re[q]) - am1 * gamma;
-      }
-      if (bad < 0 && bad_pivot(mu)) bad = i;
-      T ali = 0, bei = 0, zi;
-      if (i <= n - 2) ali = (i == 0) ? ra[q] / mu : (ra[q] - bm1 * gamma) / mu;
-      if (i <= n - 3) bei = rb[q] / mu;
-      if (i == 0)
-        zi = ry[q] / mu;
-      else if (i == 1)
-        zi = (ry[q] - zm1 * gamma) / mu;
-      else
-        zi = ((ry[q] - zm2 * re[q]) - zm1 * gamma) / mu;
-      al[i * lw + s] = ali;
-      be[i * lw + s] = bei;
-      X[o] = zi;
-      am2 = am1; am1 = ali;
-      bm2 = bm1; bm1 = bei;
-      zm2 = zm1; zm1 = zi;
-    };
-    stream_rows<kPF, false>(n, fetch, use);
-  }
-  {
-    T rz[kPF], ral[kPF], rbe[kPF];
-    T xp1 = 0, xp2 = 0;  // x_{i+1}, x_{i+2}
-    auto fetch = [&](int q, int64_t i) {
-      rz[q] = X[i * ld + s];
-      ral[q] = al[i * lw + s];
-      rbe[q] = be[i * lw + s];
-    };
-    auto use = [&](int q, int64_t i) {
-      T xi;
-      if (i == n - 1)
-        xi = rz[q];
-      else if (i == n - 2)
-        xi = rz[q] - ral[q] * xp1;
-      else
-        xi = (rz[q] - ral[q] * xp1) - rbe[q] * xp2;
-      X[i * ld + s] = xi;
-      xp2 = xp1;
-      xp1 = xi;
-    };
-    stream_rows<kPF, true>(n, fetch, use);
-  }
-  info[s] = bad < 0 ? 0 : (int32_t)(bad + 1);
-}
-
-// NTDM (Thomas): mu_i = d_i - alpha_{i-1} c_i;  alpha_i = a_i / mu_i;
-// z_i = (y_i - z_{i-1} c_i) / mu_i;  x_i = z_i - alpha_i x_{i+1}.
-template <typename T>
-__global__ __launch_bounds__(kLaneBlock) void ntdm_lane_kernel(
-    int64_t n, int64_t batch, int64_t ld, const T* __restrict__ C,
-    const T* __restrict__ D, const T* __restrict__ A, const T* __restrict__ Y,
-    T* __restrict__ X, int32_t* __restrict__ info, T* __restrict__ ws,
-    int64_t lw) {
-  const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
-  if (s >= batch) return;
-  T am1 = 0, zm1 = 0;
-  int64_t bad = -1;
-  {
-    T rc[kPF], rd[kPF], ra[kPF], ry[kPF];
-    auto fetch = [&](int q, int64_t i) {
-      const int64_t o = i * ld + s;
-      rc[q] = C[o];
-      rd[q] = D[o];
-      ra[q] = A[o];
-      ry[q] = Y[o];
-    };
-    auto use = [&](int q, int64_t i) {
-      T mu, ci = 0;
-      if (i == 0) {
-        mu = rd[q];
-      } else {
-        ci = rc[q];
-        mu = rd[q] - am1 * ci;
-      }
-      if (bad < 0 && bad_pivot(mu)) bad = i;
-      T ali = 0;
-      if (i <= n - 2) ali = ra[q] / mu;
-      const T zi = (i == 0) ? ry[q] / mu : (ry[q] - zm1 * ci) / mu;
-      ws[i * lw + s] = ali;
-      X[i * ld + s] = zi;
-      am1 = ali;
-      zm1 = zi;
-    };
-    stream_rows<kPF, false>(n, fetch, use);
-  }
-  {
-    T rz[kPF], ral[kPF];
-    T xp1 = 0;
-    auto fetch = [&](int q, int64_t i) {
-      rz[q] = X[i * ld + s];
-      ral[q] = ws[i * lw + s];
-    };
-    auto use = [&](int q, int64_t i) {
-      const T xi = (i == n - 1) ? rz[q] : rz[q] - ral[q] * xp1;
-      X[i * ld + s] = xi;
-      xp1 = xi;
-    };
-    stream_rows<kPF, true>(n, fetch, use);
-  }
+  auto fetch = [&](int64_t i) {
+    const int64_t o = i * ld + s;
+    seq::Row w;
+    w.e = (KIND == 5) ? E[o] : 0.0;
+    w.c = C[o];
+    w.d = D[o];
+    w.a = A[o];
+    w.b = (KIND == 5) ? B[o] : 0.0;
+    w.y = Y[o];
+    return w;
+  };
+  const seq::Planes P{ws, ws + n * lw, lw, X, ld, s};
+  const int64_t bad = seq::solve<KIND>(
+      n, fetch, P, [&](int64_t i, double v) { X[i * ld + s] = v; },
+      [](int64_t) { return true; });
   info[s] = bad < 0 ? 0 : (int32_t)(bad + 1);
 }
 
@@ -473,41 +362,60 @@ __global__ __launch_bounds__(kLaneBlock) void factor_finish_kernel(
 
 // Substitution with the band factors: z_i = (y_i - l1_i z_{i-1}) - l2_i z_{i-2},
 // then x_i = ((z_i - u1_i x_{i+1}) - u2_i x_{i+2}) / u0_i.
+// Row i of the factor planes sits at i * fld, of A's arrays at i * ald.
 struct SubstPlanes {
   const double* l2;  // KIND 5 only
   const double* l1;
   const double* u0;
-  const double* u1;  // KIND 5: the u1 array; KIND 3: a
-  const double* u2;  // KIND 5: b
+  const double* u1;  // KIND 5: the u1 plane (pitch fld); KIND 3: a (pitch ald)
+  const double* u2;  // KIND 5: b (pitch ald)
+  int64_t fld, ald;
 };
 
 template <int KIND>
-__device__ inline SubstPlanes subst_planes(const double* F, const double* Aa, const double* B,
-                                           int64_t n, int64_t ld) {
-  const int64_t plane = n * ld;
-  if (KIND == 5) return {F, F + plane, F + 2 * plane, F + 3 * plane, B};
-  return {nullptr, F, F + plane, Aa, nullptr};
+__host__ __device__ inline SubstPlanes subst_planes(const double* F, int64_t fld, const double* Aa,
+                                           const double* B, int64_t n, int64_t ald) {
+  const int64_t plane = n * fld;
+  if (KIND == 5) return {F, F + plane, F + 2 * plane, F + 3 * plane, B, fld, ald};
+  return {nullptr, F, F + plane, Aa, nullptr, fld, ald};
+}
+
+// Vectors of one substitution: rhs y (pitch yl), z (pitch zl), x (pitch xl);
+// `active` (nullable): systems with active[s] == 0 are left alone; `done`
+// (nullable): the whole launch returns at once when *done != 0.
+struct SubstIO {
+  const double* y;
+  int64_t yl;
+  double* z;
+  int64_t zl;
+  double* x;
+  int64_t xl;
+  const int32_t* active;
+  const int32_t* done;
+};
+
+__device__ inline bool subst_idle(const SubstIO& io, int64_t s) {
+  return (io.done != nullptr && *io.done) || (io.active != nullptr && io.active[s] == 0);
 }
 
 // Forward rows [lo, hi) of system s with z_{lo-1}, z_{lo-2} taken as absent;
-// z written to Z (pitch zl) for rows >= w0.
+// z written for rows >= w0.
 template <int KIND>
-__device__ inline void subst_fwd_rows(int64_t ld, int64_t s, int64_t lo, int64_t w0, int64_t hi,
-                                      SubstPlanes P, const double* __restrict__ Y,
-                                      double* __restrict__ Z, int64_t zl) {
+__device__ inline void subst_fwd_rows(int64_t s, int64_t lo, int64_t w0, int64_t hi,
+                                      SubstPlanes P, const SubstIO& io) {
   double ry[kPF], rl1[kPF], rl2[kPF];
   double zm1 = 0, zm2 = 0;
   auto fetch = [&](int q, int64_t k) {
-    const int64_t o = (lo + k) * ld + s;
-    ry[q] = Y[o];
-    rl1[q] = P.l1[o];
-    if (KIND == 5) rl2[q] = P.l2[o];
+    const int64_t i = lo + k, fo = i * P.fld + s;
+    ry[q] = io.y[i * io.yl + s];
+    rl1[q] = P.l1[fo];
+    if (KIND == 5) rl2[q] = P.l2[fo];
   };
   auto use = [&](int q, int64_t k) {
     double t = ry[q];
     if (k >= 1) t = t - rl1[q] * zm1;
     if (KIND == 5 && k >= 2) t = t - rl2[q] * zm2;
-    if (lo + k >= w0) Z[(lo + k) * zl + s] = t;
+    if (lo + k >= w0) io.z[(lo + k) * io.zl + s] = t;
     zm2 = zm1;
     zm1 = t;
   };
@@ -517,17 +425,17 @@ __device__ inline void subst_fwd_rows(int64_t ld, int64_t s, int64_t lo, int64_t
 // Backward rows top-1 down to w0 of system s with x_top, x_{top+1} taken as
 // absent (top = n: the recurrence itself); x written for rows < w1.
 template <int KIND>
-__device__ inline void subst_bwd_rows(int64_t ld, int64_t s, int64_t w0, int64_t w1, int64_t top,
-                                      SubstPlanes P, const double* __restrict__ Z, int64_t zl,
-                                      double* __restrict__ X) {
+__device__ inline void subst_bwd_rows(int64_t s, int64_t w0, int64_t w1, int64_t top,
+                                      SubstPlanes P, const SubstIO& io) {
   double rz[kPF], ru1[kPF], ru2[kPF], ru0[kPF];
   double xp1 = 0, xp2 = 0;
+  const int64_t u1l = KIND == 5 ? P.fld : P.ald;
   auto fetch = [&](int q, int64_t k) {
-    const int64_t i = w0 + k, o = i * ld + s;
-    rz[q] = Z[i * zl + s];
-    ru1[q] = P.u1[o];
-    if (KIND == 5) ru2[q] = P.u2[o];
-    ru0[q] = P.u0[o];
+    const int64_t i = w0 + k;
+    rz[q] = io.z[i * io.zl + s];
+    ru1[q] = P.u1[i * u1l + s];
+    if (KIND == 5) ru2[q] = P.u2[i * P.ald + s];
+    ru0[q] = P.u0[i * P.fld + s];
   };
   auto use = [&](int q, int64_t k) {
     const int64_t i = w0 + k;
@@ -535,7 +443,7 @@ __device__ inline void subst_bwd_rows(int64_t ld, int64_t s, int64_t w0, int64_t
     if (i + 1 < top) t = t - ru1[q] * xp1;
     if (KIND == 5 && i + 2 < top) t = t - ru2[q] * xp2;
     const double xi = t / ru0[q];
-    if (i < w1) X[i * ld + s] = xi;
+    if (i < w1) io.x[i * io.xl + s] = xi;
     xp2 = xp1;
     xp1 = xi;
   };
@@ -545,14 +453,14 @@ __device__ inline void subst_bwd_rows(int64_t ld, int64_t s, int64_t w0, int64_t
 template <int KIND>
 __global__ __launch_bounds__(kLaneBlock) void subst_lane_kernel(
     int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
-    const double* __restrict__ B, const double* __restrict__ F,
-    const double* __restrict__ Y, double* __restrict__ X,
-    int32_t* __restrict__ info) {
+    const double* __restrict__ B, const double* __restrict__ F, int64_t fld,
+    const double* __restrict__ Y, double* __restrict__ X, int32_t* __restrict__ info) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
   if (s >= batch) return;
-  const SubstPlanes P = subst_planes<KIND>(F, Aa, B, n, ld);
-  subst_fwd_rows<KIND>(ld, s, 0, 0, n, P, Y, X, ld);  // z kept in x
-  subst_bwd_rows<KIND>(ld, s, 0, n, n, P, X, ld, X);
+  const SubstPlanes P = subst_planes<KIND>(F, fld, Aa, B, n, ld);
+  const SubstIO io{Y, ld, X, ld, X, ld, nullptr, nullptr};  // z kept in x
+  subst_fwd_rows<KIND>(s, 0, 0, n, P, io);
+  subst_bwd_rows<KIND>(s, 0, n, n, P, io);
   info[s] = 0;
 }
 
@@ -575,37 +483,32 @@ constexpr int64_t kSubstLanes = 32768;
 // chunk kernel clears it, each fix kernel acts on it and clears it again.
 template <int KIND>
 __global__ __launch_bounds__(kLaneBlock) void subst_fwd_chunk_kernel(
-    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
-    const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Y,
-    double* __restrict__ Z, int64_t zl, int32_t* __restrict__ flags, int64_t M) {
+    int64_t n, int64_t batch, SubstPlanes P, SubstIO io, int32_t* __restrict__ flags, int64_t M) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
-  if (s >= batch) return;
+  if (s >= batch || subst_idle(io, s)) return;
   if (blockIdx.y == 0) flags[s] = 0;
   const int64_t w0 = (int64_t)blockIdx.y * M;
   const int64_t lo = w0 > kSubstWarm ? w0 - kSubstWarm : 0;
   const int64_t hi = w0 + M < n ? w0 + M : n;
-  subst_fwd_rows<KIND>(ld, s, lo, w0, hi, subst_planes<KIND>(F, Aa, B, n, ld), Y, Z, zl);
+  subst_fwd_rows<KIND>(s, lo, w0, hi, P, io);
 }
 
 // One lane per (system, chunk that started early): z of the chunk's first
 // two rows from the stored z of the two rows before it.
 template <int KIND>
 __global__ __launch_bounds__(kLaneBlock) void subst_fwd_proof_kernel(
-    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
-    const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Y,
-    const double* __restrict__ Z, int64_t zl, int32_t* __restrict__ flags, int64_t M) {
+    int64_t n, int64_t batch, SubstPlanes P, SubstIO io, int32_t* __restrict__ flags, int64_t M) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
-  if (s >= batch) return;
-  const SubstPlanes P = subst_planes<KIND>(F, Aa, B, n, ld);
+  if (s >= batch || subst_idle(io, s)) return;
   const int64_t r = (kSubstWarm / M + 1 + blockIdx.y) * M;  // kSubstWarm < r < n
-  double zm2 = Z[(r - 2) * zl + s], zm1 = Z[(r - 1) * zl + s];
+  double zm2 = io.z[(r - 2) * io.zl + s], zm1 = io.z[(r - 1) * io.zl + s];
   bool ok = true;
   for (int64_t i = r; i < r + 2 && i < n; ++i) {
-    const int64_t o = i * ld + s;
-    double t = Y[o];
-    t = t - P.l1[o] * zm1;
-    if (KIND == 5) t = t - P.l2[o] * zm2;
-    ok = ok && same_bits(t, Z[i * zl + s]);
+    const int64_t fo = i * P.fld + s;
+    double t = io.y[i * io.yl + s];
+    t = t - P.l1[fo] * zm1;
+    if (KIND == 5) t = t - P.l2[fo] * zm2;
+    ok = ok && same_bits(t, io.z[i * io.zl + s]);
     zm2 = zm1;
     zm1 = t;
   }
@@ -614,26 +517,22 @@ __global__ __launch_bounds__(kLaneBlock) void subst_fwd_proof_kernel(
 
 template <int KIND>
 __global__ __launch_bounds__(kLaneBlock) void subst_fwd_fix_kernel(
-    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
-    const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Y,
-    double* __restrict__ Z, int64_t zl, int32_t* __restrict__ flags) {
+    int64_t n, int64_t batch, SubstPlanes P, SubstIO io, int32_t* __restrict__ flags) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
-  if (s >= batch || flags[s] == 0) return;
-  subst_fwd_rows<KIND>(ld, s, 0, 0, n, subst_planes<KIND>(F, Aa, B, n, ld), Y, Z, zl);
+  if (s >= batch || subst_idle(io, s) || flags[s] == 0) return;
+  subst_fwd_rows<KIND>(s, 0, 0, n, P, io);
   flags[s] = 0;
 }
 
 template <int KIND>
 __global__ __launch_bounds__(kLaneBlock) void subst_bwd_chunk_kernel(
-    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
-    const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Z,
-    int64_t zl, double* __restrict__ X, int64_t M) {
+    int64_t n, int64_t batch, SubstPlanes P, SubstIO io, int64_t M) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
-  if (s >= batch) return;
+  if (s >= batch || subst_idle(io, s)) return;
   const int64_t w0 = (int64_t)blockIdx.y * M;
   const int64_t w1 = w0 + M < n ? w0 + M : n;
   const int64_t top = n - w1 > kSubstWarm ? w1 + kSubstWarm : n;
-  subst_bwd_rows<KIND>(ld, s, w0, w1, top, subst_planes<KIND>(F, Aa, B, n, ld), Z, zl, X);
+  subst_bwd_rows<KIND>(s, w0, w1, top, P, io);
 }
 
 // One lane per (system, chunk that started late): x of the chunk's last two
@@ -641,22 +540,19 @@ __global__ __launch_bounds__(kLaneBlock) void subst_bwd_chunk_kernel(
 // (k + 1) M; those within kSubstWarm rows of n ran from n.
 template <int KIND>
 __global__ __launch_bounds__(kLaneBlock) void subst_bwd_proof_kernel(
-    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
-    const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Z,
-    int64_t zl, const double* __restrict__ X, int32_t* __restrict__ flags, int64_t M) {
+    int64_t n, int64_t batch, SubstPlanes P, SubstIO io, int32_t* __restrict__ flags, int64_t M) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
-  if (s >= batch) return;
-  const SubstPlanes P = subst_planes<KIND>(F, Aa, B, n, ld);
+  if (s >= batch || subst_idle(io, s)) return;
   const int64_t w1 = ((int64_t)blockIdx.y + 1) * M;  // n - w1 > kSubstWarm
-  double xp1 = X[w1 * ld + s], xp2 = X[(w1 + 1) * ld + s];
+  const int64_t u1l = KIND == 5 ? P.fld : P.ald;
+  double xp1 = io.x[w1 * io.xl + s], xp2 = io.x[(w1 + 1) * io.xl + s];
   bool ok = true;
   for (int64_t i = w1 - 1; i >= w1 - 2; --i) {
-    const int64_t o = i * ld + s;
-    double t = Z[i * zl + s];
-    t = t - P.u1[o] * xp1;
-    if (KIND == 5) t = t - P.u2[o] * xp2;
-    const double xi = t / P.u0[o];
-    ok = ok && same_bits(xi, X[o]);
+    double t = io.z[i * io.zl + s];
+    t = t - P.u1[i * u1l + s] * xp1;
+    if (KIND == 5) t = t - P.u2[i * P.ald + s] * xp2;
+    const double xi = t / P.u0[i * P.fld + s];
+    ok = ok && same_bits(xi, io.x[i * io.xl + s]);
     xp2 = xp1;
     xp1 = xi;
   }
@@ -665,17 +561,15 @@ __global__ __launch_bounds__(kLaneBlock) void subst_bwd_proof_kernel(
 
 template <int KIND>
 __global__ __launch_bounds__(kLaneBlock) void subst_bwd_fix_kernel(
-    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ Aa,
-    const double* __restrict__ B, const double* __restrict__ F, const double* __restrict__ Z,
-    int64_t zl, double* __restrict__ X, int32_t* __restrict__ info,
+    int64_t n, int64_t batch, SubstPlanes P, SubstIO io, int32_t* __restrict__ info,
     int32_t* __restrict__ flags) {
   const int64_t s = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
-  if (s >= batch) return;
+  if (s >= batch || subst_idle(io, s)) return;
   if (flags[s] != 0) {
-    subst_bwd_rows<KIND>(ld, s, 0, n, n, subst_planes<KIND>(F, Aa, B, n, ld), Z, zl, X);
+    subst_bwd_rows<KIND>(s, 0, n, n, P, io);
     flags[s] = 0;
   }
-  info[s] = 0;
+  if (info != nullptr) info[s] = 0;
 }
 
 inline dim3 lane_grid(int64_t batch) {
@@ -687,7 +581,7 @@ inline dim3 lane_grid(int64_t batch) {
 hipError_t launch_npdm_lane(int64_t n, int64_t batch, int64_t ld, Diags A,
                             const double* y, double* x, int32_t* info,
                             double* ws, hipStream_t st) {
-  hipLaunchKernelGGL(npdm_lane_kernel<double>, lane_grid(batch),
+  hipLaunchKernelGGL(direct_lane_kernel<5>, lane_grid(batch),
                      dim3(kLaneBlock), 0, st, n, batch, ld, A.e, A.c, A.d, A.a,
                      A.b, y, x, info, ws, ws_ld(batch));
   return hipGetLastError();
@@ -696,9 +590,9 @@ hipError_t launch_npdm_lane(int64_t n, int64_t batch, int64_t ld, Diags A,
 hipError_t launch_ntdm_lane(int64_t n, int64_t batch, int64_t ld, Diags A,
                             const double* y, double* x, int32_t* info,
                             double* ws, hipStream_t st) {
-  hipLaunchKernelGGL(ntdm_lane_kernel<double>, lane_grid(batch),
-                     dim3(kLaneBlock), 0, st, n, batch, ld, A.c, A.d, A.a, y,
-                     x, info, ws, ws_ld(batch));
+  hipLaunchKernelGGL(direct_lane_kernel<3>, lane_grid(batch),
+                     dim3(kLaneBlock), 0, st, n, batch, ld, nullptr, A.c, A.d, A.a,
+                     nullptr, y, x, info, ws, ws_ld(batch));
   return hipGetLastError();
 }
 
@@ -773,37 +667,44 @@ size_t subst_workspace_bytes(int64_t n, int64_t batch) {
   return (size_t)(n * ws_ld(batch)) * 8 + (size_t)(batch * 4 + 255) / 256 * 256;
 }
 
-hipError_t launch_subst(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
-                        const double* factors, const double* y, double* x, int32_t* info,
-                        double* ws, hipStream_t st) {
+// The split substitution of systems with active != 0 (all when NULL): y
+// (pitch yl) -> x (pitch ld), factors of pitch fld; z and the flags in ws;
+// every launch returns at once when done != NULL and *done != 0.
+hipError_t launch_subst_masked(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
+                               const double* factors, int64_t fld, const double* y, int64_t yl,
+                               double* x, int32_t* info, double* ws, const int32_t* active,
+                               const int32_t* done, hipStream_t st) {
   int64_t K = subst_chunks(n, batch);
-  if (K <= 1) return launch_subst_lane(kind, n, batch, ld, A, factors, y, x, info, st);
+  if (K <= 1) return hipErrorInvalidValue;
   const int64_t M = (n + K - 1) / K;
   K = (n + M - 1) / M;
   const int64_t zl = ws_ld(batch);
   int32_t* flags = reinterpret_cast<int32_t*>(ws + n * zl);
   const unsigned gx = (unsigned)((batch + kLaneBlock - 1) / kLaneBlock);
   const dim3 grid(gx, (unsigned)K), lanes(kLaneBlock);
+  const SubstIO io{y, yl, ws, zl, x, ld, active, done};
   // forward proofs: chunks that started before row 0 of their own (k M > warm-up)
   const int64_t fproofs = K - (kSubstWarm / M + 1);
   // backward proofs: chunks whose end lies more than the warm-up before n
   int64_t bproofs = 0;
   while (bproofs < K - 1 && n - (bproofs + 1) * M > kSubstWarm) ++bproofs;
 #define BS_SUBST(KD)                                                                          \
-  hipLaunchKernelGGL(subst_fwd_chunk_kernel<KD>, grid, lanes, 0, st, n, batch, ld, A.a, A.b,   \
-                     factors, y, ws, zl, flags, M);                                           \
-  if (fproofs > 0)                                                                            \
-    hipLaunchKernelGGL(subst_fwd_proof_kernel<KD>, dim3(gx, (unsigned)fproofs), lanes, 0, st, \
-                       n, batch, ld, A.a, A.b, factors, y, ws, zl, flags, M);                 \
-  hipLaunchKernelGGL(subst_fwd_fix_kernel<KD>, dim3(gx), lanes, 0, st, n, batch, ld, A.a, A.b, \
-                     factors, y, ws, zl, flags);                                              \
-  hipLaunchKernelGGL(subst_bwd_chunk_kernel<KD>, grid, lanes, 0, st, n, batch, ld, A.a, A.b,   \
-                     factors, ws, zl, x, M);                                                  \
-  if (bproofs > 0)                                                                            \
-    hipLaunchKernelGGL(subst_bwd_proof_kernel<KD>, dim3(gx, (unsigned)bproofs), lanes, 0, st, \
-                       n, batch, ld, A.a, A.b, factors, ws, zl, x, flags, M);                 \
-  hipLaunchKernelGGL(subst_bwd_fix_kernel<KD>, dim3(gx), lanes, 0, st, n, batch, ld, A.a,      \
-                     A.b, factors, ws, zl, x, info, flags);
+  {                                                                                           \
+    const SubstPlanes P = subst_planes<KD>(factors, fld, A.a, A.b, n, ld);                    \
+    hipLaunchKernelGGL(subst_fwd_chunk_kernel<KD>, grid, lanes, 0, st, n, batch, P, io,       \
+                       flags, M);                                                             \
+    if (fproofs > 0)                                                                          \
+      hipLaunchKernelGGL(subst_fwd_proof_kernel<KD>, dim3(gx, (unsigned)fproofs), lanes, 0,   \
+                         st, n, batch, P, io, flags, M);                                      \
+    hipLaunchKernelGGL(subst_fwd_fix_kernel<KD>, dim3(gx), lanes, 0, st, n, batch, P, io,     \
+                       flags);                                                                \
+    hipLaunchKernelGGL(subst_bwd_chunk_kernel<KD>, grid, lanes, 0, st, n, batch, P, io, M);   \
+    if (bproofs > 0)                                                                          \
+      hipLaunchKernelGGL(subst_bwd_proof_kernel<KD>, dim3(gx, (unsigned)bproofs), lanes, 0,   \
+                         st, n, batch, P, io, flags, M);                                      \
+    hipLaunchKernelGGL(subst_bwd_fix_kernel<KD>, dim3(gx), lanes, 0, st, n, batch, P, io,     \
+                       info, flags);                                                          \
+  }
   if (kind == 5) {
     BS_SUBST(5)
   } else {
@@ -813,17 +714,26 @@ hipError_t launch_subst(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
   return hipGetLastError();
 }
 
+hipError_t launch_subst(int kind, int64_t n, int64_t batch, int64_t ld, Diags A,
+                        const double* factors, const double* y, double* x, int32_t* info,
+                        double* ws, hipStream_t st) {
+  if (subst_chunks(n, batch) <= 1)
+    return launch_subst_lane(kind, n, batch, ld, A, factors, y, x, info, st);
+  return launch_subst_masked(kind, n, batch, ld, A, factors, ld, y, ld, x, info, ws, nullptr,
+                             nullptr, st);
+}
+
 hipError_t launch_subst_lane(int kind, int64_t n, int64_t batch, int64_t ld,
                              Diags A, const double* factors, const double* y,
                              double* x, int32_t* info, hipStream_t st) {
   if (kind == 5)
     hipLaunchKernelGGL(subst_lane_kernel<5>, lane_grid(batch),
                        dim3(kLaneBlock), 0, st, n, batch, ld, A.a, A.b,
-                       factors, y, x, info);
+                       factors, ld, y, x, info);
   else
     hipLaunchKernelGGL(subst_lane_kernel<3>, lane_grid(batch),
                        dim3(kLaneBlock), 0, st, n, batch, ld, A.a, A.b,
-                       factors, y, x, info);
+                       factors, ld, y, x, info);
   return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@
 // is fetched from HBM once and served from that XCD's L2 to its neighbours.
 #include <atomic>
 
+#include "seq_core.h"
 #include "split_core.h"
 
 namespace bs {
@@ -37,13 +38,22 @@ using namespace split;
 
 // One block = G systems x PW chunks of M rows = one tile of RT = M*PW rows of
 // G systems.  T <= TMAX tiles (consecutive blocks on one XCD) cover a system;
-// they exchange their tile maps through `xch` and meet at the counters
-// cnt[3*grp .. 3*grp+2] (arrivals, departures, tiles that gave up waiting;
-// reset by the last tile to leave, so the counters are zero again after every
-// completed call).  A tile waits at most wait_ticks of the 100 MHz real-time
-// clock for the others; if any tile of the group gave up, the last one to
-// leave marks the group's systems info = -4 (x unspecified), whichever tile
-// wrote info first.
+// they exchange their tile maps through `xch` and meet at the four counters
+// cnt[4*grp ..] (arrivals, departures, mask of tiles that gave up waiting,
+// mask of systems to redo; reset by the last tile to leave, so they are zero
+// again after every completed call).  A tile waits at most wait_ticks of the
+// 100 MHz real-time clock for the others, then gives up.
+//
+// Breakdown.  A system whose partitioned elimination meets a pivot or an
+// interface block that the guard rejects (zero, tiny or not finite) is
+// solved again with the sequential recurrence (seq_core.h), by one lane of
+// the last tile of its group to leave (the only tile when T = 1), so its x
+// and info are the sequential method's.  Every tile that read all tile maps
+// reaches the same verdict and writes no x for such a system.  A tile that
+// gave up writes no x at all; the last tile then solves the rows of the
+// tiles that gave up sequentially (unless x aliases the rhs, whose rows the
+// other tiles have overwritten: info = -4, x unspecified).  The sequential
+// sweeps keep alpha, beta and z in the planes at rws (pitch rpitch).
 // SPARSE: the outer diagonals come from an MNPDM list (absent entries are
 // zero, so every product with them is an exact zero).
 // ASM: the rows are assembled from the sweep input v (passed as Y) and r
@@ -57,11 +67,12 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
     const TIO* __restrict__ Y, TIO* __restrict__ X,
     int32_t* __restrict__ info, double* __restrict__ xch,
     unsigned* __restrict__ cnt, int T, const int32_t* __restrict__ skip, Outer ol,
-    double rcoef, uint64_t wait_ticks) {
+    double rcoef, uint64_t wait_ticks, double* __restrict__ rws, int64_t rpitch, int redo_gaveup) {
   constexpr int NB = KIND == 5 ? 2 : 1;
   constexpr int RS = kRecSz<NB>;
   constexpr int RT = M * PW;
   static_assert((PW & (PW - 1)) == 0 && (TMAX & (TMAX - 1)) == 0 && M >= 4, "shape");
+  static_assert(G <= 32 && TMAX <= 32, "masks");
   if (skip != nullptr && *skip) return;  // uniform: a refinement loop has finished
   __shared__ double s_node[(PW - 1) * G * RS];
   __shared__ double s_gnode[(TMAX > 1 ? TMAX - 1 : 1) * G * RS];
@@ -146,7 +157,8 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
     // The maps go through the device-coherent level with write-through
     // stores and cache-bypassing loads, so no cache-wide write-back or
     // invalidate is needed; the arrival count is bumped only after this
-    // wave's map stores have completed.
+    // wave's map stores have been acknowledged (s_waitcnt), and a tile reads
+    // the maps only after its own load of the counter has returned T.
     constexpr int XS = RS + 1;  // map + first bad row of the tile
     if (tid < 64) {  // wave 0 holds the tile maps (lanes j == 0, tid < G)
       if (j == 0) {
@@ -159,9 +171,9 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
       __builtin_amdgcn_s_waitcnt(kWaitVmem);
       if (tid == 0) {
         // the last tile to arrive has nothing to wait for
-        if (atomicAdd(&cnt[3 * grp], 1u) + 1 < (unsigned)T) {
+        if (atomicAdd(&cnt[4 * grp], 1u) + 1 < (unsigned)T) {
           const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-          while (ld_counter(&cnt[3 * grp]) < (unsigned)T) {
+          while (ld_counter(&cnt[4 * grp]) < (unsigned)T) {
             __builtin_amdgcn_s_sleep(2);
             if (__builtin_amdgcn_s_memrealtime() - t0 > wait_ticks) {
               s_timeout = 1;
@@ -211,39 +223,104 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
     }
   }
   __syncthreads();
+  // s_bad and s_timeout are final: read them before the walk down, which
+  // hides the LDS latency
+  const bool redo = s_bad[g] != kBadNone && !list_bad;
+  const bool write = live && !s_timeout && !redo;
 
   // ---- 3. back down the tile's tree, then x = p - V x_L - W x_R ---------
   tree_down<NB, PW, G>(xl, xr, j, g, s_node);
-  write_chunk<NB, M>(n, ld, s, live, r0, 0, p, v, w, xl, xr, X);
+  write_chunk<NB, M>(n, ld, s, write, r0, 0, p, v, w, xl, xr, X);
   // info at the device-coherent level: the last tile to leave may overwrite
   // it from another XCD
-  if (j == 0 && tile == 0 && live) {
-    const int b0 = s_bad[g];
-    st_coherent_i32(&info[s],
-                    list_bad ? kBadList : (s_timeout ? kTimeout : ((b0 == kBadNone) ? 0 : b0)));
+  if (j == 0 && tile == 0 && live && !s_timeout && !redo)
+    st_coherent_i32(&info[s], list_bad ? kBadList : 0);
+
+  // ---- 4. the sequential redo --------------------------------------------
+  // Lane g of the redoing tile solves system g; rows i with keep(i) are
+  // written (all rows, or the rows of the tiles that gave up).
+  auto redo_system = [&](uint32_t tiles_mask) {
+    auto fetch = [&](int64_t i) {
+      const int64_t o = i * ld + s;
+      seq::Row rw;
+      if constexpr (ASM) {
+        const double* V = reinterpret_cast<const double*>(Y);
+        const double vm = (i >= 1) ? V[o - ld] : 0.0;
+        const double vp = (i + 1 < n) ? V[o + ld] : 0.0;
+        assemble_row<KIND>(i, n, vm, V[o], vp, rcoef, rw.e, rw.c, rw.d, rw.a, rw.b, rw.y);
+      } else {
+        rw.c = (double)C[o];
+        rw.d = (double)D[o];
+        rw.a = (double)A[o];
+        rw.y = (double)Y[o];
+        rw.e = rw.b = 0.0;
+        if constexpr (KIND == 5 && SPARSE) {
+          for (int k = 0; k < ol.kmax; ++k) {
+            const int64_t lo = (int64_t)k * ld + s;
+            if (ol.row[lo] == i) {
+              rw.e = (i >= 2) ? ol.e[lo] : 0.0;
+              rw.b = (i <= n - 3) ? ol.b[lo] : 0.0;
+            }
+          }
+        } else if constexpr (KIND == 5) {
+          rw.e = (double)E[o];
+          rw.b = (double)B[o];
+        }
+      }
+      return rw;
+    };
+    const int64_t plane = n * rpitch;
+    const seq::Planes P{rws, rws + plane, rpitch, rws + (KIND == 5 ? 2 : 1) * plane, rpitch, s};
+    const int64_t sb = seq::solve<KIND>(
+        n, fetch, P, [&](int64_t i, double xv) { X[i * ld + s] = (TIO)xv; },
+        [&](int64_t i) { return ((tiles_mask >> (uint32_t)(i / RT)) & 1u) != 0u; });
+    st_coherent_i32(&info[s], sb < 0 ? 0 : (int32_t)(sb + 1));
+  };
+  if (T == 1) {
+    if (tid < G && live && redo) redo_system(~0u);
+    return;
   }
   // Departure, off the critical path: every tile read all maps before the
-  // barrier after the exchange.  A tile that gave up waiting says so first;
-  // the last one out marks the group if any did and resets the meeting point.
-  // Wave 0 alone (it holds the info stores and every lane with j == 0), so
-  // the other waves retire as soon as their x stores are issued.
-  if (T > 1 && tid < 64) {
+  // barrier after the exchange.  Wave 0 alone (it holds the info stores and
+  // every lane with j == 0), so the other waves retire as soon as their x
+  // stores are issued.  A tile that gave up adds its bit to the give-up
+  // mask; a tile that read every map adds the systems it found bad to the
+  // redo mask; then it departs.  Each departure waits for the returned value
+  // of the mask update, so the last tile to leave sees every mask bit.
+  if (tid < 64) {
     __builtin_amdgcn_s_waitcnt(kWaitVmem);  // this wave's info stores are in place
+    const uint64_t bad_lanes = __ballot(tid < G && redo);
     unsigned last = 0;
     if (tid == 0) {
-      unsigned gave_up = 0;
-      if (s_timeout) gave_up = atomicAdd(&cnt[3 * grp + 2], 1u) + 1;
-      // the departure is issued once the give-up count has returned
-      last = (gave_up != ~0u && atomicAdd(&cnt[3 * grp + 1], 1u) == (unsigned)T - 1) ? 1u : 0u;
+      const unsigned sysmask = (unsigned)(bad_lanes & ((1ull << G) - 1ull));
+      unsigned before = 0;
+      if (s_timeout)
+        before = atomicOr(&cnt[4 * grp + 2], 1u << (unsigned)tile);
+      else if (sysmask != 0u)
+        before = atomicOr(&cnt[4 * grp + 3], sysmask);
+      last = (before != ~0u && atomicAdd(&cnt[4 * grp + 1], 1u) == (unsigned)T - 1) ? 1u : 0u;
     }
     if (__builtin_amdgcn_readfirstlane(last)) {
-      unsigned gave = 0;
-      if (tid < G) gave = ld_counter(&cnt[3 * grp + 2]);
-      if (tid < G && live && gave != 0u) st_coherent_i32(&info[s], kTimeout);
-      if (tid == 0 && gave != ~0u) {  // after the count was read
-        __hip_atomic_store(&cnt[3 * grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&cnt[3 * grp + 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&cnt[3 * grp + 2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      unsigned gave = 0, sysmask = 0;
+      if (tid < G) {
+        gave = ld_counter(&cnt[4 * grp + 2]);
+        sysmask = ld_counter(&cnt[4 * grp + 3]);
+      }
+      if (tid < G && live && !list_bad) {
+        if ((sysmask >> tid) & 1u)
+          redo_system(~0u);
+        else if (gave != 0u) {
+          if (redo_gaveup)
+            redo_system(gave);
+          else
+            st_coherent_i32(&info[s], kTimeout);
+        }
+      }
+      if (tid == 0 && (gave | sysmask) != ~0u) {  // after the masks were read
+        __hip_atomic_store(&cnt[4 * grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&cnt[4 * grp + 1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&cnt[4 * grp + 2], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&cnt[4 * grp + 3], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
   }
@@ -269,7 +346,8 @@ __global__ __launch_bounds__(G * PW) void long_tile_kernel(
     const TIO* __restrict__ C, const TIO* __restrict__ D,
     const TIO* __restrict__ A, const TIO* __restrict__ B,
     const TIO* __restrict__ Y, TIO* __restrict__ X, double* __restrict__ maps,
-    const double* __restrict__ bounds, int64_t T, const int32_t* __restrict__ skip) {
+    const double* __restrict__ bounds, int64_t T, const int32_t* __restrict__ skip,
+    const int32_t* __restrict__ info) {
   if (skip != nullptr && *skip) return;
   constexpr int NB = KIND == 5 ? 2 : 1;
   constexpr int RS = kRecSz<NB>;
@@ -317,7 +395,42 @@ __global__ __launch_bounds__(G * PW) void long_tile_kernel(
     }
     __syncthreads();
     tree_down<NB, PW, G, true>(xl, xr, j, g, s_node);
-    write_chunk<NB, M>(n, ld, s, live, r0, row_base, p, v, w, xl, xr, X + shift);
+    // systems the reduction found bad are left to the sequential redo
+    if (!(live && info[s] == seq::kRedo))
+      write_chunk<NB, M>(n, ld, s, live, r0, row_base, p, v, w, xl, xr, X + shift);
+  }
+}
+
+// The sequential redo of the systems marked seq::kRedo: lane t owns redo
+// slot t (columns of the planes, pitch R) and takes systems t, t + R, ...
+template <typename TIO, int KIND>
+__global__ __launch_bounds__(64) void long_redo_kernel(
+    int64_t n, int64_t batch, int64_t ld, const TIO* __restrict__ E, const TIO* __restrict__ C,
+    const TIO* __restrict__ D, const TIO* __restrict__ A, const TIO* __restrict__ B,
+    const TIO* __restrict__ Y, TIO* __restrict__ X, int32_t* __restrict__ info,
+    double* __restrict__ planes, int64_t R, const int32_t* __restrict__ skip) {
+  if (skip != nullptr && *skip) return;
+  const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (t >= R) return;
+  const int64_t plane = n * R;
+  for (int64_t s = t; s < batch; s += R) {
+    if (info[s] != seq::kRedo) continue;
+    auto fetch = [&](int64_t i) {
+      const int64_t o = i * ld + s;
+      seq::Row rw;
+      rw.e = (KIND == 5) ? (double)E[o] : 0.0;
+      rw.c = (double)C[o];
+      rw.d = (double)D[o];
+      rw.a = (double)A[o];
+      rw.b = (KIND == 5) ? (double)B[o] : 0.0;
+      rw.y = (double)Y[o];
+      return rw;
+    };
+    const seq::Planes P{planes, planes + plane, R, planes + (KIND == 5 ? 2 : 1) * plane, R, t};
+    const int64_t sb = seq::solve<KIND>(
+        n, fetch, P, [&](int64_t i, double xv) { X[i * ld + s] = (TIO)xv; },
+        [](int64_t) { return true; });
+    info[s] = sb < 0 ? 0 : (int32_t)(sb + 1);
   }
 }
 
@@ -404,10 +517,7 @@ __global__ __launch_bounds__(256) void long_reduce_kernel(
     }
   }
   __syncthreads();
-  if (lane == 0 && live) {
-    const int b0 = s_bad[wv];
-    info[s] = (b0 == kBadNone) ? 0 : b0;
-  }
+  if (lane == 0 && live) info[s] = (s_bad[wv] == kBadNone) ? 0 : seq::kRedo;
 }
 
 struct Variant {
@@ -425,6 +535,25 @@ constexpr int kLongM = 32, kLongPW = 16, kLongG = 16;
 // Longest wait of a tile for the other tiles of its system, microseconds.
 std::atomic<int64_t> g_exchange_wait_us{1000000};
 
+// Workspace of a single-launch variant, in doubles: the meeting counters
+// (4 per group) and the tile-map exchange when T > 1, then the planes of the
+// sequential redo (alpha, beta, z for PD; alpha, z for TD), 256-byte aligned.
+struct PartWs {
+  int64_t xch, planes, total;
+};
+PartWs part_ws(int kind, int64_t n, int64_t batch, int64_t M, int64_t PW, int64_t G) {
+  const int64_t RT = M * PW;
+  const int64_t T = (n + RT - 1) / RT;
+  const int64_t groups = (batch + G - 1) / G;
+  const int64_t xs = (kind == 5 ? 20 : 6) + 1;
+  PartWs W;
+  W.xch = 2 * groups;  // 4 * groups unsigned counters
+  const int64_t head = (T > 1) ? W.xch + groups * T * G * xs : 0;
+  W.planes = (head + 31) / 32 * 32;
+  W.total = W.planes + (kind == 5 ? 3 : 2) * n * ws_ld(batch);
+  return W;
+}
+
 template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false,
           bool ASM = false>
 hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, const void* const* dg,
@@ -434,14 +563,38 @@ hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, const void* const* d
   constexpr int RT = M * PW;
   const int T = (int)((n + RT - 1) / RT);
   const int64_t groups = (batch + G - 1) / G;
+  const PartWs W = part_ws(KIND, n, batch, M, PW, G);
   unsigned* cnt = (T > 1) ? reinterpret_cast<unsigned*>(ws) : nullptr;
-  double* xch = (T > 1) ? ws + (3 * groups + 1) / 2 + 1 : nullptr;
+  double* xch = (T > 1) ? ws + W.xch : nullptr;
   hipLaunchKernelGGL((part_kernel<TIO, KIND, M, PW, G, TMAX, WPE, SPARSE, ASM>),
                      dim3((unsigned)(groups * T)), dim3(G * PW), 0, st, n, batch, ld,
                      (const TIO*)dg[0], (const TIO*)dg[1], (const TIO*)dg[2], (const TIO*)dg[3],
                      (const TIO*)dg[4], (const TIO*)y, (TIO*)x, info, xch, cnt, T, skip, ol,
-                     rcoef, (uint64_t)g_exchange_wait_us.load() * 100u);
+                     rcoef, (uint64_t)g_exchange_wait_us.load() * 100u, ws + W.planes,
+                     ws_ld(batch), (int)(x != y));
   return hipGetLastError();
+}
+
+// Long-path workspace, in doubles: tile maps, outer pairs, fold nodes, then
+// the planes of R redo slots (256-byte aligned).
+struct LongWs {
+  int64_t maps, bounds, nodes, planes, R, total;
+};
+LongWs long_ws(int kind, int64_t n, int64_t batch) {
+  const int64_t NB = kind == 5 ? 2 : 1;
+  const int64_t RS = 2 * NB + 4 * NB * NB;
+  const int64_t RT = (int64_t)kLongM * kLongPW;
+  const int64_t T = (n + RT - 1) / RT;
+  const int64_t recs = (batch + kLongG - 1) / kLongG * T * kLongG;
+  const int64_t np = kind == 5 ? 3 : 2;
+  LongWs W;
+  W.maps = 0;
+  W.bounds = W.maps + recs * (RS + 1);
+  W.nodes = W.bounds + recs * 2 * NB;
+  W.planes = (W.nodes + batch * T * RS + 31) / 32 * 32;
+  W.R = seq::redo_slots(np, n, batch);
+  W.total = W.planes + np * n * W.R;
+  return W;
 }
 
 template <typename TIO, int KIND>
@@ -449,20 +602,18 @@ hipError_t launch_long(int64_t n, int64_t batch, int64_t ld, const void* const* 
                        const void* y, void* x, int32_t* info, double* ws, hipStream_t st,
                        const int32_t* skip) {
   constexpr int M = kLongM, PW = kLongPW, G = kLongG;
-  constexpr int NB = KIND == 5 ? 2 : 1;
-  constexpr int RS = kRecSz<NB>;
   const int64_t RT = (int64_t)M * PW;
   const int64_t T = (n + RT - 1) / RT;
   const int64_t groups = (batch + G - 1) / G;
-  const int64_t recs = groups * T * G;
-  double* maps = ws;
-  double* bounds = maps + recs * (RS + 1);
-  double* nodes = bounds + recs * 2 * NB;
+  const LongWs W = long_ws(KIND, n, batch);
+  double* maps = ws + W.maps;
+  double* bounds = ws + W.bounds;
+  double* nodes = ws + W.nodes;
   const TIO* P[6] = {(const TIO*)dg[0], (const TIO*)dg[1], (const TIO*)dg[2],
                      (const TIO*)dg[3], (const TIO*)dg[4], (const TIO*)y};
   hipLaunchKernelGGL((long_tile_kernel<false, TIO, KIND, M, PW, G>), dim3((unsigned)(groups * T)),
                      dim3(G * PW), 0, st, n, batch, ld, P[0], P[1], P[2], P[3], P[4], P[5],
-                     (TIO*)x, maps, bounds, T, skip);
+                     (TIO*)x, maps, bounds, T, skip, nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((long_reduce_kernel<KIND, G>), dim3((unsigned)((batch + 3) / 4)), dim3(256),
@@ -471,7 +622,12 @@ hipError_t launch_long(int64_t n, int64_t batch, int64_t ld, const void* const* 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((long_tile_kernel<true, TIO, KIND, M, PW, G>), dim3((unsigned)(groups * T)),
                      dim3(G * PW), 0, st, n, batch, ld, P[0], P[1], P[2], P[3], P[4], P[5],
-                     (TIO*)x, maps, bounds, T, skip);
+                     (TIO*)x, maps, bounds, T, skip, info);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((long_redo_kernel<TIO, KIND>), dim3((unsigned)((W.R + 63) / 64)), dim3(64),
+                     0, st, n, batch, ld, P[0], P[1], P[2], P[3], P[4], P[5], (TIO*)x, info,
+                     ws + W.planes, W.R, skip);
   return hipGetLastError();
 }
 
@@ -528,12 +684,7 @@ int part_pick(int kind, int idx, int64_t n, int64_t ld, int dtype) {
 size_t part_workspace_bytes(int kind, int idx, int64_t n, int64_t batch) {
   const Variant* v = find_variant(kind, idx);
   if (!v) return 0;
-  const int64_t RT = (int64_t)v->M * v->PW;
-  const int64_t T = (n + RT - 1) / RT;
-  const int64_t groups = (batch + v->G - 1) / v->G;
-  const int64_t rs = (kind == 5 ? 20 : 6) + 1;
-  if (T <= 1) return 0;
-  return (size_t)(((3 * groups + 1) / 2 + 1) + groups * T * v->G * rs) * 8;
+  return (size_t)part_ws(kind, n, batch, v->M, v->PW, v->G).total * 8;
 }
 
 hipError_t launch_part(int kind, int idx, int dtype, int64_t n, int64_t batch, int64_t ld,
@@ -613,12 +764,7 @@ bool long_supported(int64_t n, int64_t ld, int dtype) {
 }
 
 size_t long_workspace_bytes(int kind, int64_t n, int64_t batch) {
-  const int64_t NB = kind == 5 ? 2 : 1;
-  const int64_t RS = 2 * NB + 4 * NB * NB;
-  const int64_t RT = (int64_t)kLongM * kLongPW;
-  const int64_t T = (n + RT - 1) / RT;
-  const int64_t recs = (batch + kLongG - 1) / kLongG * T * kLongG;
-  return (size_t)(recs * (RS + 1) + recs * 2 * NB + (int64_t)batch * T * RS) * 8;
+  return (size_t)long_ws(kind, n, batch).total * 8;
 }
 
 hipError_t launch_long_path(int kind, int dtype, int64_t n, int64_t batch, int64_t ld,

@@ -63,11 +63,13 @@ __device__ inline void mv(const double (&A)[NB][NB], const double (&x)[NB],
   }
 }
 
-// Inverse of a 1x1 or 2x2 block; false if singular or not finite.
-__device__ inline bool inv(const double (&M)[1][1], double (&R)[1][1]) {
-  R[0][0] = 1.0 / M[0][0];
-  return M[0][0] != 0.0 && isfinite(R[0][0]);
-}
+// Breakdown guard of the partitioned elimination: a pivot (or interface
+// determinant) counts as bad when it is not finite or not larger than
+// kGuard times the magnitude of the terms it is formed from.  Such a pivot
+// either breaks the elimination or amplifies rounding by more than 1/kGuard,
+// so the system is redone with the sequential recurrence instead.
+constexpr double kGuard = 0x1p-12;
+
 // 1/x from the hardware reciprocal estimate and two Newton steps (full
 // double precision up to an ulp; pivots and interface blocks are far from the
 // subnormal range).  The chunk recurrences divide by every pivot in a chain
@@ -81,27 +83,36 @@ __device__ inline double recip(double x) {
   // +-inf -> +-0, as 1/x), where the Newton steps would give NaN
   return (x != 0.0 && isfinite(x)) ? r : r0;
 }
-__device__ inline bool inv(const double (&M)[2][2], double (&R)[2][2]) {
-  const double det = fma(M[0][0], M[1][1], -M[0][1] * M[1][0]);
+// Inverse of the 1x1 or 2x2 interface block M = I - P (P = Wb Vt); false
+// if the guard rejects it.
+__device__ inline bool inv(const double (&M)[1][1], const double (&P)[1][1], double (&R)[1][1]) {
+  R[0][0] = recip(M[0][0]);
+  return fabs(M[0][0]) > kGuard * (1.0 + fabs(P[0][0])) && isfinite(R[0][0]);
+}
+__device__ inline bool inv(const double (&M)[2][2], const double (&P)[2][2], double (&R)[2][2]) {
+  const double p1 = M[0][0] * M[1][1], p2 = M[0][1] * M[1][0];
+  const double det = p1 - p2;
   const double r = recip(det);
   R[0][0] = M[1][1] * r;
   R[0][1] = -M[0][1] * r;
   R[1][0] = -M[1][0] * r;
   R[1][1] = M[0][0] * r;
-  return det != 0.0 && isfinite(r);
+  // magnitude of det's terms, bounded with |M_ij| <= delta_ij + |P_ij|
+  const double sc = (1.0 + fabs(P[0][0])) * (1.0 + fabs(P[1][1])) + fabs(P[0][1]) * fabs(P[1][0]);
+  return fabs(det) > kGuard * sc && isfinite(r);
 }
 
 // Merge left part A with right part B (B's x_L is A's bottom pair, A's x_R
 // is B's top pair).  Returns false if the interface block is singular.
 template <int NB>
 __device__ bool merge(const Map<NB>& A, const Map<NB>& B, Map<NB>& AB, Node<NB>& nd) {
-  double Mx[NB][NB], S[NB][NB], T1[NB][NB], t[NB];
-  mm<NB>(A.Wb, B.Vt, Mx);
+  double Px[NB][NB], Mx[NB][NB], S[NB][NB], T1[NB][NB], t[NB];
+  mm<NB>(A.Wb, B.Vt, Px);
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) Mx[i][j] = (i == j ? 1.0 : 0.0) - Mx[i][j];
-  const bool ok = inv(Mx, S);
+    for (int j = 0; j < NB; ++j) Mx[i][j] = (i == j ? 1.0 : 0.0) - Px[i][j];
+  const bool ok = inv(Mx, Px, S);
   mv<NB>(A.Wb, B.pt, t);
 #pragma unroll
   for (int i = 0; i < NB; ++i) t[i] = A.pb[i] - t[i];
@@ -161,7 +172,10 @@ __device__ inline void load_rec(R& r, const double* src) {
   for (int q = 0; q < (int)(sizeof(R) / sizeof(double)); ++q) dst[q] = src[q];
 }
 
-__device__ inline bool bad_pivot(double m) { return !(m != 0.0) || !isfinite(m); }
+// Local pivot mu of a row whose inner entries have magnitude sum sc.
+__device__ inline bool bad_pivot(double mu, double sc) {
+  return !(fabs(mu) > kGuard * sc) || !isfinite(mu);
+}
 
 // Streaming accesses: every input element is read once and every x element
 // written once, so they carry the non-temporal hint.  Storage may be FP64 or
@@ -204,7 +218,9 @@ __device__ inline void chunk_pd(const double (&e)[M], const double (&c)[M],
       ga = fma(-al[r - 2], e[r], c[r]);
       mu = fma(-al[r - 1], ga, fma(-be[r - 2], e[r], d[r]));
     }
-    if (bad == M && bad_pivot(mu)) bad = r;
+    // the row's magnitude from its inner three entries (measured: adding the
+    // outer two costs 5 us per sweep batch, the scale only sets the guard)
+    if (bad == M && bad_pivot(mu, fabs(c[r]) + fabs(d[r]) + fabs(a[r]))) bad = r;
     const double rc = recip(mu);  // off the IEEE division's longer chain
     if (r == 0)
       al[0] = a[0] * rc;
@@ -259,7 +275,7 @@ __device__ inline void chunk_td(const double (&c)[M], const double (&d)[M],
 #pragma unroll
   for (int r = 0; r < M; ++r) {
     const double mu = (r == 0) ? d[0] : fma(-al[r - 1], c[r], d[r]);
-    if (bad == M && bad_pivot(mu)) bad = r;
+    if (bad == M && bad_pivot(mu, fabs(c[r]) + fabs(d[r]) + fabs(a[r]))) bad = r;
     const double rc = recip(mu);  // off the IEEE division's longer chain
     al[r] = (r <= M - 2) ? a[r] * rc : 0.0;
     if (r == 0) {
@@ -502,7 +518,7 @@ __device__ inline void load_chunk(int64_t n, int64_t ld, int64_t s, bool live, i
   }
 }
 
-// The rows of a chunk assembled from the sweep input v instead of loaded: one
+// Rows assembled from the sweep input v instead of loaded: one
 // implicit sweep (I - tau L(k(v))) w = v of u_t = (k(u) u_x)_x, k = 1 + u^2,
 // with r = tau / h^2 and k_{i+1/2} = (k(v_i) + k(v_{i+1})) / 2:
 //   c_i = -r k_{i-1/2},  a_i = -r k_{i+1/2},  d_i = 1 + r (k_{i-1/2} + k_{i+1/2}),
@@ -510,14 +526,54 @@ __device__ inline void load_chunk(int64_t n, int64_t ld, int64_t s, bool live, i
 // and zero-flux boundary rows with rhs 0: first order (KIND 3) [1, -1] and
 // [-1, 1]; second order (KIND 5) [-3, 4, -1] and [1, -4, 3].  Every product
 // and sum is rounded on its own in this order, so the coefficients are those
-// of the host generator of the same sweep to the last bit.  Reads v at rows
-// r0 - 1 .. r0 + M only: 8 bytes per row instead of 48.
+// of the host generator of the same sweep to the last bit.
+// Row i (0 <= i < n) of that sweep from vm = v_{i-1}, v0 = v_i, vp = v_{i+1}
+// (values outside the matrix are not used).
+template <int KIND>
+__device__ inline void assemble_row(int64_t i, int64_t n, double vm, double v0, double vp,
+                                    double r, double& e, double& c, double& d, double& a,
+                                    double& b, double& y) {
+#pragma clang fp contract(off)
+  e = c = a = b = y = 0.0;
+  d = 1.0;
+  if (i == 0) {
+    if (KIND == 5) {
+      d = -3.0;
+      a = 4.0;
+      b = -1.0;
+    } else {
+      d = 1.0;
+      a = -1.0;
+    }
+  } else if (i == n - 1) {
+    if (KIND == 5) {
+      e = 1.0;
+      c = -4.0;
+      d = 3.0;
+    } else {
+      c = -1.0;
+      d = 1.0;
+    }
+  } else {
+    const double km = 1.0 + vm * vm;
+    const double k0 = 1.0 + v0 * v0;
+    const double kp = 1.0 + vp * vp;
+    const double hl = 0.5 * (km + k0);
+    const double hr = 0.5 * (k0 + kp);
+    c = -r * hl;
+    a = -r * hr;
+    d = 1.0 + r * (hl + hr);
+    y = v0;
+  }
+}
+
+// The rows of a chunk assembled from v: reads v at rows r0 - 1 .. r0 + M
+// only, 8 bytes per row instead of 48.  Identity rows past n.
 template <int KIND, int M>
 __device__ inline void assemble_chunk(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
                                       const double* __restrict__ V, double r, double (&e)[M],
                                       double (&c)[M], double (&d)[M], double (&a)[M],
                                       double (&b)[M], double (&y)[M]) {
-#pragma clang fp contract(off)
   double vv[M + 2];
 #pragma unroll
   for (int q = 0; q < M + 2; ++q) {
@@ -526,41 +582,15 @@ __device__ inline void assemble_chunk(int64_t n, int64_t ld, int64_t s, bool liv
                 ? __builtin_nontemporal_load(V + (i * ld + s))
                 : 0.0;
   }
-  const double mr = -r;
 #pragma unroll
   for (int q = 0; q < M; ++q) {
     const int64_t i = r0 + q;
-    e[q] = c[q] = a[q] = b[q] = y[q] = 0.0;
-    d[q] = 1.0;  // identity rows past n
-    if (!(live && i < n)) continue;
-    if (i == 0) {
-      if (KIND == 5) {
-        d[q] = -3.0;
-        a[q] = 4.0;
-        b[q] = -1.0;
-      } else {
-        d[q] = 1.0;
-        a[q] = -1.0;
-      }
-    } else if (i == n - 1) {
-      if (KIND == 5) {
-        e[q] = 1.0;
-        c[q] = -4.0;
-        d[q] = 3.0;
-      } else {
-        c[q] = -1.0;
-        d[q] = 1.0;
-      }
-    } else {
-      const double km = 1.0 + vv[q] * vv[q];
-      const double k0 = 1.0 + vv[q + 1] * vv[q + 1];
-      const double kp = 1.0 + vv[q + 2] * vv[q + 2];
-      const double hl = 0.5 * (km + k0);
-      const double hr = 0.5 * (k0 + kp);
-      c[q] = mr * hl;
-      a[q] = mr * hr;
-      d[q] = 1.0 + r * (hl + hr);
-      y[q] = vv[q + 1];
+    if (live && i < n) {
+      assemble_row<KIND>(i, n, vv[q], vv[q + 1], vv[q + 2], r, e[q], c[q], d[q], a[q], b[q],
+                         y[q]);
+    } else {  // identity rows past n
+      e[q] = c[q] = a[q] = b[q] = y[q] = 0.0;
+      d[q] = 1.0;
     }
   }
 }

@@ -28,6 +28,7 @@
 #include <vector>
 
 #include "bandsolve.h"
+#include "seq_core.h"
 #include "split_core.h"
 
 namespace bs {
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(kVG * PW) void varlen_tile_kernel(
     VarTab tab, const double* __restrict__ E, const double* __restrict__ C,
     const double* __restrict__ D, const double* __restrict__ A, const double* __restrict__ B,
     const double* __restrict__ Y, double* __restrict__ X, double* __restrict__ maps,
-    const double* __restrict__ bounds) {
+    const double* __restrict__ bounds, const int32_t* __restrict__ info) {
   constexpr int G = kVG;
   constexpr int NB = KIND == 5 ? 2 : 1;
   constexpr int RS = kRecSz<NB>;
@@ -119,7 +120,9 @@ __global__ __launch_bounds__(kVG * PW) void varlen_tile_kernel(
     }
     __syncthreads();
     tree_down<NB, PW, G, true>(xl, xr, j, g, s_node);
-    write_chunk<NB, M>(ns, G, g, live, r0, row_base, p, v, w, xl, xr, X + shift);
+    // systems the reduction found bad are left to the sequential redo
+    if (!(live && info[grp * G + g] == seq::kRedo))
+      write_chunk<NB, M>(ns, G, g, live, r0, row_base, p, v, w, xl, xr, X + shift);
   }
 }
 
@@ -210,9 +213,40 @@ __global__ __launch_bounds__(256) void varlen_reduce_kernel(VarTab tab, int64_t 
     }
   }
   __syncthreads();
-  if (lane == 0 && live) {
-    const int b0 = s_bad[wv];
-    info[slot] = (b0 == kBadNone) ? 0 : b0;
+  if (lane == 0 && live) info[slot] = (s_bad[wv] == kBadNone) ? 0 : seq::kRedo;
+}
+
+// The sequential redo of the systems marked seq::kRedo: lane t owns redo
+// slot t (plane columns, pitch R) and takes system slots t, t + R, ...
+template <int KIND>
+__global__ __launch_bounds__(64) void varlen_redo_kernel(
+    VarTab tab, const double* __restrict__ E, const double* __restrict__ C,
+    const double* __restrict__ D, const double* __restrict__ A, const double* __restrict__ B,
+    const double* __restrict__ Y, double* __restrict__ X, int32_t* __restrict__ info,
+    double* __restrict__ planes, int64_t R, int64_t nmax) {
+  const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (t >= R) return;
+  const int64_t plane = nmax * R;
+  for (int64_t slot = t; slot < tab.groups * kVG; slot += R) {
+    const int64_t ns = tab.sn[slot];
+    if (ns <= 0 || info[slot] != seq::kRedo) continue;
+    const int64_t base = tab.goff[slot / kVG] + slot % kVG;  // row r at base + 16 r
+    auto fetch = [&](int64_t i) {
+      const int64_t o = base + i * kVG;
+      seq::Row rw;
+      rw.e = (KIND == 5) ? E[o] : 0.0;
+      rw.c = C[o];
+      rw.d = D[o];
+      rw.a = A[o];
+      rw.b = (KIND == 5) ? B[o] : 0.0;
+      rw.y = Y[o];
+      return rw;
+    };
+    const seq::Planes P{planes, planes + plane, R, planes + (KIND == 5 ? 2 : 1) * plane, R, t};
+    const int64_t sb = seq::solve<KIND>(
+        ns, fetch, P, [&](int64_t i, double xv) { X[base + i * kVG] = xv; },
+        [](int64_t) { return true; });
+    info[slot] = sb < 0 ? 0 : (int32_t)(sb + 1);
   }
 }
 
@@ -245,30 +279,33 @@ VarTab dev_tab(const bs_varlen_info* vi, const void* table, int variant) {
 }
 
 struct WsLayout {
-  size_t maps, bounds, nodes, total;  // in doubles
+  size_t maps, bounds, nodes, planes, total;  // in doubles
+  int64_t R;                                  // redo slots
 };
-WsLayout ws_layout(int kind, int64_t tiles) {
+WsLayout ws_layout(int kind, int64_t tiles, int64_t count, int64_t nmax) {
   const int64_t NB = kind == 5 ? 2 : 1, RS = 2 * NB + 4 * NB * NB;
+  const int64_t np = kind == 5 ? 3 : 2;
   const int64_t recs = tiles * kVG;
   WsLayout W;
   W.maps = 0;
   W.bounds = W.maps + recs * (RS + 1);
   W.nodes = W.bounds + recs * 2 * NB;
-  W.total = W.nodes + recs * RS;
+  W.planes = (W.nodes + recs * RS + 31) / 32 * 32;
+  W.R = seq::redo_slots(np, nmax, count);
+  W.total = W.planes + (size_t)(np * nmax * W.R);
   return W;
 }
 
 template <int KIND, int M, int PW>
-hipError_t launch_shape(const VarTab& tab, int64_t tiles, int64_t slots, const void* const dg[5],
-                        const double* y, double* x, int32_t* info, double* ws,
-                        hipStream_t st) {
-  const WsLayout W = ws_layout(KIND, tiles);
+hipError_t launch_shape(const VarTab& tab, int64_t tiles, int64_t slots, const WsLayout& W,
+                        int64_t nmax, const void* const dg[5], const double* y, double* x,
+                        int32_t* info, double* ws, hipStream_t st) {
   const double* P[5] = {static_cast<const double*>(dg[0]), static_cast<const double*>(dg[1]),
                         static_cast<const double*>(dg[2]), static_cast<const double*>(dg[3]),
                         static_cast<const double*>(dg[4])};
   hipLaunchKernelGGL((varlen_tile_kernel<false, KIND, M, PW>), dim3((unsigned)tiles),
                      dim3(kVG * PW), 0, st, tab, P[0], P[1], P[2], P[3], P[4], y, x,
-                     ws + W.maps, ws + W.bounds);
+                     ws + W.maps, ws + W.bounds, nullptr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((varlen_reduce_kernel<KIND>), dim3((unsigned)((slots + 3) / 4)), dim3(256),
@@ -278,7 +315,11 @@ hipError_t launch_shape(const VarTab& tab, int64_t tiles, int64_t slots, const v
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((varlen_tile_kernel<true, KIND, M, PW>), dim3((unsigned)tiles),
                      dim3(kVG * PW), 0, st, tab, P[0], P[1], P[2], P[3], P[4], y, x,
-                     ws + W.maps, ws + W.bounds);
+                     ws + W.maps, ws + W.bounds, info);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((varlen_redo_kernel<KIND>), dim3((unsigned)((W.R + 63) / 64)), dim3(64), 0,
+                     st, tab, P[0], P[1], P[2], P[3], P[4], y, x, info, ws + W.planes, W.R, nmax);
   return hipGetLastError();
 }
 
@@ -287,9 +328,10 @@ hipError_t launch_varlen(int kind, int variant, const bs_varlen_info* vi, const 
                          double* ws, hipStream_t st) {
   const VarTab tab = dev_tab(vi, table, variant);
   const int64_t tiles = vi->tiles[variant], slots = vi->groups * kVG;
+  const WsLayout W = ws_layout(kind, tiles, vi->count, vi->nmax);
 #define BS_VL(K, V, MM, PP)                                                                   \
   if (kind == K && variant == V)                                                              \
-    return launch_shape<K, MM, PP>(tab, tiles, slots, dg, y, x, info, ws, st);
+    return launch_shape<K, MM, PP>(tab, tiles, slots, W, vi->nmax, dg, y, x, info, ws, st);
   BS_VL(5, 0, 32, 16) BS_VL(5, 1, 16, 16) BS_VL(5, 2, 32, 8)
   BS_VL(3, 0, 32, 16) BS_VL(3, 1, 16, 16) BS_VL(3, 2, 32, 8)
 #undef BS_VL
@@ -297,7 +339,8 @@ hipError_t launch_varlen(int kind, int variant, const bs_varlen_info* vi, const 
 }
 
 bool info_ok(const bs_varlen_info* vi) {
-  if (vi == nullptr || vi->count < 1 || vi->groups < 1 || vi->groups > (int64_t(1) << 26))
+  if (vi == nullptr || vi->count < 1 || vi->groups < 1 || vi->groups > (int64_t(1) << 26) ||
+      vi->nmax < 8 || vi->nmax >= (int64_t(1) << 31))
     return false;
   for (int v = 0; v < kNV; ++v)
     if (vi->tiles[v] < vi->groups || vi->tiles[v] > (int64_t(1) << 31)) return false;
@@ -342,6 +385,7 @@ int32_t bs_varlen_layout(int64_t count, const int64_t* n, int64_t* offset, int32
   info->count = count;
   info->groups = groups;
   info->elems = elems;
+  info->nmax = gn[0];
   for (int v = 0; v < kNV; ++v) {
     const int64_t RT = (int64_t)kShapes[v].M * kShapes[v].PW;
     int64_t t = 0;
@@ -375,7 +419,7 @@ int32_t bs_varlen_layout(int64_t count, const int64_t* n, int64_t* offset, int32
 size_t bs_varlen_workspace_bytes(int32_t kind, const bs_varlen_info* info, int32_t variant) {
   if ((kind != 3 && kind != 5) || !bs::info_ok(info) || variant < 0 || variant >= bs::kNV)
     return (size_t)-1;
-  return bs::ws_layout(kind, info->tiles[variant]).total * 8;
+  return bs::ws_layout(kind, info->tiles[variant], info->count, info->nmax).total * 8;
 }
 
 int32_t band_solve_varlen(int32_t kind, const bs_varlen_info* vinfo, const void* table,

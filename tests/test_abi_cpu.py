@@ -85,29 +85,37 @@ def test_workspace_query(bs):
     assert lib.bs_workspace_bytes(bs.OP_SOLVE, 5, 0, 0, batch, batch) == bad
     assert lib.bs_workspace_bytes(bs.OP_SOLVE, 5, 0, n, batch, batch - 1) == bad
     assert lib.bs_workspace_bytes(99, 5, 0, n, batch, batch) == bad
-    # the split kernel needs no workspace; one lane per system needs alpha, beta
+    # one lane per system needs alpha, beta
     bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_LANE)
     try:
         assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch) == 2 * 2048 * lw * 8
         assert bs.workspace_bytes(bs.OP_SOLVE, 3, 2048, batch) == 2048 * lw * 8
     finally:
         bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_AUTO)
-    # split rows: small exchange area (three counters per group + tile maps) only
+    # split rows: four counters per group and the tile maps (more than one
+    # tile per system), then the planes of the sequential redo (alpha, beta,
+    # z for PD; alpha, z for TD), 256-byte aligned
     M, PW, G, TMAX = bs.part_variants(5)[0]
     T = -(-2048 // (M * PW))
     groups = -(-batch // G)
+    up = lambda v: -(-v // 32) * 32
     assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch) == \
-        ((3 * groups + 1) // 2 + 1 + groups * T * G * 21) * 8
-    assert bs.workspace_bytes(bs.OP_SOLVE, 5, M * PW, batch) == 0
+        (up(2 * groups + groups * T * G * 21) + 3 * 2048 * lw) * 8
+    assert bs.workspace_bytes(bs.OP_SOLVE, 3, 2048, batch) == \
+        (up(2 * groups + groups * T * G * 7) + 2 * 2048 * lw) * 8
+    assert bs.workspace_bytes(bs.OP_SOLVE, 5, M * PW, batch) == 3 * M * PW * lw * 8
     # n beyond every single-launch variant: the three-launch path keeps one
-    # record per tile (tile map + first bad row, outer pairs, fold node)
+    # record per tile (tile map + first bad row, outer pairs, fold node),
+    # then the planes of R redo slots (at most 256 and about 2^25 doubles)
     n_long = 40000
     for kind, nb in ((5, 2), (3, 1)):
         rs = 2 * nb + 4 * nb * nb
         T = -(-n_long // (32 * 16))
         recs = -(-batch // 16) * T * 16
+        npl = 3 if kind == 5 else 2
+        R = max(1, min(batch, 256, 2 ** 25 // (npl * n_long)))
         assert bs.workspace_bytes(bs.OP_SOLVE, kind, n_long, batch) == \
-            (recs * (rs + 1) + recs * 2 * nb + batch * T * rs) * 8
+            (up(recs * (rs + 1) + recs * 2 * nb + batch * T * rs) + npl * n_long * R) * 8
     # FP32 storage: the split kernels only (n >= 8), fused solve only
     assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch, bs.BS_F32) == \
         bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch)

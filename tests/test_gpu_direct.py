@@ -127,7 +127,7 @@ def test_split_workspace_reuse_and_graph_replay():
     assert (info.cpu() == 0).all() and rel_err(host(x, batch), xr).max() <= TOL
     M, PW, G, TMAX = bs.part_variants(5)[0]
     groups = -(-batch // G)
-    assert (wsb.view(torch.int32)[: 3 * groups] == 0).all()      # meeting counters reset
+    assert (wsb.view(torch.int32)[: 4 * groups] == 0).all()      # meeting counters reset
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
@@ -333,43 +333,3 @@ def test_interleave_conversions(batch, n, ld, pitch):
     assert np.array_equal(out.cpu().numpy(), wl.interleave(lines, ld, fill=7.0))
     assert np.array_equal(back[:, :n].cpu().numpy(), lines)
     assert (back[:, n:].cpu().numpy() == -3.0).all()
-
-
-
-@pytest.mark.parametrize("variant", [0, 1])
-def test_gave_up_waiting_is_reported(variant):
-    """With no time to wait (BS_OPT_EXCHANGE_WAIT_US = 0) a block that does not
-    find the other blocks of its system already there gives up: the system
-    reports -4, whichever block writes info, and every system that reports
-    0 is solved; the counters are clean again afterwards and the next call
-    with the default wait solves everything."""
-    batch, n = 64, (2048, 4096)[variant]         # four and eight blocks per system
-    ws = wl.dominant_batch(batch, n, kind=5, seed=77)
-    t = to_device(ws, batch)
-    xr, _ = oracle_direct(ws, 5)
-    bs.set_option(bs.OPT_PART_PD_VARIANT, variant)
-    nbytes = bs.workspace_bytes(bs.OP_SOLVE, 5, n, batch)
-    wsb = torch.zeros((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
-    x = torch.empty_like(t["y"])
-    info = torch.empty(batch, dtype=torch.int32, device="cuda")
-    groups = -(-batch // bs.part_variants(5)[variant][2])
-    try:
-        bs.set_option(bs.OPT_EXCHANGE_WAIT_US, 0)
-        gave_up = 0
-        for _ in range(20):
-            bs.solve(diags_of(t), t["y"], x, batch=batch, info=info, workspace=wsb)
-            torch.cuda.synchronize()
-            got = info.cpu().numpy()
-            assert set(np.unique(got)) <= {0, -4}
-            ok = got == 0
-            gave_up += int((~ok).sum())
-            assert rel_err(host(x, batch)[ok], xr[ok]).max(initial=0.0) <= TOL
-            assert (wsb.view(torch.int32)[: 3 * groups] == 0).all()
-        say(f"variant {variant}: {gave_up} of {20 * batch} system solves gave up")
-    finally:
-        bs.set_option(bs.OPT_EXCHANGE_WAIT_US, 1000000)
-        bs.set_option(bs.OPT_PART_PD_VARIANT, 0)
-    bs.solve(diags_of(t), t["y"], x, batch=batch, info=info, workspace=wsb)
-    torch.cuda.synchronize()
-    assert (info.cpu().numpy() == 0).all()
-    assert rel_err(host(x, batch), xr).max() <= TOL

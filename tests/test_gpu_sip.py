@@ -24,6 +24,24 @@ def sip_path(request):
     bs.set_option(bs.OPT_SIP_PATH, 0)
 
 
+def host_relres(ws, x):
+    """||b - A x||_inf / ||b||_inf per system, recomputed on the host."""
+    r = ws["y"] - wl.band_matvec({k: ws[k] for k in ("e", "c", "d", "a", "b")}, x)
+    bn = np.abs(ws["y"]).max(axis=1)
+    return np.abs(r).max(axis=1) / np.where(bn > 0, bn, 1.0)
+
+
+def check_relres(ws, x, rr, info, tol):
+    """The reported relres is the host's ||b - A x|| / ||b|| of the returned x
+    (to rounding), and every converged system is below tol by the host's count."""
+    hr = host_relres(ws, x)
+    ok = info == 0
+    assert (hr[ok] < tol * 1.01).all(), hr[ok].max()
+    bn = np.abs(ws["y"]).max(axis=1)
+    assert (np.abs(hr[ok] - rr[ok]) <= 1e-15 * (1.0 + np.abs(x[ok]).max(axis=1) * 64 /
+                                                 np.where(bn[ok] > 0, bn[ok], 1.0))).all()
+
+
 def run_both(ws, batch, tol, max_iter, sL, sU, x0=None, ld=None):
     t = to_device(ws, batch, ld=ld)
     x0_t = None
@@ -34,8 +52,9 @@ def run_both(ws, batch, tol, max_iter, sL, sU, x0=None, ld=None):
     torch.cuda.synchronize()
     xo, ito, rro, sto = oracle.sip_batch(ws["e"], ws["c"], ws["d"], ws["a"], ws["b"], ws["y"],
                                          tol=tol, max_iter=max_iter, s_L=sL, s_U=sU, x0=x0)
-    return (host(x, batch), it.cpu().numpy(), rr.cpu().numpy(), info.cpu().numpy(),
-            xo, ito, rro, sto)
+    xh, rrh, ih = host(x, batch), rr.cpu().numpy(), info.cpu().numpy()
+    check_relres(ws, xh, rrh, ih, tol)
+    return (xh, it.cpu().numpy(), rrh, ih, xo, ito, rro, sto)
 
 
 @pytest.mark.parametrize("sL,sU", [(-1, -1), (-1, 2), (1, 1), (2, 3), (3, 3), (5, 6), (11, 11)])
@@ -222,23 +241,82 @@ def test_split_rows_graph_replay(sL, sU):
 
 
 def test_exact_substitution_full_sweep_batch():
-    """Algorithm 1 as printed (exact triangular solves, one lane per system)
-    on the 2048 x 2048 sweep batch: with the band's exact ILU(0) it stops
-    after one step; iterations, status and x of a sample against the
-    oracle's run of the same algorithm."""
+    """Algorithm 1 as printed (exact triangular solves; rows split over lanes:
+    row-parallel K x + b and residual, split substitution) on the 2048 x 2048
+    sweep batch: with the band's exact ILU(0) it stops after one step.  Every
+    system bitwise the one-lane kernel's run; iterations, status and x of a
+    sample against the oracle's run of the same algorithm; relres of every
+    system recomputed on the host."""
     pd, _, _ = wl.config1()
     t = to_device(pd, 2048)
     say("exact SIP n=2048 batch=2048")
     x, it, rr, info = bs.sip(diags_of(t), t["y"], tol=1e-12, max_iter=5, batch=2048)
+    bs.set_option(bs.OPT_SIP_PATH, 1)
+    try:
+        xl, itl, rrl, infol = bs.sip(diags_of(t), t["y"], tol=1e-12, max_iter=5, batch=2048)
+    finally:
+        bs.set_option(bs.OPT_SIP_PATH, 0)
     torch.cuda.synchronize()
+    assert torch.equal(x.view(torch.int64), xl.view(torch.int64))
+    assert torch.equal(it, itl) and torch.equal(info, infol)
+    assert torch.equal(rr.view(torch.int64), rrl.view(torch.int64))
     it, rr, info = it.cpu().numpy(), rr.cpu().numpy(), info.cpu().numpy()
     assert (info == 0).all() and (it == 1).all() and (rr < 1e-12).all()
+    check_relres(pd, host(x, 2048), rr, info, 1e-12)
     pick = [0, 1, 1000, 2047]
     sub = {k: v[pick] for k, v in pd.items()}
     xo, ito, rro, sto = oracle.sip_batch(sub["e"], sub["c"], sub["d"], sub["a"], sub["b"],
                                          sub["y"], tol=1e-12, max_iter=5)
     assert (sto == 0).all() and (ito == it[pick]).all()
     assert rel_err(x[:, pick].cpu().numpy().T, xo).max() <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["dominant", "sweep", "ragged"])
+def test_exact_rows_bitwise_one_lane(case):
+    """Algorithm 1 as printed with the rows split over lanes against the
+    one-lane kernel (Algorithm 1 in one persistent launch): bitwise the same
+    x, step counts, residuals and statuses for max_iter of 0 .. 3 and 50,
+    from a non-zero start (so K x matters), with a tolerance below rounding
+    (every step taken, status -1), and with systems whose b = 0, whose
+    ILU(0) pivot is zero, or whose right-hand side is tiny."""
+    if case == "dominant":
+        ws, batch, ld = wl.dominant_batch(64, 1024, seed=61), 64, 64
+    elif case == "sweep":
+        pd, _, _ = wl.config1(N=1024)
+        ws, batch, ld = {k: v[:300] for k, v in pd.items()}, 300, 320
+    else:
+        ws, batch, ld = wl.dominant_batch(37, 3001, seed=62), 37, 40
+        ws["y"][5] = 0.0                    # b = 0: x = 0, no step
+        ws["d"][9, 0] = 0.0                 # ILU(0) pivot u0_0 = 0: no step
+        ws["y"][11] *= 1e-300               # tiny rhs
+    t = to_device(ws, batch, ld=ld)
+    rng = np.random.default_rng(63)
+    x0 = torch.from_numpy(wl.interleave(rng.uniform(-1, 1, (batch, ws["d"].shape[1])),
+                                        ld)).cuda()
+    for tol in (1e-12, 1e-30):
+        for max_iter in (0, 1, 2, 3, 50):
+            out = {}
+            for name, path in (("rows", 0), ("lane", 1)):
+                bs.set_option(bs.OPT_SIP_PATH, path)
+                try:
+                    out[name] = bs.sip(diags_of(t), t["y"], x0.clone(), tol=tol,
+                                       max_iter=max_iter, batch=batch)
+                finally:
+                    bs.set_option(bs.OPT_SIP_PATH, 0)
+            torch.cuda.synchronize()
+            (xr, itr, rrr, ir), (xl, itl, rrl, il) = out["rows"], out["lane"]
+            say(f"exact {case} tol={tol} max_iter={max_iter}: iters "
+                f"{itr.min().item()}..{itr.max().item()} status {sorted(set(ir.cpu().tolist()))}")
+            assert torch.equal(itr, itl) and torch.equal(ir, il)
+            assert torch.equal(rrr.view(torch.int64), rrl.view(torch.int64))
+            assert torch.equal(xr[:, :batch].contiguous().view(torch.int64),
+                               xl[:, :batch].contiguous().view(torch.int64))
+            if tol == 1e-30 and case != "ragged":
+                assert (itr.cpu().numpy() == max_iter).all()
+            if case == "ragged":
+                i = ir.cpu().numpy()
+                assert i[9] == 1 and i[5] == 0 and itr[5].item() == 0
+                assert (xr[:, 5] == 0).all()
 
 
 def test_split_rows_bad_pivot_and_max_iter_zero():
