@@ -216,6 +216,25 @@ int32_t band_solve(int32_t kind, int32_t dtype, int64_t n, int64_t batch,
                    const void* rhs, void* x, int32_t* info, void* workspace,
                    size_t ws_bytes, void* stream);
 
+/* band_solve (factors == NULL) for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the scratch that band_solve takes from `workspace`
+ * comes from a static device array of BS_NOALLOC_SCRATCH_BYTES bytes that
+ * every GPU the library runs on holds from module load until the process
+ * ends.  Same kernels, so x and info are band_solve's to the bit.  The call
+ * allocates nothing; its first call on a device looks the array's address up
+ * (hipGetSymbolAddress) once for that device.  Each call clears the meeting
+ * counters it needs (a fill kernel on `stream`).  BS_EWORKSPACE when the
+ * shape needs more than BS_NOALLOC_SCRATCH_BYTES (bs_workspace_bytes of
+ * BS_OP_SOLVE; e.g. PD FP64 up to about n * batch = 5.3e6 with the default
+ * path); other checks as band_solve.  All calls on one GPU share the one
+ * array: calls that overlap in time on one GPU (on different streams or from
+ * different threads) race, and must be serialised by the caller. */
+#define BS_NOALLOC_SCRATCH_BYTES (128u << 20)
+int32_t band_solve_noalloc(int32_t kind, int32_t dtype, int64_t n, int64_t batch, int64_t ld,
+                           const void* const diags[5], const void* rhs, void* x, int32_t* info,
+                           void* stream);
+
 /* One ADI sweep assembled inside the solver: for every line s (column s of
  * the batch-interleaved [n, ld] input v, the field the sweep starts from),
  * solve (I - tau L(k(v))) w = v for u_t = (k(u) u_x)_x, k(u) = 1 + u^2 (the

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libbandsolve.so")
 
 BS_OK, BS_EINVAL, BS_ELAUNCH, BS_EWORKSPACE, BS_ENODEV = range(5)
 BS_F64, BS_F32 = 0, 1
+NOALLOC_SCRATCH_BYTES = 128 << 20     # BS_NOALLOC_SCRATCH_BYTES of include/bandsolve.h
 OP_FACTOR, OP_SOLVE, OP_SOLVE_FACTORED, OP_MNPDM, OP_SIP, OP_REFINE, OP_ADI = range(7)
 
 EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "bs_set_option",
@@ -30,7 +31,7 @@ EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "bs_set_option"
             "bs_varlen_variants",
             "bs_varlen_variant_shape", "bs_varlen_layout", "bs_varlen_workspace_bytes",
             "band_solve_varlen", "bs_varlen_tune", "bs_pack_interleave", "bs_unpack_interleave",
-            "bs_stream_probe")
+            "bs_stream_probe", "band_solve_noalloc")
 OPT_DIRECT_PATH, OPT_PART_PD_VARIANT, OPT_PART_TD_VARIANT, OPT_SIP_PATH, OPT_EXCHANGE_WAIT_US = \
     range(5)
 PATH_AUTO, PATH_LANE, PATH_PART = range(3)
@@ -90,6 +91,7 @@ def load():
         "bs_varlen_tune": (i32, [i32, vip, vp, vp5, vp, vp, vp, vp, sz, i32, vp, vp, vp]),
         "bs_stream_probe": (i32, [i64, i32, ctypes.c_void_p * 6, vp, vp]),
         "bs_pack_interleave": (i32, [i64, i64, vp, i64, vp, i64, vp]),
+        "band_solve_noalloc": (i32, [i32, i32, i64, i64, i64, vp5, vp, vp, vp, vp]),
         "bs_unpack_interleave": (i32, [i64, i64, vp, i64, vp, i64, vp]),
     })
     for name, (res, args) in sig.items():
@@ -261,6 +263,21 @@ def solve(diags, rhs, x=None, *, kind=None, batch=None, factors=None, info=None,
                         0 if workspace is None else workspace.numel() * workspace.element_size(),
                         _stream(stream))
     _raise(st, "band_solve")
+    return x, info
+
+
+def solve_noalloc(diags, rhs, x=None, *, kind=None, batch=None, info=None, stream=None):
+    """band_solve_noalloc: the fused solve with the library's static scratch
+    (no workspace).  Returns (x, info)."""
+    lib = load()
+    kind, n, ld, batch, dtype = _prep(diags, rhs, kind, batch)
+    x = torch.empty_like(rhs) if x is None else x
+    _check2d(x, "x", n, dtype)
+    info = torch.empty(batch, dtype=torch.int32, device=rhs.device) if info is None else info
+    st = lib.band_solve_noalloc(kind, _dtype_code(dtype), n, batch, ld,
+                                lib.VP5(*[_ptr(t) for t in diags]), _ptr(rhs), _ptr(x),
+                                _ptr(info), _stream(stream))
+    _raise(st, "band_solve_noalloc")
     return x, info
 
 

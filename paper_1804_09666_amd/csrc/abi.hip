@@ -99,6 +99,12 @@ size_t direct_ws_bytes(int kind, int dtype, int64_t n, int64_t batch, int64_t ld
   }
 }
 
+size_t direct_counter_bytes(int kind, int dtype, int64_t n, int64_t batch, int64_t ld) {
+  int idx;
+  return route(kind, dtype, n, ld, &idx) == Route::kPart ? part_counter_bytes(kind, idx, n, batch)
+                                                         : 0;
+}
+
 hipError_t launch_direct(int kind, int dtype, int64_t n, int64_t batch, int64_t ld,
                          const void* const dg[5], const void* y, void* x, int32_t* info,
                          void* ws, hipStream_t st, const int32_t* skip) {

@@ -76,6 +76,9 @@ bool part_variant_shape(int kind, int idx, int out[4]);
 // that does; -1 if none.
 int part_pick(int kind, int idx, int64_t n, int64_t ld, int dtype);
 size_t part_workspace_bytes(int kind, int idx, int64_t n, int64_t batch);
+// Leading bytes of that workspace that must be zero before a launch (the
+// meeting counters; 0 when a system fits one tile).
+size_t part_counter_bytes(int kind, int idx, int64_t n, int64_t batch);
 // skip (nullable device flag): when *skip != 0 at launch the kernels return
 // at once (a refinement loop that has converged).
 hipError_t launch_part(int kind, int idx, int dtype, int64_t n, int64_t batch, int64_t ld,
@@ -117,6 +120,8 @@ hipError_t launch_direct(int kind, int dtype, int64_t n, int64_t batch, int64_t 
                          void* ws, hipStream_t st, const int32_t* skip = nullptr);
 // false if no kernel handles this (FP32 storage needs the split or long path).
 bool direct_supported(int kind, int dtype, int64_t n, int64_t ld);
+// Leading bytes of the fused solve's workspace that must be zero at launch.
+size_t direct_counter_bytes(int kind, int dtype, int64_t n, int64_t batch, int64_t ld);
 
 // ---- SIP (sip_lane.hip) --------------------------------------------------
 hipError_t launch_sip_lane(int64_t n, int64_t batch, int64_t ld, Diags A,

@@ -681,6 +681,13 @@ int part_pick(int kind, int idx, int64_t n, int64_t ld, int dtype) {
   return -1;
 }
 
+size_t part_counter_bytes(int kind, int idx, int64_t n, int64_t batch) {
+  const Variant* v = find_variant(kind, idx);
+  if (!v) return 0;
+  const int64_t RT = (int64_t)v->M * v->PW;
+  return (n + RT - 1) / RT > 1 ? (size_t)part_ws(kind, n, batch, v->M, v->PW, v->G).xch * 8 : 0;
+}
+
 size_t part_workspace_bytes(int kind, int idx, int64_t n, int64_t batch) {
   const Variant* v = find_variant(kind, idx);
   if (!v) return 0;

@@ -241,6 +241,29 @@ def test_invalid_arguments_rejected_on_host(bs):
 
 
 @pytest.mark.skipif(__import__("torch").cuda.is_available(), reason="needs a machine without GPU")
+def test_noalloc_host_checks(bs):
+    """band_solve_noalloc: bad arguments and shapes whose scratch exceeds the
+    static array are refused on the host; a valid call without a GPU reports
+    BS_ENODEV; the array's size in the header matches the binding."""
+    lib = bs.load()
+    text = open(HEADER).read()
+    assert "#define BS_NOALLOC_SCRATCH_BYTES (128u << 20)" in text
+    assert bs.NOALLOC_SCRATCH_BYTES == 128 << 20
+    arr = ctypes.create_string_buffer(64)
+    p = ctypes.c_void_p(ctypes.addressof(arr))
+    d5 = lib.VP5(p, p, p, p, p)
+    info = ctypes.c_void_p(ctypes.addressof(arr))
+    f = lib.band_solve_noalloc
+    assert f(5, 0, 0, 4, 4, d5, p, p, info, None) == bs.BS_EINVAL        # n < 1
+    assert f(4, 0, 100, 4, 4, d5, p, p, info, None) == bs.BS_EINVAL      # kind
+    assert f(5, 0, 100, 4, 3, d5, p, p, info, None) == bs.BS_EINVAL      # ld < batch
+    assert f(5, 0, 100, 4, 4, d5, None, p, info, None) == bs.BS_EINVAL   # rhs
+    assert bs.workspace_bytes(bs.OP_SOLVE, 5, 4096, 4096) > bs.NOALLOC_SCRATCH_BYTES
+    assert f(5, 0, 4096, 4096, 4096, d5, p, p, info, None) == bs.BS_EWORKSPACE
+    assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, 2048) <= bs.NOALLOC_SCRATCH_BYTES
+    assert f(5, 0, 2048, 2048, 2048, d5, p, p, info, None) == bs.BS_ENODEV
+
+
 def test_valid_call_without_device_reports_enodev(bs):
     lib = bs.load()
     d5 = lib.VP5(*[_fake(k) for k in range(5)])
