@@ -95,6 +95,8 @@ def load():
         "bs_unpack_interleave": (i32, [i64, i64, vp, i64, vp, i64, vp]),
     })
     for name, (res, args) in sig.items():
+        if not hasattr(lib, name):
+            raise RuntimeError(f"{LIB_PATH} does not export {name}; rebuild it")
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args

@@ -103,12 +103,19 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
   if (tid == 0) s_timeout = 0;
 
   // ---- 1. load the chunk and eliminate it locally -------------------------
+  double p[M], v[NB][M], w[NB][M];
+  int bad;
+  bool list_bad = false;
+  if constexpr (!SPARSE && !ASM) {
+    // loads streamed under the forward elimination
+    stream_eliminate<KIND, M, KIND == 5 ? 10 : 15, TIO>(n, ld, s, live, r0, E, C, D, A, B, Y, p,
+                                                        v, w, bad);
+  } else {
   double c[M], d[M], a[M], y[M], e[M], b[M];
   if constexpr (ASM)
     assemble_chunk<KIND, M>(n, ld, s, live, r0, Y, rcoef, e, c, d, a, b, y);
   else
     load_chunk<KIND, M, TIO, !SPARSE>(n, ld, s, live, r0, 0, E, C, D, A, B, Y, e, c, d, a, b, y);
-  bool list_bad = false;
   if constexpr (SPARSE) {
     // every lane of the system checks the whole list (strictly ascending
     // rows in [0, n), then only -1) and picks the entries of its rows
@@ -139,9 +146,8 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
       }
     }
   }
-  double p[M], v[NB][M], w[NB][M];
-  int bad;
   eliminate_chunk<KIND, M>(e, c, d, a, b, y, p, v, w, bad);
+  }
   Map<NB> mp = chunk_map<NB, M>(p, v, w);
   __syncthreads();  // s_bad initialised
   if (bad < M && r0 + bad < n) atomicMin(&s_bad[g], (int)(r0 + bad + 1));

@@ -195,57 +195,60 @@ __device__ inline void stg(TIO* __restrict__ base, uint32_t byte_off, double v) 
 // x_R = (x_M, x_{M+1}) (b_{M-2} of row M-2, a_{M-1} and b_{M-1} of row M-1)
 // as right-hand sides.  On return p, v0, v1, w0, w1 hold U^{-1} L^{-1} of
 // y and of the coupling columns; `bad` is the first local row with a bad
-// pivot (M if none).
-template <int M>
-__device__ inline void chunk_pd(const double (&e)[M], const double (&c)[M],
-                                const double (&d)[M], const double (&a)[M],
-                                const double (&b)[M], const double (&y)[M],
-                                double (&p)[M], double (&v0)[M], double (&v1)[M],
-                                double (&w0)[M], double (&w1)[M], int& bad) {
+// pivot (M if none).  src(r, e, c, d, a, b, y) gives row r; pre(r) runs at
+// the start of the forward step of row r (a streaming caller issues the
+// loads of a later row there).
+template <int M, typename Src, typename Pre>
+__device__ inline void chunk_pd_rows(Src&& src, Pre&& pre, double (&p)[M], double (&v0)[M],
+                                     double (&v1)[M], double (&w0)[M], double (&w1)[M],
+                                     int& bad) {
   double al[M], be[M];
   double fm2 = 0.0;  // L^{-1} of the x_M column at row M-2
   bad = M;
 #pragma unroll
   for (int r = 0; r < M; ++r) {
+    pre(r);
+    double e, c, d, a, b, y;
+    src(r, e, c, d, a, b, y);
     double ga, mu;
     if (r == 0) {
       ga = 0.0;
-      mu = d[0];
+      mu = d;
     } else if (r == 1) {
-      ga = c[1];
-      mu = fma(-al[0], ga, d[1]);
+      ga = c;
+      mu = fma(-al[0], ga, d);
     } else {
-      ga = fma(-al[r - 2], e[r], c[r]);
-      mu = fma(-al[r - 1], ga, fma(-be[r - 2], e[r], d[r]));
+      ga = fma(-al[r - 2], e, c);
+      mu = fma(-al[r - 1], ga, fma(-be[r - 2], e, d));
     }
     // the row's magnitude from its inner three entries (measured: adding the
     // outer two costs 5 us per sweep batch, the scale only sets the guard)
-    if (bad == M && bad_pivot(mu, fabs(c[r]) + fabs(d[r]) + fabs(a[r]))) bad = r;
+    if (bad == M && bad_pivot(mu, fabs(c) + fabs(d) + fabs(a))) bad = r;
     const double rc = recip(mu);  // off the IEEE division's longer chain
     if (r == 0)
-      al[0] = a[0] * rc;
+      al[0] = a * rc;
     else if (r <= M - 2)
-      al[r] = fma(-be[r - 1], ga, a[r]) * rc;
+      al[r] = fma(-be[r - 1], ga, a) * rc;
     else
       al[r] = 0.0;
-    be[r] = (r <= M - 3) ? b[r] * rc : 0.0;
+    be[r] = (r <= M - 3) ? b * rc : 0.0;
     if (r == 0) {
-      p[0] = y[0] * rc;
-      v0[0] = e[0] * rc;
-      v1[0] = c[0] * rc;
+      p[0] = y * rc;
+      v0[0] = e * rc;
+      v1[0] = c * rc;
     } else if (r == 1) {
-      p[1] = fma(-ga, p[0], y[1]) * rc;
+      p[1] = fma(-ga, p[0], y) * rc;
       v0[1] = (-ga * v0[0]) * rc;
-      v1[1] = fma(-ga, v1[0], e[1]) * rc;
+      v1[1] = fma(-ga, v1[0], e) * rc;
     } else {
-      p[r] = fma(-ga, p[r - 1], fma(-e[r], p[r - 2], y[r])) * rc;
-      v0[r] = fma(-ga, v0[r - 1], -e[r] * v0[r - 2]) * rc;
-      v1[r] = fma(-ga, v1[r - 1], -e[r] * v1[r - 2]) * rc;
+      p[r] = fma(-ga, p[r - 1], fma(-e, p[r - 2], y)) * rc;
+      v0[r] = fma(-ga, v0[r - 1], -e * v0[r - 2]) * rc;
+      v1[r] = fma(-ga, v1[r - 1], -e * v1[r - 2]) * rc;
     }
-    if (r == M - 2) fm2 = b[M - 2] * rc;
+    if (r == M - 2) fm2 = b * rc;
     if (r == M - 1) {
-      w0[M - 1] = fma(-ga, fm2, a[M - 1]) * rc;
-      w1[M - 1] = b[M - 1] * rc;
+      w0[M - 1] = fma(-ga, fm2, a) * rc;
+      w1[M - 1] = b * rc;
     }
   }
   w0[M - 2] = fma(-al[M - 2], w0[M - 1], fm2);
@@ -264,28 +267,30 @@ __device__ inline void chunk_pd(const double (&e)[M], const double (&c)[M],
 }
 
 // Chunk of a tridiagonal system: local Thomas with the couplings to x_{-1}
-// (c_0 of row 0) and x_M (a_{M-1} of row M-1) as right-hand sides.
-template <int M>
-__device__ inline void chunk_td(const double (&c)[M], const double (&d)[M],
-                                const double (&a)[M], const double (&y)[M],
-                                double (&p)[M], double (&v0)[M], double (&w0)[M],
-                                int& bad) {
+// (c_0 of row 0) and x_M (a_{M-1} of row M-1) as right-hand sides.  src and
+// pre as for chunk_pd_rows (e and b unused).
+template <int M, typename Src, typename Pre>
+__device__ inline void chunk_td_rows(Src&& src, Pre&& pre, double (&p)[M], double (&v0)[M],
+                                     double (&w0)[M], int& bad) {
   double al[M];
   bad = M;
 #pragma unroll
   for (int r = 0; r < M; ++r) {
-    const double mu = (r == 0) ? d[0] : fma(-al[r - 1], c[r], d[r]);
-    if (bad == M && bad_pivot(mu, fabs(c[r]) + fabs(d[r]) + fabs(a[r]))) bad = r;
+    pre(r);
+    double e, c, d, a, b, y;
+    src(r, e, c, d, a, b, y);
+    const double mu = (r == 0) ? d : fma(-al[r - 1], c, d);
+    if (bad == M && bad_pivot(mu, fabs(c) + fabs(d) + fabs(a))) bad = r;
     const double rc = recip(mu);  // off the IEEE division's longer chain
-    al[r] = (r <= M - 2) ? a[r] * rc : 0.0;
+    al[r] = (r <= M - 2) ? a * rc : 0.0;
     if (r == 0) {
-      p[0] = y[0] * rc;
-      v0[0] = c[0] * rc;
+      p[0] = y * rc;
+      v0[0] = c * rc;
     } else {
-      p[r] = fma(-c[r], p[r - 1], y[r]) * rc;
-      v0[r] = (-c[r] * v0[r - 1]) * rc;
+      p[r] = fma(-c, p[r - 1], y) * rc;
+      v0[r] = (-c * v0[r - 1]) * rc;
     }
-    if (r == M - 1) w0[M - 1] = a[M - 1] * rc;
+    if (r == M - 1) w0[M - 1] = a * rc;
   }
 #pragma unroll
   for (int r = M - 2; r >= 0; --r) {
@@ -293,6 +298,112 @@ __device__ inline void chunk_td(const double (&c)[M], const double (&d)[M],
     v0[r] = fma(-al[r], v0[r + 1], v0[r]);
     w0[r] = -al[r] * w0[r + 1];
   }
+}
+
+template <int M>
+__device__ inline void chunk_pd(const double (&e)[M], const double (&c)[M],
+                                const double (&d)[M], const double (&a)[M],
+                                const double (&b)[M], const double (&y)[M],
+                                double (&p)[M], double (&v0)[M], double (&v1)[M],
+                                double (&w0)[M], double (&w1)[M], int& bad) {
+  chunk_pd_rows<M>(
+      [&](int r, double& er, double& cr, double& dr, double& ar, double& br, double& yr) {
+        er = e[r];
+        cr = c[r];
+        dr = d[r];
+        ar = a[r];
+        br = b[r];
+        yr = y[r];
+      },
+      [](int) {}, p, v0, v1, w0, w1, bad);
+}
+
+template <int M>
+__device__ inline void chunk_td(const double (&c)[M], const double (&d)[M],
+                                const double (&a)[M], const double (&y)[M],
+                                double (&p)[M], double (&v0)[M], double (&w0)[M],
+                                int& bad) {
+  chunk_td_rows<M>(
+      [&](int r, double& er, double& cr, double& dr, double& ar, double& br, double& yr) {
+        er = br = 0.0;
+        cr = c[r];
+        dr = d[r];
+        ar = a[r];
+        yr = y[r];
+      },
+      [](int) {}, p, v0, w0, bad);
+}
+
+// ---- streamed chunk: loads interleaved with the forward elimination -----
+// The rows come through raw buffer loads: one 32-bit byte offset per row and
+// array on a buffer resource whose range is the array, so a slot outside
+// the matrix (a corner slot, a row past n, a padding system) is an offset
+// past the range and reads as zero without a branch.  The loads of row
+// r + D are issued at the start of row r's forward step, so the elimination
+// of the rows that have arrived runs while later rows are in flight (a wave
+// holds at most 63 loads: D = 10 rows of six arrays).
+constexpr uint32_t kOOB = 0xFFFFFFF8u;  // beyond any array (n ld bytes < 2^32 - ld)
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename TIO>
+__device__ inline __amdgpu_buffer_rsrc_t rsrc_of(const TIO* p, uint32_t bytes) {
+  // raw buffer, byte offsets, range checked against `bytes`
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<TIO*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename TIO>
+__device__ inline TIO bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(TIO) == 8)
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 2));
+  else
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 2));
+}
+
+template <int KIND, int M, int D, typename TIO>
+__device__ inline void stream_eliminate(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
+                                        const TIO* __restrict__ E, const TIO* __restrict__ C,
+                                        const TIO* __restrict__ Dg, const TIO* __restrict__ A,
+                                        const TIO* __restrict__ B, const TIO* __restrict__ Y,
+                                        double (&p)[M], double (&v)[KIND == 5 ? 2 : 1][M],
+                                        double (&w)[KIND == 5 ? 2 : 1][M], int& bad) {
+  const uint32_t bytes = (uint32_t)(n * ld * (int64_t)sizeof(TIO));
+  const uint32_t row_bytes = (uint32_t)(ld * sizeof(TIO));
+  const uint32_t off0 = (uint32_t)((r0 * ld + s) * (int64_t)sizeof(TIO));
+  __amdgpu_buffer_rsrc_t rE = rsrc_of(KIND == 5 ? E : C, bytes), rC = rsrc_of(C, bytes),
+                         rD = rsrc_of(Dg, bytes), rA = rsrc_of(A, bytes),
+                         rB = rsrc_of(KIND == 5 ? B : C, bytes), rY = rsrc_of(Y, bytes);
+  TIO xe[M], xc[M], xd[M], xa[M], xb[M], xy[M];
+  auto issue = [&](int q) {
+    const int64_t i = r0 + q;
+    const uint32_t o = (live && i < n) ? off0 + (uint32_t)q * row_bytes : kOOB;
+    xd[q] = bload<TIO>(rD, o);
+    xy[q] = bload<TIO>(rY, o);
+    xc[q] = bload<TIO>(rC, i >= 1 ? o : kOOB);
+    xa[q] = bload<TIO>(rA, i <= n - 2 ? o : kOOB);
+    if (KIND == 5) {
+      xe[q] = bload<TIO>(rE, i >= 2 ? o : kOOB);
+      xb[q] = bload<TIO>(rB, i <= n - 3 ? o : kOOB);
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < D && q < M; ++q) issue(q);
+  auto pre = [&](int r) {
+    if (r + D < M) issue(r + D);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads of row r + D here
+  };
+  auto src = [&](int r, double& er, double& cr, double& dr, double& ar, double& br, double& yr) {
+    const bool in = live && r0 + r < n;
+    er = KIND == 5 ? (double)xe[r] : 0.0;
+    cr = (double)xc[r];
+    dr = in ? (double)xd[r] : 1.0;  // identity rows past n
+    ar = (double)xa[r];
+    br = KIND == 5 ? (double)xb[r] : 0.0;
+    yr = (double)xy[r];
+  };
+  if constexpr (KIND == 5)
+    chunk_pd_rows<M>(src, pre, p, v[0], v[1], w[0], w[1], bad);
+  else
+    chunk_td_rows<M>(src, pre, p, v[0], w[0], bad);
 }
 
 // Binary tree over NL leaf maps held by lanes (leaf, g), leaf in [0, NL);
