@@ -106,47 +106,49 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
   double p[M], v[NB][M], w[NB][M];
   int bad;
   bool list_bad = false;
-  if constexpr (!SPARSE && !ASM) {
-    // loads streamed under the forward elimination
-    stream_eliminate<KIND, M, KIND == 5 ? 10 : 15, TIO>(n, ld, s, live, r0, E, C, D, A, B, Y, p,
-                                                        v, w, bad);
+  // rows in flight: at most 63 loads per wave; at two waves per SIMD the
+  // register budget halves
+  constexpr int DPF = WPE == 1 ? (KIND == 5 && !SPARSE ? 10 : 15) : (KIND == 5 ? 6 : 9);
+  if constexpr (ASM) {
+    stream_assemble<KIND, M>(n, ld, s, live, r0, reinterpret_cast<const double*>(Y), rcoef, p,
+                             v, w, bad);
   } else {
-  double c[M], d[M], a[M], y[M], e[M], b[M];
-  if constexpr (ASM)
-    assemble_chunk<KIND, M>(n, ld, s, live, r0, Y, rcoef, e, c, d, a, b, y);
-  else
-    load_chunk<KIND, M, TIO, !SPARSE>(n, ld, s, live, r0, 0, E, C, D, A, B, Y, e, c, d, a, b, y);
-  if constexpr (SPARSE) {
-    // every lane of the system checks the whole list (strictly ascending
-    // rows in [0, n), then only -1) and picks the entries of its rows
-    int64_t prev = -1;
-    bool ended = false;
-    for (int k = 0; k < ol.kmax; ++k) {
-      const int64_t lo = (int64_t)k * ld + s;
-      const int32_t rr = live ? ol.row[lo] : -1;
-      if (rr < 0) {
-        ended = true;
-        continue;
-      }
-      if (ended || rr >= n || rr <= prev) {
-        list_bad = true;
-        continue;
-      }
-      prev = rr;
-      const int64_t loc = rr - r0;
-      if (loc >= 0 && loc < M) {
-        const double ev = (rr >= 2) ? ol.e[lo] : 0.0;
-        const double bv = (rr <= n - 3) ? ol.b[lo] : 0.0;
+    double eo[M], bo[M];
 #pragma unroll
-        for (int r = 0; r < M; ++r)
-          if (loc == r) {
-            e[r] = ev;
-            b[r] = bv;
-          }
+    for (int r = 0; r < M; ++r) eo[r] = bo[r] = 0.0;
+    if constexpr (SPARSE) {
+      // every lane of the system checks the whole list (strictly ascending
+      // rows in [0, n), then only -1) and picks the entries of its rows
+      int64_t prev = -1;
+      bool ended = false;
+      for (int k = 0; k < ol.kmax; ++k) {
+        const int64_t lo = (int64_t)k * ld + s;
+        const int32_t rr = live ? ol.row[lo] : -1;
+        if (rr < 0) {
+          ended = true;
+          continue;
+        }
+        if (ended || rr >= n || rr <= prev) {
+          list_bad = true;
+          continue;
+        }
+        prev = rr;
+        const int64_t loc = rr - r0;
+        if (loc >= 0 && loc < M) {
+          const double ev = (rr >= 2) ? ol.e[lo] : 0.0;
+          const double bv = (rr <= n - 3) ? ol.b[lo] : 0.0;
+#pragma unroll
+          for (int r = 0; r < M; ++r)
+            if (loc == r) {
+              eo[r] = ev;
+              bo[r] = bv;
+            }
+        }
       }
     }
-  }
-  eliminate_chunk<KIND, M>(e, c, d, a, b, y, p, v, w, bad);
+    // loads streamed under the forward elimination
+    stream_eliminate<KIND, M, DPF, TIO, SPARSE>(n, ld, s, live, r0, E, C, D, A, B, Y, eo, bo, p,
+                                                v, w, bad);
   }
   Map<NB> mp = chunk_map<NB, M>(p, v, w);
   __syncthreads();  // s_bad initialised

@@ -334,78 +334,6 @@ __device__ inline void chunk_td(const double (&c)[M], const double (&d)[M],
       [](int) {}, p, v0, w0, bad);
 }
 
-// ---- streamed chunk: loads interleaved with the forward elimination -----
-// The rows come through raw buffer loads: one 32-bit byte offset per row and
-// array on a buffer resource whose range is the array, so a slot outside
-// the matrix (a corner slot, a row past n, a padding system) is an offset
-// past the range and reads as zero without a branch.  The loads of row
-// r + D are issued at the start of row r's forward step, so the elimination
-// of the rows that have arrived runs while later rows are in flight (a wave
-// holds at most 63 loads: D = 10 rows of six arrays).
-constexpr uint32_t kOOB = 0xFFFFFFF8u;  // beyond any array (n ld bytes < 2^32 - ld)
-
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-
-template <typename TIO>
-__device__ inline __amdgpu_buffer_rsrc_t rsrc_of(const TIO* p, uint32_t bytes) {
-  // raw buffer, byte offsets, range checked against `bytes`
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<TIO*>(p), (short)0, (int)bytes, 0x00020000);
-}
-template <typename TIO>
-__device__ inline TIO bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
-  if constexpr (sizeof(TIO) == 8)
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 2));
-  else
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 2));
-}
-
-template <int KIND, int M, int D, typename TIO>
-__device__ inline void stream_eliminate(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
-                                        const TIO* __restrict__ E, const TIO* __restrict__ C,
-                                        const TIO* __restrict__ Dg, const TIO* __restrict__ A,
-                                        const TIO* __restrict__ B, const TIO* __restrict__ Y,
-                                        double (&p)[M], double (&v)[KIND == 5 ? 2 : 1][M],
-                                        double (&w)[KIND == 5 ? 2 : 1][M], int& bad) {
-  const uint32_t bytes = (uint32_t)(n * ld * (int64_t)sizeof(TIO));
-  const uint32_t row_bytes = (uint32_t)(ld * sizeof(TIO));
-  const uint32_t off0 = (uint32_t)((r0 * ld + s) * (int64_t)sizeof(TIO));
-  __amdgpu_buffer_rsrc_t rE = rsrc_of(KIND == 5 ? E : C, bytes), rC = rsrc_of(C, bytes),
-                         rD = rsrc_of(Dg, bytes), rA = rsrc_of(A, bytes),
-                         rB = rsrc_of(KIND == 5 ? B : C, bytes), rY = rsrc_of(Y, bytes);
-  TIO xe[M], xc[M], xd[M], xa[M], xb[M], xy[M];
-  auto issue = [&](int q) {
-    const int64_t i = r0 + q;
-    const uint32_t o = (live && i < n) ? off0 + (uint32_t)q * row_bytes : kOOB;
-    xd[q] = bload<TIO>(rD, o);
-    xy[q] = bload<TIO>(rY, o);
-    xc[q] = bload<TIO>(rC, i >= 1 ? o : kOOB);
-    xa[q] = bload<TIO>(rA, i <= n - 2 ? o : kOOB);
-    if (KIND == 5) {
-      xe[q] = bload<TIO>(rE, i >= 2 ? o : kOOB);
-      xb[q] = bload<TIO>(rB, i <= n - 3 ? o : kOOB);
-    }
-  };
-#pragma unroll
-  for (int q = 0; q < D && q < M; ++q) issue(q);
-  auto pre = [&](int r) {
-    if (r + D < M) issue(r + D);
-    __builtin_amdgcn_sched_barrier(0);  // keep the loads of row r + D here
-  };
-  auto src = [&](int r, double& er, double& cr, double& dr, double& ar, double& br, double& yr) {
-    const bool in = live && r0 + r < n;
-    er = KIND == 5 ? (double)xe[r] : 0.0;
-    cr = (double)xc[r];
-    dr = in ? (double)xd[r] : 1.0;  // identity rows past n
-    ar = (double)xa[r];
-    br = KIND == 5 ? (double)xb[r] : 0.0;
-    yr = (double)xy[r];
-  };
-  if constexpr (KIND == 5)
-    chunk_pd_rows<M>(src, pre, p, v[0], v[1], w[0], w[1], bad);
-  else
-    chunk_td_rows<M>(src, pre, p, v[0], w[0], bad);
-}
-
 // Binary tree over NL leaf maps held by lanes (leaf, g), leaf in [0, NL);
 // lanes with leaf >= NL only take part in the barriers.  Each internal node
 // owns one record slot in s_node: the right child parks its map there, the
@@ -754,6 +682,118 @@ __device__ inline void write_chunk(int64_t n, int64_t ld, int64_t s, bool live, 
     for (int k = 0; k < NB; ++k) xv = fma(-v[k][r], xl[k], fma(-w[k][r], xr[k], xv));
     if (live && i < n) stg(X, off0 + (uint32_t)r * row_bytes, xv);
   }
+}
+
+// ---- streamed chunk: loads interleaved with the forward elimination -----
+// The rows come through raw buffer loads: one 32-bit byte offset per row and
+// array on a buffer resource whose range is the array, so a slot outside
+// the matrix (a corner slot, a row past n, a padding system) is an offset
+// past the range and reads as zero without a branch.  The loads of row
+// r + D are issued at the start of row r's forward step, so the elimination
+// of the rows that have arrived runs while later rows are in flight (a wave
+// holds at most 63 loads: D = 10 rows of six arrays).
+constexpr uint32_t kOOB = 0xFFFFFFF8u;  // beyond any array (n ld bytes < 2^32 - ld)
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+template <typename TIO>
+__device__ inline __amdgpu_buffer_rsrc_t rsrc_of(const TIO* p, uint32_t bytes) {
+  // raw buffer, byte offsets, range checked against `bytes`
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<TIO*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename TIO>
+__device__ inline TIO bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  if constexpr (sizeof(TIO) == 8)
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 2));
+  else
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 2));
+}
+
+// LIST: the outer diagonals e, b are not loaded but taken from eo, bo (an
+// MNPDM list scattered into registers); only c, d, a, y are streamed.
+template <int KIND, int M, int D, typename TIO, bool LIST = false>
+__device__ inline void stream_eliminate(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
+                                        const TIO* __restrict__ E, const TIO* __restrict__ C,
+                                        const TIO* __restrict__ Dg, const TIO* __restrict__ A,
+                                        const TIO* __restrict__ B, const TIO* __restrict__ Y,
+                                        const double (&eo)[M], const double (&bo)[M],
+                                        double (&p)[M], double (&v)[KIND == 5 ? 2 : 1][M],
+                                        double (&w)[KIND == 5 ? 2 : 1][M], int& bad) {
+  constexpr bool OUTER = KIND == 5 && !LIST;  // e, b streamed
+  const uint32_t bytes = (uint32_t)(n * ld * (int64_t)sizeof(TIO));
+  const uint32_t row_bytes = (uint32_t)(ld * sizeof(TIO));
+  const uint32_t off0 = (uint32_t)((r0 * ld + s) * (int64_t)sizeof(TIO));
+  __amdgpu_buffer_rsrc_t rE = rsrc_of(OUTER ? E : C, bytes), rC = rsrc_of(C, bytes),
+                         rD = rsrc_of(Dg, bytes), rA = rsrc_of(A, bytes),
+                         rB = rsrc_of(OUTER ? B : C, bytes), rY = rsrc_of(Y, bytes);
+  TIO xe[M], xc[M], xd[M], xa[M], xb[M], xy[M];
+  auto issue = [&](int q) {
+    const int64_t i = r0 + q;
+    const uint32_t o = (live && i < n) ? off0 + (uint32_t)q * row_bytes : kOOB;
+    xd[q] = bload<TIO>(rD, o);
+    xy[q] = bload<TIO>(rY, o);
+    xc[q] = bload<TIO>(rC, i >= 1 ? o : kOOB);
+    xa[q] = bload<TIO>(rA, i <= n - 2 ? o : kOOB);
+    if (OUTER) {
+      xe[q] = bload<TIO>(rE, i >= 2 ? o : kOOB);
+      xb[q] = bload<TIO>(rB, i <= n - 3 ? o : kOOB);
+    }
+  };
+#pragma unroll
+  for (int q = 0; q < D && q < M; ++q) issue(q);
+  auto pre = [&](int r) {
+    if (r + D < M) issue(r + D);
+    __builtin_amdgcn_sched_barrier(0);  // keep the loads of row r + D here
+  };
+  auto src = [&](int r, double& er, double& cr, double& dr, double& ar, double& br, double& yr) {
+    const bool in = live && r0 + r < n;
+    er = OUTER ? (double)xe[r] : (LIST ? eo[r] : 0.0);
+    cr = (double)xc[r];
+    dr = in ? (double)xd[r] : 1.0;  // identity rows past n
+    ar = (double)xa[r];
+    br = OUTER ? (double)xb[r] : (LIST ? bo[r] : 0.0);
+    yr = (double)xy[r];
+  };
+  if constexpr (KIND == 5)
+    chunk_pd_rows<M>(src, pre, p, v[0], v[1], w[0], w[1], bad);
+  else
+    chunk_td_rows<M>(src, pre, p, v[0], w[0], bad);
+}
+
+// The ADI sweep's rows assembled from v (assemble_row) as v arrives: all
+// M + 2 values of v the chunk needs are requested at once (out-of-range rows
+// read zero), and row r is assembled and eliminated once v_{r+1} is in.
+template <int KIND, int M>
+__device__ inline void stream_assemble(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
+                                       const double* __restrict__ V, double rcoef, double (&p)[M],
+                                       double (&v)[KIND == 5 ? 2 : 1][M],
+                                       double (&w)[KIND == 5 ? 2 : 1][M], int& bad) {
+  const uint32_t bytes = (uint32_t)(n * ld * 8);
+  const uint32_t row_bytes = (uint32_t)(ld * 8);
+  __amdgpu_buffer_rsrc_t rV = rsrc_of(V, bytes);
+  double vv[M + 2];  // v at rows r0 - 1 .. r0 + M
+#pragma unroll
+  for (int q = 0; q < M + 2; ++q) {
+    const int64_t i = r0 - 1 + q;
+    vv[q] = bload<double>(rV, (live && i >= 0 && i < n)
+                                  ? (uint32_t)((i * ld + s) * 8)
+                                  : kOOB);
+  }
+  (void)row_bytes;
+  __builtin_amdgcn_sched_barrier(0);
+  auto src = [&](int r, double& er, double& cr, double& dr, double& ar, double& br, double& yr) {
+    const int64_t i = r0 + r;
+    if (live && i < n) {
+      assemble_row<KIND>(i, n, vv[r], vv[r + 1], vv[r + 2], rcoef, er, cr, dr, ar, br, yr);
+    } else {  // identity rows past n
+      er = cr = ar = br = yr = 0.0;
+      dr = 1.0;
+    }
+  };
+  if constexpr (KIND == 5)
+    chunk_pd_rows<M>(src, [](int) {}, p, v[0], v[1], w[0], w[1], bad);
+  else
+    chunk_td_rows<M>(src, [](int) {}, p, v[0], w[0], bad);
 }
 
 }  // namespace split
