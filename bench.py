@@ -501,7 +501,7 @@ def varlen_rows(reps=5):
     }, got, samples
 
 
-def warmstart_rows(N=4096, steps=200, train_steps=150, eval_every=5, hb_s=(3, 3), tol=1e-10,
+def warmstart_rows(N=4096, steps=200, train_steps=150, eval_every=1, hb_s=(3, 3), tol=1e-10,
                    iters=2000, per_step=4096, batch=4096):
     """Learned SIP start vector on an N x N ADI run: train on the x-sweeps of
     the first `train_steps` steps (sampled patches), then start SIP-HB on

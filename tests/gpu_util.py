@@ -35,7 +35,9 @@ def diags_of(t, kind=5):
 
 
 def host(t, batch):
-    return wl.deinterleave(t.cpu().numpy().astype(np.float64), batch)
+    """[n, ld] device tensor -> [batch, n] float64 (padding columns, which
+    the library never writes, are left out before the cast)."""
+    return wl.deinterleave(t[:, :batch].cpu().numpy().astype(np.float64), batch)
 
 
 def rel_err(x, ref):
