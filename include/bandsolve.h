@@ -31,9 +31,14 @@
  * rhs.
  *
  * PRECISION.  dtype BS_F64: every array is double.  dtype BS_F32 (fused
- * band_solve only, n >= 8): diags, rhs and x are stored as float, and every
- * arithmetic step (pivots and recurrences included) runs in FP64 on the
- * values read; only the storage rounding differs from FP64.
+ * band_solve only, n >= 8): diags, rhs and x are stored as float.  The
+ * pivots and the forward (L) recurrences always run in FP64 on the values
+ * read.  By default (BS_OPT_F32_STATE = 1, systems of n <= 4096) the per-row
+ * results of the forward sweep are kept in FP32 and the backward (U)
+ * substitution and the final x run in FP32 (forward error a few FP32
+ * roundings of ||x||; the FP64 state takes twice the registers and half the
+ * rows per block).  With BS_OPT_F32_STATE = 0, and for longer systems, every
+ * step runs in FP64 and only the storage rounding differs from FP64.
  * band_solve_refine takes FP64 arrays, solves with FP32 storage and restores
  * FP64 accuracy by iterative refinement.
  *
@@ -120,6 +125,9 @@ size_t bs_workspace_bytes(int32_t op, int32_t kind, int32_t dtype, int64_t n,
  *                          10^6), of a split-row block for the other blocks of
  *                          its system before it gives up and the system's
  *                          info becomes -4
+ *   BS_OPT_F32_STATE       FP32 storage (dtype BS_F32): 1 (default) keeps
+ *                          the per-row state of the split kernels in FP32,
+ *                          0 in FP64; 2 + k forces compact variant k (tuning)
  * bs_set_option returns BS_EINVAL for an unknown key or a value out of range;
  * bs_get_option returns -1 for an unknown key. */
 enum bs_option_code {
@@ -127,7 +135,8 @@ enum bs_option_code {
   BS_OPT_PART_PD_VARIANT = 1,
   BS_OPT_PART_TD_VARIANT = 2,
   BS_OPT_SIP_PATH = 3,
-  BS_OPT_EXCHANGE_WAIT_US = 4
+  BS_OPT_EXCHANGE_WAIT_US = 4,
+  BS_OPT_F32_STATE = 5
 };
 int32_t bs_set_option(int32_t key, int64_t value);
 int64_t bs_get_option(int32_t key);

@@ -32,8 +32,8 @@ EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "bs_set_option"
             "bs_varlen_variant_shape", "bs_varlen_layout", "bs_varlen_workspace_bytes",
             "band_solve_varlen", "bs_varlen_tune", "bs_pack_interleave", "bs_unpack_interleave",
             "bs_stream_probe", "band_solve_noalloc")
-OPT_DIRECT_PATH, OPT_PART_PD_VARIANT, OPT_PART_TD_VARIANT, OPT_SIP_PATH, OPT_EXCHANGE_WAIT_US = \
-    range(5)
+(OPT_DIRECT_PATH, OPT_PART_PD_VARIANT, OPT_PART_TD_VARIANT, OPT_SIP_PATH, OPT_EXCHANGE_WAIT_US,
+ OPT_F32_STATE) = range(6)
 PATH_AUTO, PATH_LANE, PATH_PART = range(3)
 
 

@@ -8,6 +8,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 
@@ -61,6 +62,7 @@ bs::Diags as_diags(int32_t kind, const void* const diags[5]) {
 std::atomic<int64_t> g_direct_path{0};
 std::atomic<int64_t> g_pd_variant{0}, g_td_variant{0};
 std::atomic<int64_t> g_sip_path{0};
+std::atomic<int64_t> g_f32_state{1};
 
 int part_idx(int32_t kind) { return (int)(kind == 5 ? g_pd_variant.load() : g_td_variant.load()); }
 
@@ -70,10 +72,15 @@ namespace bs {
 namespace {
 
 // Which fused kernel solves (kind, dtype, n, ld) under the current options.
-enum class Route { kLane, kPart, kLong, kNone };
+enum class Route { kLane, kPart, kCompact, kLong, kNone };
 
 Route route(int kind, int dtype, int64_t n, int64_t ld, int* idx) {
   *idx = -1;
+  const int64_t fs = g_f32_state.load();
+  if (g_direct_path.load() != 1 && dtype == BS_F32 && fs != 0) {
+    *idx = compact_pick(kind, fs >= 2 ? (int)(fs - 2) : 0, n, ld);
+    if (*idx >= 0) return Route::kCompact;
+  }
   if (g_direct_path.load() != 1) {
     *idx = part_pick(kind, part_idx(kind), n, ld, dtype);
     if (*idx >= 0) return Route::kPart;
@@ -93,6 +100,7 @@ size_t direct_ws_bytes(int kind, int dtype, int64_t n, int64_t batch, int64_t ld
   int idx;
   switch (route(kind, dtype, n, ld, &idx)) {
     case Route::kPart: return part_workspace_bytes(kind, idx, n, batch);
+    case Route::kCompact: return compact_workspace_bytes(kind, idx, n, batch);
     case Route::kLong: return long_workspace_bytes(kind, n, batch);
     case Route::kLane: return (size_t)((kind == 5 ? 2 : 1) * n * ws_ld(batch)) * 8;
     default: return 0;
@@ -101,8 +109,11 @@ size_t direct_ws_bytes(int kind, int dtype, int64_t n, int64_t batch, int64_t ld
 
 size_t direct_counter_bytes(int kind, int dtype, int64_t n, int64_t batch, int64_t ld) {
   int idx;
-  return route(kind, dtype, n, ld, &idx) == Route::kPart ? part_counter_bytes(kind, idx, n, batch)
-                                                         : 0;
+  switch (route(kind, dtype, n, ld, &idx)) {
+    case Route::kPart: return part_counter_bytes(kind, idx, n, batch);
+    case Route::kCompact: return compact_counter_bytes(kind, idx, n, batch);
+    default: return 0;
+  }
 }
 
 hipError_t launch_direct(int kind, int dtype, int64_t n, int64_t batch, int64_t ld,
@@ -113,6 +124,8 @@ hipError_t launch_direct(int kind, int dtype, int64_t n, int64_t batch, int64_t 
   switch (route(kind, dtype, n, ld, &idx)) {
     case Route::kPart:
       return launch_part(kind, idx, dtype, n, batch, ld, dg, y, x, info, w, st, skip);
+    case Route::kCompact:
+      return launch_compact(kind, idx, n, batch, ld, dg, y, x, info, w, st, skip);
     case Route::kLong:
       return launch_long_path(kind, dtype, n, batch, ld, dg, y, x, info, w, st, skip);
     case Route::kLane: {
@@ -174,6 +187,11 @@ int32_t bs_set_option(int32_t key, int64_t value) {
       if (value < 0 || value > 4) return BS_EINVAL;
       g_sip_path = value;
       return BS_OK;
+    case BS_OPT_F32_STATE:
+      if (value < 0 || value > 1 + std::max(bs::compact_count(3), bs::compact_count(5)))
+        return BS_EINVAL;
+      g_f32_state = value;
+      return BS_OK;
     case BS_OPT_EXCHANGE_WAIT_US:
       if (value < 0 || value > 10000000) return BS_EINVAL;
       bs::set_exchange_wait_us(value);
@@ -197,6 +215,7 @@ int64_t bs_get_option(int32_t key) {
     case BS_OPT_PART_TD_VARIANT: return g_td_variant.load();
     case BS_OPT_SIP_PATH: return g_sip_path.load();
     case BS_OPT_EXCHANGE_WAIT_US: return bs::exchange_wait_us();
+    case BS_OPT_F32_STATE: return g_f32_state.load();
     default: return -1;
   }
 }

@@ -84,6 +84,17 @@ size_t part_counter_bytes(int kind, int idx, int64_t n, int64_t batch);
 hipError_t launch_part(int kind, int idx, int dtype, int64_t n, int64_t batch, int64_t ld,
                        const void* const dg[5], const void* y, void* x, int32_t* info,
                        double* ws, hipStream_t st, const int32_t* skip = nullptr);
+// FP32 storage with the compact chunk state (FP32 per-row state and backward
+// substitution, FP64 forward recurrences): variant idx of a kind (as
+// part_pick: the preferred one if it covers n, else the first that does, -1
+// if none), its workspace, leading counter bytes and launch.
+int compact_count(int kind);
+int compact_pick(int kind, int idx, int64_t n, int64_t ld);
+size_t compact_workspace_bytes(int kind, int idx, int64_t n, int64_t batch);
+size_t compact_counter_bytes(int kind, int idx, int64_t n, int64_t batch);
+hipError_t launch_compact(int kind, int idx, int64_t n, int64_t batch, int64_t ld,
+                          const void* const dg[5], const void* y, void* x, int32_t* info,
+                          double* ws, hipStream_t st, const int32_t* skip = nullptr);
 // MNPDM (outer diagonals as a per-system list) on the split kernels: the
 // variant to use for (n, ld) (-1 if none) and its launch; the workspace is
 // part_workspace_bytes(5, idx, n, batch).

@@ -26,6 +26,7 @@
 // Block -> system-group mapping is XCD-aware: consecutive system groups
 // (which share 128-byte lines of every row) go to the same XCD, so the line
 // is fetched from HBM once and served from that XCD's L2 to its neighbours.
+#include <algorithm>
 #include <atomic>
 
 #include "seq_core.h"
@@ -58,8 +59,10 @@ using namespace split;
 // zero, so every product with them is an exact zero).
 // ASM: the rows are assembled from the sweep input v (passed as Y) and r
 // instead of being loaded (the ADI sweep of the PDE, see assemble_chunk).
+// TS: type of the per-row chunk state: double, or float for the compact
+// state of FP32 storage (chunk_pd_rows / chunk_td_rows on float arrays).
 template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false,
-          bool ASM = false>
+          bool ASM = false, typename TS = double>
 __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void part_kernel(
     int64_t n, int64_t batch, int64_t ld, const TIO* __restrict__ E,
     const TIO* __restrict__ C, const TIO* __restrict__ D,
@@ -73,6 +76,8 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
   constexpr int RT = M * PW;
   static_assert((PW & (PW - 1)) == 0 && (TMAX & (TMAX - 1)) == 0 && M >= 4, "shape");
   static_assert(G <= 32 && TMAX <= 32, "masks");
+  static_assert(G >= 16, "the counter region is sized for groups of at least 16 systems");
+  static_assert(sizeof(TS) == 8 || (sizeof(TIO) == 4 && !ASM && !SPARSE), "compact state");
   if (skip != nullptr && *skip) return;  // uniform: a refinement loop has finished
   __shared__ double s_node[(PW - 1) * G * RS];
   __shared__ double s_gnode[(TMAX > 1 ? TMAX - 1 : 1) * G * RS];
@@ -103,7 +108,7 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
   if (tid == 0) s_timeout = 0;
 
   // ---- 1. load the chunk and eliminate it locally -------------------------
-  double p[M], v[NB][M], w[NB][M];
+  TS p[M], v[NB][M], w[NB][M];
   int bad;
   bool list_bad = false;
   // rows in flight: at most 63 loads per wave; at two waves per SIMD the
@@ -147,8 +152,8 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
       }
     }
     // loads streamed under the forward elimination
-    stream_eliminate<KIND, M, DPF, TIO, SPARSE>(n, ld, s, live, r0, E, C, D, A, B, Y, eo, bo, p,
-                                                v, w, bad);
+    stream_eliminate<KIND, M, DPF, TIO, SPARSE, TS>(n, ld, s, live, r0, E, C, D, A, B, Y, eo, bo,
+                                                    p, v, w, bad);
   }
   Map<NB> mp = chunk_map<NB, M>(p, v, w);
   __syncthreads();  // s_bad initialised
@@ -537,6 +542,12 @@ constexpr Variant kVariants[] = {
     {5, 32, 16, 16, 4, 1}, {5, 32, 16, 16, 8, 1}, {5, 16, 16, 16, 8, 1}, {5, 8, 32, 16, 8, 1},
     {3, 32, 16, 16, 4, 1}, {3, 32, 16, 16, 8, 1}, {3, 16, 16, 16, 8, 2}, {3, 16, 32, 16, 4, 2},
 };
+// FP32 storage with the compact (FP32) chunk state: twice the rows per lane
+// (64), so the sweep batch is one round of blocks, and 32 systems per block,
+// so a row of the tile is one 128-byte line of FP32 values.
+constexpr Variant kCompact[] = {
+    {5, 64, 8, 32, 4, 1}, {5, 64, 8, 32, 8, 1}, {3, 64, 8, 32, 4, 1}, {3, 64, 8, 32, 8, 1},
+};
 // Shape of the long-system path (both kinds).
 constexpr int kLongM = 32, kLongPW = 16, kLongG = 16;
 
@@ -555,7 +566,11 @@ PartWs part_ws(int kind, int64_t n, int64_t batch, int64_t M, int64_t PW, int64_
   const int64_t groups = (batch + G - 1) / G;
   const int64_t xs = (kind == 5 ? 20 : 6) + 1;
   PartWs W;
-  W.xch = 2 * groups;  // 4 * groups unsigned counters
+  // 4 unsigned counters per group, in a region sized for groups of 16 (the
+  // smallest G) whatever this variant's G: every variant's counters then lie
+  // in the same leading bytes, which every completed call leaves zero, so a
+  // workspace may serve calls of different variants or dtypes in turn.
+  W.xch = 2 * std::max(groups, (batch + 15) / 16);
   const int64_t head = (T > 1) ? W.xch + groups * T * G * xs : 0;
   W.planes = (head + 31) / 32 * 32;
   W.total = W.planes + (kind == 5 ? 3 : 2) * n * ws_ld(batch);
@@ -563,7 +578,7 @@ PartWs part_ws(int kind, int64_t n, int64_t batch, int64_t M, int64_t PW, int64_
 }
 
 template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false,
-          bool ASM = false>
+          bool ASM = false, typename TS = double>
 hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, const void* const* dg,
                       const void* y, void* x, int32_t* info, double* ws, hipStream_t st,
                       const int32_t* skip, Outer ol = Outer{0, nullptr, nullptr, nullptr},
@@ -574,7 +589,7 @@ hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, const void* const* d
   const PartWs W = part_ws(KIND, n, batch, M, PW, G);
   unsigned* cnt = (T > 1) ? reinterpret_cast<unsigned*>(ws) : nullptr;
   double* xch = (T > 1) ? ws + W.xch : nullptr;
-  hipLaunchKernelGGL((part_kernel<TIO, KIND, M, PW, G, TMAX, WPE, SPARSE, ASM>),
+  hipLaunchKernelGGL((part_kernel<TIO, KIND, M, PW, G, TMAX, WPE, SPARSE, ASM, TS>),
                      dim3((unsigned)(groups * T)), dim3(G * PW), 0, st, n, batch, ld,
                      (const TIO*)dg[0], (const TIO*)dg[1], (const TIO*)dg[2], (const TIO*)dg[3],
                      (const TIO*)dg[4], (const TIO*)y, (TIO*)x, info, xch, cnt, T, skip, ol,
@@ -721,6 +736,56 @@ hipError_t launch_part(int kind, int idx, int dtype, int64_t n, int64_t batch, i
     BS_PV(float, 3, 32, 16, 16, 4, 1) BS_PV(float, 3, 32, 16, 16, 8, 1)
   }
 #undef BS_PV
+  return hipErrorInvalidValue;
+}
+
+const Variant* find_compact(int kind, int idx) {
+  int k = 0;
+  for (const Variant& v : kCompact)
+    if (v.kind == kind && k++ == idx) return &v;
+  return nullptr;
+}
+
+int compact_count(int kind) {
+  int k = 0;
+  for (const Variant& v : kCompact) k += v.kind == kind;
+  return k;
+}
+
+int compact_pick(int kind, int idx, int64_t n, int64_t ld) {
+  const Variant* v = find_compact(kind, idx);
+  if (v && covers(v, n, ld, 1)) return idx;
+  for (int k = 0; k < compact_count(kind); ++k)
+    if (covers(find_compact(kind, k), n, ld, 1)) return k;
+  return -1;
+}
+
+size_t compact_counter_bytes(int kind, int idx, int64_t n, int64_t batch) {
+  const Variant* v = find_compact(kind, idx);
+  if (!v) return 0;
+  const int64_t RT = (int64_t)v->M * v->PW;
+  return (n + RT - 1) / RT > 1 ? (size_t)part_ws(kind, n, batch, v->M, v->PW, v->G).xch * 8 : 0;
+}
+
+size_t compact_workspace_bytes(int kind, int idx, int64_t n, int64_t batch) {
+  const Variant* v = find_compact(kind, idx);
+  if (!v) return 0;
+  return (size_t)part_ws(kind, n, batch, v->M, v->PW, v->G).total * 8;
+}
+
+hipError_t launch_compact(int kind, int idx, int64_t n, int64_t batch, int64_t ld,
+                          const void* const dg[5], const void* y, void* x, int32_t* info,
+                          double* ws, hipStream_t st, const int32_t* skip) {
+  const Variant* v = find_compact(kind, idx);
+  if (!v) return hipErrorInvalidValue;
+#define BS_PC(K, MM, PP, GG, TT, WW)                                                     \
+  if (v->kind == K && v->M == MM && v->PW == PP && v->G == GG && v->TMAX == TT &&        \
+      v->WPE == WW)                                                                      \
+    return launch_cfg<float, K, MM, PP, GG, TT, WW, false, false, float>(                \
+        n, batch, ld, dg, y, x, info, ws, st, skip);
+  BS_PC(5, 64, 8, 32, 4, 1) BS_PC(5, 64, 8, 32, 8, 1)
+  BS_PC(3, 64, 8, 32, 4, 1) BS_PC(3, 64, 8, 32, 8, 1)
+#undef BS_PC
   return hipErrorInvalidValue;
 }
 

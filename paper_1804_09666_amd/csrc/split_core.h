@@ -300,6 +300,139 @@ __device__ inline void chunk_td_rows(Src&& src, Pre&& pre, double (&p)[M], doubl
   }
 }
 
+// The FP32 rounding of a value, materialised where it is written: without
+// this the compiler sinks the conversion to the value's use in the backward
+// sweep and keeps the FP64 value alive in between (twice the registers).
+__device__ inline float keep32(double x) {
+  float f = (float)x;
+  asm volatile("" : "+v"(f));
+  return f;
+}
+
+// Compact chunk state (FP32 storage only).  The forward step of every row
+// -- pivot, multipliers and the L^{-1} columns -- runs in FP64 exactly as in
+// chunk_pd_rows, with the two previous rows carried in FP64 registers; the
+// per-row results are kept in FP32, and the backward substitution U^{-1}
+// runs in FP32.  Half the registers of the FP64 state, so a lane can own
+// twice the rows (or a SIMD two waves).
+template <int M, typename Src, typename Pre>
+__device__ inline void chunk_pd_rows(Src&& src, Pre&& pre, float (&p)[M], float (&v0)[M],
+                                     float (&v1)[M], float (&w0)[M], float (&w1)[M],
+                                     int& bad) {
+  float al[M], be[M];
+  double am1 = 0.0, am2 = 0.0, bm1 = 0.0, bm2 = 0.0;  // alpha, beta of rows r-1, r-2
+  double pm1 = 0.0, pm2 = 0.0, xm1 = 0.0, xm2 = 0.0, ym1 = 0.0, ym2 = 0.0;  // p, v0, v1
+  double fm2 = 0.0;
+  bad = M;
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    pre(r);
+    double e, c, d, a, b, y;
+    src(r, e, c, d, a, b, y);
+    double ga, mu;
+    if (r == 0) {
+      ga = 0.0;
+      mu = d;
+    } else if (r == 1) {
+      ga = c;
+      mu = fma(-am1, ga, d);
+    } else {
+      ga = fma(-am2, e, c);
+      mu = fma(-am1, ga, fma(-bm2, e, d));
+    }
+    if (bad == M && bad_pivot(mu, fabs(c) + fabs(d) + fabs(a))) bad = r;
+    const double rc = recip(mu);
+    double ali, pi, xi, yi;
+    if (r == 0)
+      ali = a * rc;
+    else if (r <= M - 2)
+      ali = fma(-bm1, ga, a) * rc;
+    else
+      ali = 0.0;
+    const double bei = (r <= M - 3) ? b * rc : 0.0;
+    if (r == 0) {
+      pi = y * rc;
+      xi = e * rc;
+      yi = c * rc;
+    } else if (r == 1) {
+      pi = fma(-ga, pm1, y) * rc;
+      xi = (-ga * xm1) * rc;
+      yi = fma(-ga, ym1, e) * rc;
+    } else {
+      pi = fma(-ga, pm1, fma(-e, pm2, y)) * rc;
+      xi = fma(-ga, xm1, -e * xm2) * rc;
+      yi = fma(-ga, ym1, -e * ym2) * rc;
+    }
+    if (r == M - 2) fm2 = b * rc;
+    if (r == M - 1) {
+      w0[M - 1] = keep32(fma(-ga, fm2, a) * rc);
+      w1[M - 1] = keep32(b * rc);
+    }
+    al[r] = keep32(ali);
+    be[r] = keep32(bei);
+    p[r] = keep32(pi);
+    v0[r] = keep32(xi);
+    v1[r] = keep32(yi);
+    am2 = am1;
+    am1 = ali;
+    bm2 = bm1;
+    bm1 = bei;
+    pm2 = pm1;
+    pm1 = pi;
+    xm2 = xm1;
+    xm1 = xi;
+    ym2 = ym1;
+    ym1 = yi;
+  }
+  w0[M - 2] = fmaf(-al[M - 2], w0[M - 1], (float)fm2);
+  w1[M - 2] = -al[M - 2] * w1[M - 1];
+  p[M - 2] = fmaf(-al[M - 2], p[M - 1], p[M - 2]);
+  v0[M - 2] = fmaf(-al[M - 2], v0[M - 1], v0[M - 2]);
+  v1[M - 2] = fmaf(-al[M - 2], v1[M - 1], v1[M - 2]);
+#pragma unroll
+  for (int r = M - 3; r >= 0; --r) {
+    p[r] = fmaf(-be[r], p[r + 2], fmaf(-al[r], p[r + 1], p[r]));
+    v0[r] = fmaf(-be[r], v0[r + 2], fmaf(-al[r], v0[r + 1], v0[r]));
+    v1[r] = fmaf(-be[r], v1[r + 2], fmaf(-al[r], v1[r + 1], v1[r]));
+    w0[r] = fmaf(-be[r], w0[r + 2], -al[r] * w0[r + 1]);
+    w1[r] = fmaf(-be[r], w1[r + 2], -al[r] * w1[r + 1]);
+  }
+}
+
+// Compact chunk state of a tridiagonal chunk (see the pentadiagonal one).
+template <int M, typename Src, typename Pre>
+__device__ inline void chunk_td_rows(Src&& src, Pre&& pre, float (&p)[M], float (&v0)[M],
+                                     float (&w0)[M], int& bad) {
+  float al[M];
+  double am1 = 0.0, pm1 = 0.0, vm1 = 0.0;
+  bad = M;
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    pre(r);
+    double e, c, d, a, b, y;
+    src(r, e, c, d, a, b, y);
+    const double mu = (r == 0) ? d : fma(-am1, c, d);
+    if (bad == M && bad_pivot(mu, fabs(c) + fabs(d) + fabs(a))) bad = r;
+    const double rc = recip(mu);
+    const double ali = (r <= M - 2) ? a * rc : 0.0;
+    const double pi = (r == 0) ? y * rc : fma(-c, pm1, y) * rc;
+    const double vi = (r == 0) ? c * rc : (-c * vm1) * rc;
+    if (r == M - 1) w0[M - 1] = keep32(a * rc);
+    al[r] = keep32(ali);
+    p[r] = keep32(pi);
+    v0[r] = keep32(vi);
+    am1 = ali;
+    pm1 = pi;
+    vm1 = vi;
+  }
+#pragma unroll
+  for (int r = M - 2; r >= 0; --r) {
+    p[r] = fmaf(-al[r], p[r + 1], p[r]);
+    v0[r] = fmaf(-al[r], v0[r + 1], v0[r]);
+    w0[r] = -al[r] * w0[r + 1];
+  }
+}
+
 template <int M>
 __device__ inline void chunk_pd(const double (&e)[M], const double (&c)[M],
                                 const double (&d)[M], const double (&a)[M],
@@ -635,9 +768,9 @@ __device__ inline void assemble_chunk(int64_t n, int64_t ld, int64_t s, bool liv
 }
 
 // The chunk's affine map: tip rows of p, V, W.
-template <int NB, int M>
-__device__ inline Map<NB> chunk_map(const double (&p)[M], const double (&v)[NB][M],
-                                    const double (&w)[NB][M]) {
+template <int NB, int M, typename TS>
+__device__ inline Map<NB> chunk_map(const TS (&p)[M], const TS (&v)[NB][M],
+                                    const TS (&w)[NB][M]) {
   Map<NB> mp;
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
@@ -684,6 +817,34 @@ __device__ inline void write_chunk(int64_t n, int64_t ld, int64_t s, bool live, 
   }
 }
 
+// x from the compact (FP32) chunk state, in FP32.
+template <int NB, int M, typename TIO>
+__device__ inline void write_chunk(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
+                                   int64_t row_base,
+                                   const float (&p)[M], const float (&v)[NB][M],
+                                   const float (&w)[NB][M], const double (&xl)[NB],
+                                   const double (&xr)[NB], TIO* __restrict__ X) {
+  static_assert(sizeof(TIO) == 4, "the compact state is for FP32 storage");
+  const uint32_t row_bytes = (uint32_t)(ld * sizeof(TIO));
+  const uint32_t off0 = (uint32_t)((r0 * ld + s) * (int64_t)sizeof(TIO));
+  float fl[NB], fr[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    fl[k] = (float)xl[k];
+    fr[k] = (float)xr[k];
+  }
+#pragma unroll
+  for (int r = 0; r < M; ++r) {
+    const int64_t i = row_base + r0 + r;
+    float xv = p[r];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) xv = fmaf(-v[k][r], fl[k], fmaf(-w[k][r], fr[k], xv));
+    if (live && i < n)
+      __builtin_nontemporal_store(xv, reinterpret_cast<TIO*>(reinterpret_cast<char*>(X) + off0 +
+                                                              (uint32_t)r * row_bytes));
+  }
+}
+
 // ---- streamed chunk: loads interleaved with the forward elimination -----
 // The rows come through raw buffer loads: one 32-bit byte offset per row and
 // array on a buffer resource whose range is the array, so a slot outside
@@ -711,14 +872,15 @@ __device__ inline TIO bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
 
 // LIST: the outer diagonals e, b are not loaded but taken from eo, bo (an
 // MNPDM list scattered into registers); only c, d, a, y are streamed.
-template <int KIND, int M, int D, typename TIO, bool LIST = false>
+// TS: state type (double, or float for the compact state of FP32 storage).
+template <int KIND, int M, int D, typename TIO, bool LIST = false, typename TS = double>
 __device__ inline void stream_eliminate(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
                                         const TIO* __restrict__ E, const TIO* __restrict__ C,
                                         const TIO* __restrict__ Dg, const TIO* __restrict__ A,
                                         const TIO* __restrict__ B, const TIO* __restrict__ Y,
                                         const double (&eo)[M], const double (&bo)[M],
-                                        double (&p)[M], double (&v)[KIND == 5 ? 2 : 1][M],
-                                        double (&w)[KIND == 5 ? 2 : 1][M], int& bad) {
+                                        TS (&p)[M], TS (&v)[KIND == 5 ? 2 : 1][M],
+                                        TS (&w)[KIND == 5 ? 2 : 1][M], int& bad) {
   constexpr bool OUTER = KIND == 5 && !LIST;  // e, b streamed
   const uint32_t bytes = (uint32_t)(n * ld * (int64_t)sizeof(TIO));
   const uint32_t row_bytes = (uint32_t)(ld * sizeof(TIO));

@@ -116,9 +116,18 @@ def test_workspace_query(bs):
         R = max(1, min(batch, 256, 2 ** 25 // (npl * n_long)))
         assert bs.workspace_bytes(bs.OP_SOLVE, kind, n_long, batch) == \
             (up(recs * (rs + 1) + recs * 2 * nb + batch * T * rs) + npl * n_long * R) * 8
-    # FP32 storage: the split kernels only (n >= 8), fused solve only
+    # FP32 storage: the split kernels only (n >= 8), fused solve only.  The
+    # compact state (default) runs 32 systems x 8 lanes x 64 rows per block;
+    # its counter region is sized for groups of 16, as the FP64 variants'.
+    T32, groups32 = -(-2048 // (64 * 8)), -(-batch // 32)
     assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch, bs.BS_F32) == \
-        bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch)
+        (up(2 * groups + groups32 * T32 * 32 * 21) + 3 * 2048 * lw) * 8
+    bs.set_option(bs.OPT_F32_STATE, 0)
+    try:
+        assert bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch, bs.BS_F32) == \
+            bs.workspace_bytes(bs.OP_SOLVE, 5, 2048, batch)
+    finally:
+        bs.set_option(bs.OPT_F32_STATE, 1)
     assert lib.bs_workspace_bytes(bs.OP_SOLVE, 5, bs.BS_F32, 4, batch, batch) == bad
     assert lib.bs_workspace_bytes(bs.OP_SIP, 5, bs.BS_F32, n, batch, batch) == bad
     assert lib.bs_workspace_bytes(bs.OP_REFINE, 5, bs.BS_F32, n, batch, batch) == bad
@@ -153,6 +162,13 @@ def test_options(bs):
     assert bs.get_option(bs.OPT_SIP_PATH) == 3
     bs.set_option(bs.OPT_SIP_PATH, 0)
     assert bs.get_option(99) == -1
+    assert bs.get_option(bs.OPT_F32_STATE) == 1          # compact FP32 state by default
+    for bad_value in (-1, 4):
+        with pytest.raises(bs.BandSolveError):
+            bs.set_option(bs.OPT_F32_STATE, bad_value)
+    for v in (0, 2, 3, 1):
+        bs.set_option(bs.OPT_F32_STATE, v)
+        assert bs.get_option(bs.OPT_F32_STATE) == v
     for kind in (5, 3):
         vs = bs.part_variants(kind)
         assert len(vs) >= 2

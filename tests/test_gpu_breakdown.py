@@ -79,18 +79,25 @@ def test_chunk_start_pivot_is_redone(kind, value):
 
 
 @pytest.mark.parametrize("kind", [5, 3])
-def test_fp32_storage_redo(kind):
-    """The same with FP32 storage: the redo runs the sequential recurrence in
-    FP64 on the FP32 values, so x is the oracle's solution of the
-    FP32-valued system, rounded once to FP32."""
+@pytest.mark.parametrize("state", [1, 0])
+def test_fp32_storage_redo(kind, state):
+    """The same with FP32 storage, with the compact (1) and the FP64 (0)
+    chunk state: the redo runs the sequential recurrence in FP64 on the FP32
+    values, so x is the oracle's solution of the FP32-valued system, rounded
+    once to FP32.  Rows 64 and 512 start a chunk in both states (64 and 32
+    rows per chunk)."""
     batch, n = 32, 2048
     ws = fresh(batch, n, kind, 42)
     ws32 = {k: ws[k].astype(np.float32).astype(np.float64) for k in KEYS}
-    for s, i in {1: 32, 9: 512}.items():
+    for s, i in {1: 64, 9: 512}.items():
         ws32["d"][s, i] = 0.0
     xr, ir, _ = oracle_direct(ws32, kind)
     assert (ir == 0).all()
-    x, info = run(ws32, kind, batch, torch.float32)
+    bs.set_option(bs.OPT_F32_STATE, state)
+    try:
+        x, info = run(ws32, kind, batch, torch.float32)
+    finally:
+        bs.set_option(bs.OPT_F32_STATE, 1)
     assert (info == 0).all()
     for s in (1, 9):
         assert np.array_equal(x[s], xr[s].astype(np.float32).astype(np.float64)), s

@@ -39,43 +39,127 @@ def host_residual(ws, kind, x):
 
 
 # ------------------------------------------------------------ FP32 storage --
+# With the compact state (BS_OPT_F32_STATE = 1, the default) the backward
+# substitution and the final x = p - V x_L - W x_R run in FP32.  A value of x
+# passes through: one rounding of each forward (FP64) result, at most two per
+# step of the backward sweep (a contraction where |alpha| + |beta| < 1, so
+# earlier errors do not grow), two roundings of the outer pairs and four
+# fused steps of the final sum: below 16 u of the terms' magnitude on
+# diagonally dominant rows.  The bar on the normwise backward error
+#     eta = ||y - A x||_inf / (||A||_inf ||x||_inf + ||y||_inf)
+# is twice that, K_BWD u.  On a strictly diagonally dominant matrix
+# ||A^-1||_inf <= 1 / delta, delta = min_i (|d_i| - sum of |off-diagonals|)
+# (Varah), so the forward error is then at most ||y - A x||_inf / delta.
+K_BWD = 32
+
+
+def abs_rowsum(ws, kind):
+    s = np.abs(ws["c"]) + np.abs(ws["d"]) + np.abs(ws["a"])
+    if kind == 5:
+        s = s + np.abs(ws["e"]) + np.abs(ws["b"])
+    return s
+
+
+def backward_error(ws, kind, x):
+    """Per system: eta (above) and ||y - A x||_inf, in FP64 on the host."""
+    d = {k: ws[k] for k in ("c", "d", "a")}
+    d["e"] = ws["e"] if kind == 5 else np.zeros_like(ws["d"])
+    d["b"] = ws["b"] if kind == 5 else np.zeros_like(ws["d"])
+    r = np.abs(ws["y"] - wl.band_matvec(d, x)).max(axis=1)
+    scale = abs_rowsum(ws, kind).max(axis=1) * np.abs(x).max(axis=1) + np.abs(ws["y"]).max(axis=1)
+    return r / scale, r
+
+
+def check_fp32(ws, kind, xg, xr, state, dominant):
+    if state == 0:   # FP64 arithmetic: within one FP32 rounding of x, plus the FP64 bar
+        bar = U32 * np.abs(xr) + 2 * TOL * np.abs(xr).max(axis=1, keepdims=True)
+        worst = (np.abs(xg - xr) / bar).max()
+        say(f"  FP64 state: max |x - x_orc| / bar = {worst:.3f}")
+        assert worst <= 1.0
+        return
+    eta, r = backward_error(ws, kind, xg)
+    say(f"  compact state: max eta = {eta.max() / U32:.2f} u")
+    assert (eta <= K_BWD * U32).all()
+    if dominant:
+        delta = (2 * np.abs(ws["d"]) - abs_rowsum(ws, kind)).min(axis=1)
+        assert (delta > 0).all()
+        err = np.abs(xg - xr).max(axis=1)
+        bound = r / delta + 2 * TOL * np.abs(xr).max(axis=1)
+        say(f"  compact state: max forward error / Varah bound = {(err / bound).max():.3f}")
+        assert (err <= bound).all()
+
+
+@pytest.fixture(params=[1, 0], ids=["compact_state", "fp64_state"])
+def f32_state(request):
+    bs.set_option(bs.OPT_F32_STATE, request.param)
+    yield request.param
+    bs.set_option(bs.OPT_F32_STATE, 1)
+
+
 @pytest.mark.parametrize("kind", [5, 3])
 @pytest.mark.parametrize("n,batch,ld", [(8, 5, 64), (9, 33, 64), (100, 17, 17), (2047, 45, 64),
-                                        (4096, 20, 64), (5000, 7, 8), (40000, 3, 64)])
-def test_fp32_storage_parity(kind, n, batch, ld):
-    """FP32 inputs, FP64 arithmetic, FP32 x: every element within one FP32
-    rounding of the FP64 oracle solution of the same (FP32-valued) system,
-    plus the FP64 parity bar."""
+                                        (2048, 70, 96), (4096, 20, 64), (5000, 7, 8),
+                                        (40000, 3, 64)])
+def test_fp32_storage_parity(kind, n, batch, ld, f32_state):
+    """FP32 inputs and x, FP64 pivots and forward recurrences.  FP64 state:
+    every element within one FP32 rounding of the FP64 oracle solution of the
+    same (FP32-valued) system, plus the FP64 parity bar.  Compact state: the
+    backward-error bar and the forward bound it implies (Varah)."""
     ws = fp32_rounded(wl.dominant_batch(batch, n, kind=kind, seed=3000 + n + batch))
-    say(f"fp32 kind={kind} n={n} batch={batch} ld={ld}")
+    say(f"fp32 kind={kind} n={n} batch={batch} ld={ld} state={f32_state}")
     t = to_device(ws, batch, ld=ld, corner_nan=True, dtype=torch.float32)
     x, info = bs.solve(diags_of(t, kind), t["y"], kind=kind, batch=batch)
     torch.cuda.synchronize()
     xr, ir = oracle_direct(ws, kind)
     assert (info.cpu().numpy() == 0).all() and (ir == 0).all()
-    xg = host(x, batch)
-    bar = U32 * np.abs(xr) + 2 * TOL * np.abs(xr).max(axis=1, keepdims=True)
-    worst = (np.abs(xg - xr) / bar).max()
-    say(f"  max |x - x_orc| / bar = {worst:.3f}")
-    assert worst <= 1.0
+    check_fp32(ws, kind, host(x, batch), xr, f32_state, dominant=True)
 
 
-def test_fp32_pde_lines_and_in_place():
+def test_workspace_shared_across_dtypes_and_states():
+    """One workspace serves FP32 calls with either state and FP64 calls in
+    turn: the variants differ in systems per block, and their meeting
+    counters share one leading region that every call leaves zero."""
+    kind, n, batch = 5, 2048, 96
+    ws = wl.dominant_batch(batch, n, kind=kind, seed=77)
+    w32 = fp32_rounded(ws)
+    xr, _ = oracle_direct(ws, kind)
+    xr32, _ = oracle_direct(w32, kind)
+    t64 = to_device(ws, batch)
+    t32 = to_device(w32, batch, dtype=torch.float32)
+    nbytes = max(bs.workspace_bytes(bs.OP_SOLVE, kind, n, batch, dt) for dt in (bs.BS_F64, bs.BS_F32))
+    wsb = torch.zeros((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
+    lead = (batch + 15) // 16 * 4
+    try:
+        for state in (1, 0, 1):
+            bs.set_option(bs.OPT_F32_STATE, state)
+            for t, ref, wsrc in ((t32, xr32, w32), (t64, xr, ws)):
+                say(f"shared workspace: state={state} dtype={t['y'].dtype}")
+                x, info = bs.solve(diags_of(t, kind), t["y"], kind=kind, batch=batch, workspace=wsb)
+                torch.cuda.synchronize()
+                assert (info.cpu().numpy() == 0).all()
+                assert (wsb.view(torch.int32)[:lead] == 0).all()
+                if t is t64:
+                    assert rel_err(host(x, batch), ref).max() <= TOL
+                else:
+                    check_fp32(wsrc, kind, host(x, batch), ref, state, dominant=True)
+    finally:
+        bs.set_option(bs.OPT_F32_STATE, 1)
+
+
+def test_fp32_pde_lines_and_in_place(f32_state):
     """Second-order (non-dominant boundary) PDE rows in FP32 storage on the
     full 2048 x 2048 sweep batch the benchmark times, every element of every
     system; x may alias rhs."""
     pd, td, _ = wl.config1()
     for kind, ws in ((5, fp32_rounded(pd)), (3, fp32_rounded(td))):
+        say(f"fp32 sweep batch kind={kind} state={f32_state}")
         t = to_device(ws, 2048, dtype=torch.float32)
         y = t["y"].clone()
         x, info = bs.solve(diags_of(t, kind), y, y, kind=kind, batch=2048)
         torch.cuda.synchronize()
         xr, _ = oracle_direct(ws, kind)
         assert (info.cpu().numpy() == 0).all()
-        bar = U32 * np.abs(xr) + 2 * TOL * np.abs(xr).max(axis=1, keepdims=True)
-        worst = (np.abs(host(x, 2048) - xr) / bar).max()
-        say(f"fp32 sweep batch kind={kind}: max |x - x_orc| / bar = {worst:.3f}")
-        assert worst <= 1.0
+        check_fp32(ws, kind, host(x, 2048), xr, f32_state, dominant=False)
 
 
 # ---------------------------------------------------- long systems, FP64 ---
