@@ -593,7 +593,8 @@ def warmstart_rows(N=4096, steps=200, train_steps=150, eval_every=1, hb_s=(3, 3)
            "train_ms": train_ms, "loss_trace": losses,
            "inference_ms_mean": float(np.mean(infer_ms)),
            # network flops over the whole inference time (features, fused network, start)
-           "inference_network_TFLOPs_whole": 2 * npatch * (448 * 512 + 2 * 512 * 512 + 512 * 64) /
+           "inference_network_TFLOPs_whole": 2 * npatch * (wsm.IN * wsm.HIDDEN + 2 * wsm.HIDDEN ** 2
+                                                           + wsm.HIDDEN * wsm.OUT) /
                                              (float(np.mean(infer_ms)) * 1e-3) / 1e12}
     for k, v in res.items():
         out[k] = {"iters_mean": float(np.mean(v["iters_mean"])),

@@ -15,7 +15,7 @@
  *             (v - mean_f) / scale_f.  Slots outside the matrix (e_0, e_1,
  *             c_0, a_{n-1}, b_{n-2}, b_{n-1}) count as 0 before scaling; rows
  *             past n are 0 after it.
- *   network   448 -> 512 -> 512 -> 512 -> 64, ReLU after each hidden layer:
+ *   network   448 -> 256 -> 256 -> 256 -> 64, ReLU after each hidden layer:
  *             h1 = relu(X W1^T + b1), h2 = relu(h1 W2^T + b2),
  *             h3 = relu(h2 W3^T + b3), Y = h3 W4^T + b4.
  *   start     x0 = u_prev + mu_t + sigma_t * Y for the rows of the patch
@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-enum ws_dims_code { WS_PATCH = 64, WS_NFEAT = 7, WS_IN = 448, WS_HIDDEN = 512, WS_OUT = 64 };
+enum ws_dims_code { WS_PATCH = 64, WS_NFEAT = 7, WS_IN = 448, WS_HIDDEN = 256, WS_OUT = 64 };
 enum ws_dtype_code { WS_F32 = 1, WS_BF16 = 2 };
 enum ws_op_code { WS_OP_FORWARD = 0, WS_OP_TRAIN = 1 };
 
@@ -119,6 +119,15 @@ int32_t ws_features(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
  * rows i of every patch p = s * ceil(n/64) + j inside the system. */
 int32_t ws_apply(int64_t n, int64_t batch, int64_t ld, const float* Y, const double* uprev,
                  float mu_t, float sigma_t, double* x0, void* stream);
+
+/* features -> network (BF16, as ws_infer) -> start vector in one launch:
+ * the x0 that ws_apply gives for the Y of ws_infer on the X of
+ * ws_features(WS_BF16, ...), bit for bit, without X or Y going through
+ * memory.  planes, norm, mu_t, sigma_t as for ws_features / ws_apply
+ * (planes[6] is u_prev); x0 [n, ld] may not alias a plane. */
+int32_t ws_predict(int64_t n, int64_t batch, int64_t ld, const double* const planes[7],
+                   const float norm[14], const float* params32, const void* paramsT,
+                   float mu_t, float sigma_t, double* x0, void* stream);
 
 #ifdef __cplusplus
 }

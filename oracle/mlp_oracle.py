@@ -30,7 +30,7 @@ import numpy as np
 
 PATCH = 64
 NFEAT = 7
-DIMS = (NFEAT * PATCH, 512, 512, 512, PATCH)  # in, hidden x 3, out
+DIMS = (NFEAT * PATCH, 256, 256, 256, PATCH)  # in, hidden x 3, out
 
 
 # ------------------------------------------------------------------ bf16 ---

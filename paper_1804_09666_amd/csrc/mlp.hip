@@ -1,5 +1,5 @@
 // mlp.hip -- the learned SIP start vector (declared in include/warmstart.h):
-// patch features, a 448-512-512-512-64 ReLU network on the matrix cores
+// patch features, a 448-256-256-256-64 ReLU network on the matrix cores
 // (forward, backward, Adam), and the start vector x0.
 //
 // One GEMM kernel serves every product, C = A B^T with both operands K-
@@ -185,61 +185,55 @@ __global__ __launch_bounds__(kThreads) void gemm_nt_kernel(int64_t M, int64_t N,
 
 // ---- the whole network for a tile of patches (inference) ------------------
 // One block carries 32 RT patches through all four layers.  The layer input
-// sits in LDS (bf16, [32 RT][kFLD]); each wave computes 128 of the 512 output
-// columns (RT x 4 MFMA tiles of 32 x 32) with its weight fragments read
-// straight from global memory: the 1.5 MB of weights stay in every XCD's L2,
-// and a wave fetches the fragments of four k-steps together (a whole 128-byte
-// line of each of its weight rows) while the matrix cores work on the four
-// before.  Then the block writes relu(acc + b) back over the input as bf16
-// and moves on; the last layer's 64 columns go to Y in FP32.  The MFMAs of a
-// tile accumulate k in the same order as gemm_nt_kernel, and the rounding
-// points (bf16 activations, FP32 accumulation, bias then ReLU) are the same,
-// so Y is the layered forward pass's.
-constexpr int kFRT = 3;              // row tiles of 32 patches per block
+// sits in LDS (bf16, [32 RT][kFLD]); each of the NW waves computes 32 CJ of
+// the hidden output columns (RT x CJ MFMA tiles of 32 x 32) with its weight
+// fragments read straight from global memory: the weights stay in every
+// XCD's L2, and a wave fetches the fragments of four k-steps together (a
+// whole 128-byte line of each of its weight rows) while the matrix cores work
+// on the four before.  Then the block writes relu(acc + b) back over the
+// input as bf16 and moves on; the last layer's 64 columns go to `out(row,
+// col, y)` in FP32 (wave w takes row tiles w, w + NW, ...: it has read the
+// tile's rows of the last hidden layer before it calls out for them).  The
+// MFMAs of a tile accumulate k in the same order as gemm_nt_kernel, and the
+// rounding points (bf16 activations, FP32 accumulation, bias then ReLU) are
+// the same, so Y is the layered forward pass's.  Two waves per SIMD (NW = 8)
+// and 128 patches per block measured 633 us on 262 144 patches of the
+// 448-512-512-512-64 network against 832 us with one wave per SIMD and 96.
+constexpr int kFRT = 4;              // row tiles of 32 patches per block
 constexpr int kFR = 32 * kFRT;       // patches per block
-constexpr int kFLD = WS_HIDDEN + 8;  // LDS row pitch in bf16 (16 bytes of padding)
+constexpr int kFLD = (WS_IN > WS_HIDDEN ? WS_IN : WS_HIDDEN) + 8;  // LDS row pitch (bf16)
+constexpr int kInferWaves = 8;       // two waves per SIMD
 
-__global__ __launch_bounds__(kThreads, 1) void mlp_infer_kernel(int64_t P, const bf16* __restrict__ X,
-                                                                const bf16* __restrict__ W,
-                                                                const float* __restrict__ p32,
-                                                                float* __restrict__ Y) {
+template <int NW, typename Out>
+__device__ inline void network_tile(bf16* __restrict__ sH, const bf16* __restrict__ W,
+                                    const float* __restrict__ p32, Out&& out) {
   constexpr int RT = kFRT;
-  __shared__ __attribute__((aligned(16))) bf16 sH[kFR * kFLD];
+  constexpr int CJ = WS_HIDDEN / 32 / NW;  // column tiles of 32 per wave
+  static_assert(CJ >= 1 && CJ * 32 * NW == WS_HIDDEN, "hidden columns split over the waves");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int hi = lane >> 5, lo = lane & 31;
-  const int64_t p0 = (int64_t)blockIdx.x * kFR;
-  {  // the input tile: 448 features = 56 chunks of 16 bytes per patch
-    constexpr int CPR = WS_IN / 8;
-    for (int c = tid; c < kFR * CPR; c += kThreads) {
-      const int r = c / CPR, kc = (c % CPR) * 8;
-      Vec16 v = Vec16{0u, 0u, 0u, 0u};
-      if (p0 + r < P) v = *reinterpret_cast<const Vec16*>(X + (p0 + r) * WS_IN + kc);
-      *reinterpret_cast<Vec16*>(&sH[r * kFLD + kc]) = v;
-    }
-  }
-  __syncthreads();
   int64_t wo = 0;  // offset of this layer's W (then b) in the parameter vector
   for (int layer = 0; layer < 3; ++layer) {
     const int K = layer == 0 ? WS_IN : WS_HIDDEN;  // a multiple of 64
     const bf16* Wl = W + wo;
     const float* bl = p32 + wo + (int64_t)WS_HIDDEN * K;
-    const int n0 = wave * 128;
-    f32x16 acc[RT][4];
+    const int n0 = wave * 32 * CJ;
+    f32x16 acc[RT][CJ];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < CJ; ++j)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[i][j][v] = 0.0f;
-    const bf16* wrow[4];
+    const bf16* wrow[CJ];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) wrow[j] = Wl + (int64_t)(n0 + 32 * j + lo) * K + hi * 8;
+    for (int j = 0; j < CJ; ++j) wrow[j] = Wl + (int64_t)(n0 + 32 * j + lo) * K + hi * 8;
     // fragments of four k-steps (64 values of k) per buffer
-    bf16x8 fb[2][4][4];
+    bf16x8 fb[2][4][CJ];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) fb[0][q][j] = *reinterpret_cast<const bf16x8*>(wrow[j] + 16 * q);
+      for (int j = 0; j < CJ; ++j) fb[0][q][j] = *reinterpret_cast<const bf16x8*>(wrow[j] + 16 * q);
     for (int kg = 0; kg < K; kg += 128) {
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -248,7 +242,7 @@ __global__ __launch_bounds__(kThreads, 1) void mlp_infer_kernel(int64_t P, const
 #pragma unroll
           for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < CJ; ++j)
               fb[h ^ 1][q][j] = *reinterpret_cast<const bf16x8*>(wrow[j] + k0 + 64 + 16 * q);
         }
         if (k0 < K) {
@@ -262,7 +256,7 @@ __global__ __launch_bounds__(kThreads, 1) void mlp_infer_kernel(int64_t P, const
 #pragma unroll
             for (int i = 0; i < RT; ++i)
 #pragma unroll
-              for (int j = 0; j < 4; ++j)
+              for (int j = 0; j < CJ; ++j)
                 acc[i][j] =
                     __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[i], fb[h][q][j], acc[i][j], 0, 0, 0);
           }
@@ -271,7 +265,7 @@ __global__ __launch_bounds__(kThreads, 1) void mlp_infer_kernel(int64_t P, const
     }
     __syncthreads();  // every wave has read the layer input
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < CJ; ++j) {
       const int col = n0 + 32 * j + lo;
       const float bv = bl[col];
 #pragma unroll
@@ -287,13 +281,13 @@ __global__ __launch_bounds__(kThreads, 1) void mlp_infer_kernel(int64_t P, const
     __syncthreads();
     wo += (int64_t)WS_HIDDEN * K + WS_HIDDEN;
   }
-  // output layer: (32 RT) x 64; wave w takes row tiles w, w + 4, ... and both column tiles
+  // output layer: (32 RT) x 64; wave w takes row tiles w, w + NW, ... and both column tiles
   {
     const int K = WS_HIDDEN;
     const float* bl = p32 + wo + (int64_t)WS_OUT * K;
     const bf16* wr0 = W + wo + (int64_t)lo * K + hi * 8;
     const bf16* wr1 = wr0 + (int64_t)32 * K;
-    for (int ti = wave; ti < RT; ti += 4) {
+    for (int ti = wave; ti < RT; ti += NW) {
       f32x16 acc0, acc1;
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc0[v] = acc1[v] = 0.0f;
@@ -308,14 +302,45 @@ __global__ __launch_bounds__(kThreads, 1) void mlp_infer_kernel(int64_t P, const
       const float b0 = bl[lo], b1 = bl[32 + lo];
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int64_t row = p0 + 32 * ti + 8 * (v >> 2) + 4 * hi + (v & 3);
-        if (row < P) {
-          Y[row * WS_OUT + lo] = acc0[v] + b0;
-          Y[row * WS_OUT + 32 + lo] = acc1[v] + b1;
-        }
+        const int row = 32 * ti + 8 * (v >> 2) + 4 * hi + (v & 3);
+        out(row, lo, acc0[v] + b0);
+        out(row, 32 + lo, acc1[v] + b1);
       }
     }
   }
+}
+
+__device__ inline float standardised(double raw, float mean, float scale) {
+  return (float)((raw - (double)mean) / (double)scale);
+}
+
+// x0 = u_prev + (mu_t + sigma_t y), rounded step by step
+__device__ inline double start_value(double u, float mu, float sigma, float y) {
+#pragma clang fp contract(off)
+  return u + ((double)mu + (double)sigma * (double)y);
+}
+
+template <int NW>
+__global__ __launch_bounds__(64 * NW, 1) void mlp_infer_kernel(int64_t P, const bf16* __restrict__ X,
+                                                              const bf16* __restrict__ W,
+                                                              const float* __restrict__ p32,
+                                                              float* __restrict__ Y) {
+  __shared__ __attribute__((aligned(16))) bf16 sH[kFR * kFLD];
+  const int tid = threadIdx.x;
+  const int64_t p0 = (int64_t)blockIdx.x * kFR;
+  {  // the input tile: 448 features = 56 chunks of 16 bytes per patch
+    constexpr int CPR = WS_IN / 8;
+    for (int c = tid; c < kFR * CPR; c += 64 * NW) {
+      const int r = c / CPR, kc = (c % CPR) * 8;
+      Vec16 v = Vec16{0u, 0u, 0u, 0u};
+      if (p0 + r < P) v = *reinterpret_cast<const Vec16*>(X + (p0 + r) * WS_IN + kc);
+      *reinterpret_cast<Vec16*>(&sH[r * kFLD + kc]) = v;
+    }
+  }
+  __syncthreads();
+  network_tile<NW>(sH, W, p32, [&](int row, int col, float y) {
+    if (p0 + row < P) Y[(p0 + row) * WS_OUT + col] = y;
+  });
 }
 
 // out[C, R] = in[R, C]^T through a 32 x 32 LDS tile.
@@ -432,18 +457,27 @@ struct Norm {
 // (terms outside the matrix omitted), every product and sum rounded on its
 // own: the residual of the previous-step solution, the input through which the
 // right-hand side reaches the network.
+__device__ inline double residual_of(int64_t n, int64_t i, double e, double c, double d,
+                                     double a, double b, double rhs, double um2, double um1,
+                                     double u0, double up1, double up2) {
+#pragma clang fp contract(off)
+  double ax = d * u0;
+  if (i >= 2) ax = ax + e * um2;
+  if (i >= 1) ax = ax + c * um1;
+  if (i <= n - 2) ax = ax + a * up1;
+  if (i <= n - 3) ax = ax + b * up2;
+  return rhs - ax;
+}
+
 __device__ inline double residual(int64_t n, int64_t ld, int64_t i, int64_t o,
                                   const double* __restrict__ E, const double* __restrict__ C,
                                   const double* __restrict__ D, const double* __restrict__ A,
                                   const double* __restrict__ B, double rhs,
                                   const double* __restrict__ U) {
-#pragma clang fp contract(off)
-  double ax = D[o] * U[o];
-  if (i >= 2) ax = ax + E[o] * U[o - 2 * ld];
-  if (i >= 1) ax = ax + C[o] * U[o - ld];
-  if (i <= n - 2) ax = ax + A[o] * U[o + ld];
-  if (i <= n - 3) ax = ax + B[o] * U[o + 2 * ld];
-  return rhs - ax;
+  return residual_of(n, i, i >= 2 ? E[o] : 0.0, i >= 1 ? C[o] : 0.0, D[o],
+                     i <= n - 2 ? A[o] : 0.0, i <= n - 3 ? B[o] : 0.0, rhs,
+                     i >= 2 ? U[o - 2 * ld] : 0.0, i >= 1 ? U[o - ld] : 0.0, U[o],
+                     i <= n - 2 ? U[o + ld] : 0.0, i <= n - 3 ? U[o + 2 * ld] : 0.0);
 }
 
 // One block: 64 systems x one patch row (64 rows); every feature plane goes
@@ -475,7 +509,7 @@ __global__ __launch_bounds__(256) void features_kernel(int64_t n, int64_t batch,
         const int64_t o = i * ld + s;
         double raw = outside ? 0.0 : P[o];
         if (f == 5) raw = residual(n, ld, i, o, P0, P1, P2, P3, P4, raw, P6);
-        val = (float)((raw - (double)nm.mean[f]) / (double)nm.scale[f]);
+        val = standardised(raw, nm.mean[f], nm.scale[f]);
       }
       tile[r][sl] = val;
     }
@@ -507,7 +541,90 @@ __global__ __launch_bounds__(256) void apply_kernel(int64_t n, int64_t batch, in
     const int64_t i = j * 64 + r, s = s0 + sl;
     if (i < n && s < batch) {
       const int64_t o = i * ld + s;
-      X0[o] = U[o] + ((double)mu + (double)sigma * (double)tile[r][sl]);
+      X0[o] = start_value(U[o], mu, sigma, tile[r][sl]);
+    }
+  }
+}
+
+// features -> network -> start vector for one block of kFR consecutive
+// systems and one patch row j (rows 64 j .. 64 j + 63), without X or Y going
+// through memory.  The feature values are those of features_kernel (the same
+// FP64 steps, rounded to FP32, then to bf16), written straight into the
+// block's LDS tile; Y is staged in the LDS rows of its patches (each wave
+// writes only rows it has finished reading) and x0 leaves row by row, so
+// every load and store covers consecutive systems.  x0 equals ws_apply of the
+// Y of ws_infer on the features of ws_features, bit for bit.
+template <int NW>
+__global__ __launch_bounds__(64 * NW, 1) void predict_kernel(
+    int64_t n, int64_t batch, int64_t ld, const double* __restrict__ P0,
+    const double* __restrict__ P1, const double* __restrict__ P2, const double* __restrict__ P3,
+    const double* __restrict__ P4, const double* __restrict__ P5, const double* __restrict__ P6,
+    Norm nm, const bf16* __restrict__ W, const float* __restrict__ p32, float mu, float sigma,
+    double* __restrict__ X0) {
+  __shared__ __attribute__((aligned(16))) bf16 sH[kFR * kFLD];
+  const int tid = threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * kFR, j = blockIdx.y;
+  // UB elements per thread at a time, all their loads issued before the
+  // arithmetic (11 loads each: the seven planes and u_prev at i -+ 1, 2)
+  constexpr int EPT = 64 * kFR / (64 * NW), UB = 4;
+  static_assert(EPT % UB == 0, "elements per thread");
+  const double* planes[7] = {P0, P1, P2, P3, P4, P5, P6};
+  for (int e0 = 0; e0 < EPT; e0 += UB) {
+    double v[UB][7], um2[UB], um1[UB], up1[UB], up2[UB];
+    int64_t ii[UB];
+    bool in[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int idx = tid + (e0 + u) * 64 * NW;
+      const int r = idx / kFR, sl = idx % kFR;  // consecutive threads: consecutive systems
+      const int64_t i = j * 64 + r, s = s0 + sl, o = i * ld + s;
+      ii[u] = i;
+      in[u] = i < n && s < batch;
+#pragma unroll
+      for (int f = 0; f < 7; ++f) {
+        const bool outside = (f == 0 && i < 2) || (f == 1 && i < 1) || (f == 3 && i > n - 2) ||
+                             (f == 4 && i > n - 3);
+        v[u][f] = (in[u] && !outside) ? __builtin_nontemporal_load(planes[f] + o) : 0.0;
+      }
+      um2[u] = (in[u] && i >= 2) ? P6[o - 2 * ld] : 0.0;
+      um1[u] = (in[u] && i >= 1) ? P6[o - ld] : 0.0;
+      up1[u] = (in[u] && i <= n - 2) ? P6[o + ld] : 0.0;
+      up2[u] = (in[u] && i <= n - 3) ? P6[o + 2 * ld] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int idx = tid + (e0 + u) * 64 * NW;
+      const int r = idx / kFR, sl = idx % kFR;
+#pragma unroll
+      for (int f = 0; f < 7; ++f) {
+        float val = 0.0f;
+        if (in[u]) {
+          const double raw = f == 5 ? residual_of(n, ii[u], v[u][0], v[u][1], v[u][2], v[u][3],
+                                                  v[u][4], v[u][5], um2[u], um1[u], v[u][6],
+                                                  up1[u], up2[u])
+                                    : v[u][f];
+          val = standardised(raw, nm.mean[f], nm.scale[f]);
+        }
+        // the FP32 value first, then bf16 (as features_kernel, which stores
+        // the FP32 value in between): without the barrier the compiler folds
+        // the two conversions into one correctly rounded FP64 -> bf16
+        // conversion, which differs from the double rounding where the FP32
+        // value is a bf16 tie
+        asm volatile("" : "+v"(val));
+        sH[sl * kFLD + f * 64 + r] = (bf16)val;
+      }
+    }
+  }
+  __syncthreads();
+  float* yS = reinterpret_cast<float*>(sH);  // patch row sl at yS[sl * kFLD / 2 + r]
+  network_tile<NW>(sH, W, p32, [&](int row, int col, float y) { yS[row * (kFLD / 2) + col] = y; });
+  __syncthreads();
+  for (int idx = tid; idx < 64 * kFR; idx += 64 * NW) {
+    const int r = idx / kFR, sl = idx % kFR;
+    const int64_t i = j * 64 + r, s = s0 + sl;
+    if (i < n && s < batch) {
+      const int64_t o = i * ld + s;
+      X0[o] = start_value(P6[o], mu, sigma, yS[sl * (kFLD / 2) + r]);
     }
   }
 }
@@ -582,9 +699,10 @@ int64_t param_count() {
   return L[kLayers - 1].b + L[kLayers - 1].out;
 }
 
-// Workspace: h1, h2, h3 [P, 512] (forward); then for training dY in dtype
-// [P, 64], two [512, P] transposes, two [P, 512] gradient buffers, a
-// [512, 512] weight transpose and the column-sum partials.
+// Workspace: h1, h2, h3 [P, WS_HIDDEN] (forward); then for training dY in
+// dtype [P, 64], two [WS_HIDDEN, P] transposes, two [P, WS_HIDDEN] gradient
+// buffers, a [WS_HIDDEN, WS_HIDDEN] weight transpose and the column-sum
+// partials.
 struct WsLayout {
   size_t h[3], dyT, ta, tb, ga, gb, wt, part, fwd_total, train_total;
 };
@@ -726,9 +844,9 @@ int32_t ws_infer(int64_t P, const void* X, const float* params32, const void* pa
   if (P < 1 || P > (int64_t(1) << 31) || (P + kFR - 1) / kFR > (int64_t(1) << 31) - 1)
     return BS_EINVAL;
   if (!al16(X) || !al16(params32) || !al16(paramsT) || !al16(Y)) return BS_EINVAL;
-  hipLaunchKernelGGL(mlp_infer_kernel, dim3((unsigned)((P + kFR - 1) / kFR)), dim3(kThreads), 0,
-                     static_cast<hipStream_t>(stream), P, static_cast<const bf16*>(X),
-                     static_cast<const bf16*>(paramsT), params32, Y);
+  hipLaunchKernelGGL(mlp_infer_kernel<kInferWaves>, dim3((unsigned)((P + kFR - 1) / kFR)),
+                     dim3(64 * kInferWaves), 0, static_cast<hipStream_t>(stream), P,
+                     static_cast<const bf16*>(X), static_cast<const bf16*>(paramsT), params32, Y);
   return hipGetLastError() == hipSuccess ? BS_OK : BS_ELAUNCH;
 }
 
@@ -815,6 +933,27 @@ int32_t ws_apply(int64_t n, int64_t batch, int64_t ld, const float* Y, const dou
   const dim3 grid((unsigned)((batch + 63) / 64), (unsigned)((n + 63) / 64));
   hipLaunchKernelGGL(apply_kernel, grid, dim3(256), 0, st, n, batch, ld, Y, uprev, mu_t, sigma_t,
                      x0);
+  return hipGetLastError() == hipSuccess ? BS_OK : BS_ELAUNCH;
+}
+
+int32_t ws_predict(int64_t n, int64_t batch, int64_t ld, const double* const planes[7],
+                   const float norm[14], const float* params32, const void* paramsT, float mu_t,
+                   float sigma_t, double* x0, void* stream) {
+  if (n < 1 || batch < 1 || ld < batch || planes == nullptr || norm == nullptr ||
+      !al16(params32) || !al16(paramsT) || x0 == nullptr)
+    return BS_EINVAL;
+  if ((n + 63) / 64 > 65535 || (batch + kFR - 1) / kFR > (int64_t(1) << 31) - 1) return BS_EINVAL;
+  Norm nm;
+  for (int f = 0; f < 7; ++f) {
+    if (planes[f] == nullptr || !(norm[7 + f] > 0.0f)) return BS_EINVAL;
+    nm.mean[f] = norm[f];
+    nm.scale[f] = norm[7 + f];
+  }
+  const dim3 grid((unsigned)((batch + kFR - 1) / kFR), (unsigned)((n + 63) / 64));
+  hipLaunchKernelGGL(predict_kernel<kInferWaves>, grid, dim3(64 * kInferWaves), 0,
+                     static_cast<hipStream_t>(stream), n, batch, ld, planes[0], planes[1],
+                     planes[2], planes[3], planes[4], planes[5], planes[6], nm,
+                     static_cast<const bf16*>(paramsT), params32, mu_t, sigma_t, x0);
   return hipGetLastError() == hipSuccess ? BS_OK : BS_ELAUNCH;
 }
 

@@ -23,9 +23,9 @@ from . import workloads as wl
 
 WS_F32, WS_BF16 = 1, 2
 OP_FORWARD, OP_TRAIN = 0, 1
-PATCH, NFEAT, IN, HIDDEN, OUT = 64, 7, 448, 512, 64
+PATCH, NFEAT, IN, HIDDEN, OUT = 64, 7, 448, 256, 64
 EXPORTED = ("ws_param_count", "ws_workspace_bytes", "ws_gemm_nt", "ws_convert", "ws_forward",
-            "ws_infer", "ws_backward", "ws_mse", "ws_adam", "ws_features", "ws_apply")
+            "ws_infer", "ws_backward", "ws_mse", "ws_adam", "ws_features", "ws_apply", "ws_predict")
 TORCH_DTYPE = {WS_F32: torch.float32, WS_BF16: torch.bfloat16}
 
 _lib = None
@@ -51,6 +51,8 @@ def load():
         "ws_features": (i32, [i32, i64, i64, i64, ctypes.c_void_p * 7, ctypes.c_float * 14, vp,
                               vp]),
         "ws_apply": (i32, [i64, i64, i64, vp, vp, f32, f32, vp, vp]),
+        "ws_predict": (i32, [i64, i64, i64, ctypes.c_void_p * 7, ctypes.c_float * 14, vp, vp, f32,
+                             f32, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -158,6 +160,18 @@ def apply(Y, uprev, mu_t, sigma_t, n, batch, x0=None, stream=None):
     return x0
 
 
+def predict_fused(planes, norm, p32, pT, mu_t, sigma_t, n, batch, x0=None, stream=None):
+    """features -> BF16 network -> x0 in one kernel (ws_predict); bitwise
+    apply(infer(features(WS_BF16, ...)))."""
+    ld = planes[6].shape[1]
+    x0 = torch.empty_like(planes[6]) if x0 is None else x0
+    arr = (ctypes.c_void_p * 7)(*[t.data_ptr() for t in planes])
+    nm = (ctypes.c_float * 14)(*[float(v) for v in norm])
+    _ok(load().ws_predict(n, batch, ld, arr, nm, _p(p32), _p(pT), float(mu_t), float(sigma_t),
+                          _p(x0), _st(stream)), "ws_predict")
+    return x0
+
+
 def init_params(seed=0):
     """Host-side initial parameters: W uniform in +-sqrt(6 / fan_in) (He),
     biases 0; returned as a float32 numpy vector in the ABI's layout."""
@@ -257,11 +271,11 @@ class WarmStart:
     def predict(self, diags, rhs, uprev, n, batch, x0=None, ws=None, X=None, Y=None):
         """x0 for a batch of pentadiagonal systems (device [n, ld] float64)."""
         planes = list(diags) + [rhs, uprev]
+        if self.dtype == WS_BF16:   # one fused launch
+            return predict_fused(planes, self.norm, self.p32, self.pT, self.mu_t, self.sigma_t,
+                                 n, batch, x0)
         X = features(self.dtype, planes, self.norm, n, batch, X)
-        if self.dtype == WS_BF16:
-            Y = infer(X, self.p32, self.pT, Y)
-        else:
-            Y = forward(self.dtype, X, self.p32, self.pT, Y, ws)
+        Y = forward(self.dtype, X, self.p32, self.pT, Y, ws)
         return apply(Y, uprev, self.mu_t, self.sigma_t, n, batch, x0)
 
 

@@ -296,7 +296,9 @@ def test_warmstart_symbols_and_host_checks(bs):
     names = set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", text, flags=re.M))
     assert names == set(wsm.EXPORTED), names
     lib = wsm.load()
-    assert wsm.param_count() == 448 * 512 + 512 + 2 * (512 * 512 + 512) + 64 * 512 + 64
+    H = 256   # 448 -> 256 -> 256 -> 256 -> 64
+    assert wsm.HIDDEN == H
+    assert wsm.param_count() == 448 * H + H + 2 * (H * H + H) + 64 * H + 64
     bad = ctypes.c_size_t(-1).value
     assert lib.ws_workspace_bytes(0, 3, 16) == bad and lib.ws_workspace_bytes(2, 1, 16) == bad
     assert lib.ws_workspace_bytes(1, 2, 16) > lib.ws_workspace_bytes(0, 2, 16) > 0
@@ -320,6 +322,13 @@ def test_warmstart_symbols_and_host_checks(bs):
     norm = (ctypes.c_float * 14)(*([0.0] * 7 + [1.0] * 6 + [0.0]))                    # scale 0
     assert lib.ws_features(2, 64, 4, 4, planes, norm, a, None) == E
     assert lib.ws_apply(64, 4, 3, a, b, 0.0, 1.0, c, None) == E                       # ld < batch
+    good = (ctypes.c_float * 14)(*([0.0] * 7 + [1.0] * 7))
+    assert lib.ws_predict(64, 4, 4, planes, norm, a, b, 0.0, 1.0, c, None) == E      # scale 0
+    assert lib.ws_predict(64, 4, 3, planes, good, a, b, 0.0, 1.0, c, None) == E      # ld < batch
+    assert lib.ws_predict(64, 4, 4, planes, good, mis, b, 0.0, 1.0, c, None) == E    # misaligned
+    assert lib.ws_predict(64, 4, 4, planes, good, a, b, 0.0, 1.0, None, None) == E   # no x0
+    nul = (ctypes.c_void_p * 7)(*([_fake(k) for k in range(6)] + [None]))
+    assert lib.ws_predict(64, 4, 4, nul, good, a, b, 0.0, 1.0, c, None) == E         # no u_prev
 
 
 def test_stream_probe_rejections_on_host(bs):

@@ -144,6 +144,37 @@ def test_features_and_start_vector(dt, n, batch, ld):
     assert np.array_equal(wl.deinterleave(x0.cpu().numpy(), batch), ref)
 
 
+@pytest.mark.parametrize("n,batch,ld", [(4096, 16, 16), (70, 5, 64), (200, 130, 136),
+                                        (4096, 4096, 4096)])
+def test_fused_predict_matches_separate_kernels(n, batch, ld):
+    """features -> network -> start vector in one kernel against the three
+    separate kernels (features in BF16, fused inference, apply): x0 bitwise
+    equal, with slots outside the matrix and the padding systems NaN, ragged
+    row and system counts, and the learned-start workload's size."""
+    rng = np.random.default_rng(n + batch + 1)
+    arrs = [rng.normal(size=(batch, n)) for _ in range(7)]
+    for k, (i, j) in {0: (0, 2), 1: (0, 1), 3: (n - 1, n), 4: (n - 2, n)}.items():
+        arrs[k][:, i:j] = np.nan
+    norm = [0.1, -0.2, 3.0, 0.5, -1.0, 0.25, 0.0] + [1.5, 2.0, 0.5, 1.0, 4.0, 0.75, 1.0]
+    planes = [dev(wl.interleave(a, ld, fill=np.nan), torch.float64) for a in arrs]
+    p, _, _ = _problem(1, 23)
+    p32 = dev(p)
+    pT = wsm.convert(p32, wsm.WS_BF16)
+    say(f"fused predict n={n} batch={batch} ld={ld}")
+    X = wsm.features(wsm.WS_BF16, planes, norm, n, batch)
+    x_sep = wsm.apply(wsm.infer(X, p32, pT), planes[6], 0.3, 1.7, n, batch)
+    x_fused = torch.full_like(planes[6], 7.0)
+    wsm.predict_fused(planes, norm, p32, pT, 0.3, 1.7, n, batch, x_fused)
+    torch.cuda.synchronize()
+    a, b = x_fused[:, :batch], x_sep[:, :batch]
+    bad = (a != b).nonzero()
+    say(f"  mismatches {bad.shape[0]}, max |diff| {(a - b).abs().max().item():.3e}, "
+        f"first rows/systems {bad[:8].tolist()}")
+    assert torch.equal(a, b)
+    if ld > batch:
+        assert (x_fused[:, batch:] == 7.0).all()    # padding systems untouched
+
+
 def test_learned_start_reduces_sip_iterations():
     """Train on the x-sweeps of the first 24 steps of a 256 x 256 ADI run,
     then start SIP-HB on the 8 steps after them from zero, from the previous
