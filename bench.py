@@ -665,6 +665,18 @@ def profile_rows():
         lambda: wsm.forward(wsm.WS_BF16, X, net.p32, net.pT, Y, wsf), k=3)
     rep("warm-start fused inference, 262144 patches",
         lambda: wsm.infer(X, net.p32, net.pT, Y), k=3)
+    del X, Y, wsf
+    g = torch.Generator(device="cuda").manual_seed(3)
+    planes = [torch.rand((4096, 4096), dtype=torch.float64, device="cuda", generator=g)
+              for _ in range(7)]
+    x0 = torch.empty_like(planes[6])
+    rep("warm-start prediction (features, network, start vector), 4096 x 4096",
+        lambda: wsm.predict_fused(planes, [0.0] * 7 + [1.0] * 7, net.p32, net.pT, 0.0, 1.0,
+                                  4096, 4096, x0), k=3)
+    Xf = wsm.features(wsm.WS_BF16, planes, [0.0] * 7 + [1.0] * 7, 4096, 4096)
+    rep("warm-start separate features and start vector, 4096 x 4096",
+        lambda: wsm.apply(wsm.infer(Xf, net.p32, net.pT), planes[6], 0.0, 1.0, 4096, 4096, x0),
+        k=2)
 
 
 def summarize_stats(csv_dir, out_path, title, command):
