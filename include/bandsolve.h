@@ -266,13 +266,18 @@ int32_t band_solve_adi(int32_t kind, int64_t n, int64_t batch, int64_t ld, doubl
                        size_t ws_bytes, void* stream);
 
 /* Mixed-precision NPDM / NTDM with iterative refinement.  The matrix and rhs
- * are FP64; the elimination reads an FP32 copy of them (half the bytes per
- * sweep), and FP64 residuals on the original matrix correct the result:
- *     A32 = fl32(A); x = 0; r = rhs
- *     repeat: solve A32 d = fl32(r) (fused band_solve, BS_F32); x += d;
+ * are FP64; the solves run in reduced precision and FP64 residuals on the
+ * matrix correct the result:
+ *     x = 0; r = rhs
+ *     repeat: solve A d = r in reduced precision; x += d;
  *             r = rhs - A x (FP64)
  *     until ||r||_inf < tol ||rhs||_inf, per system, or max_steps solves.
- * Refinement of this kind converges when cond(A) times the FP32 rounding
+ * With the compact FP32 state (BS_OPT_F32_STATE = 1, n <= 4096) each solve
+ * is the split kernel with FP32 per-row state on the FP64 A and r (FP64
+ * pivots; no FP32 copy of A is made) and adds d into x as it stores it.
+ * Otherwise (longer systems, or BS_OPT_F32_STATE = 0) A32 = fl32(A) is
+ * formed once and each step solves A32 d = fl32(r) with the fused FP32
+ * band_solve.  Refinement converges when cond(A) times the FP32 rounding
  * unit is well below 1 (diagonally dominant ADI sweeps: a few steps to
  * 1e-12).  Systems that have converged are frozen; once all have, the
  * remaining launches return at once (no host synchronisation, so the call
@@ -281,8 +286,8 @@ int32_t band_solve_adi(int32_t kind, int64_t n, int64_t batch, int64_t ld, doubl
  * x is output only and must not alias rhs.  n >= 8.
  * steps[s]: FP32 solves the system took; relres[s]: final
  * ||r||_inf / ||rhs||_inf (0 for rhs = 0); info[s]: 0, -1 (not converged
- * within max_steps), -2 (residual not finite), i+1 (bad pivot of the FP32
- * elimination at row i) or -4 (as band_solve).
+ * within max_steps), -2 (residual not finite), i+1 (bad pivot of the
+ * reduced-precision solve at row i) or -4 (as band_solve).
  * workspace: bs_workspace_bytes(BS_OP_REFINE, kind, BS_F64, ...) bytes,
  * 256-byte aligned, zero before its first use (as for band_solve; the call
  * leaves its counters at zero again). */

@@ -91,6 +91,8 @@ Route route(int kind, int dtype, int64_t n, int64_t ld, int* idx) {
 
 }  // namespace
 
+bool f32_compact_state() { return g_f32_state.load() != 0 && g_direct_path.load() != 1; }
+
 bool direct_supported(int kind, int dtype, int64_t n, int64_t ld) {
   int idx;
   return route(kind, dtype, n, ld, &idx) != Route::kNone;

@@ -89,12 +89,21 @@ hipError_t launch_part(int kind, int idx, int dtype, int64_t n, int64_t batch, i
 // part_pick: the preferred one if it covers n, else the first that does, -1
 // if none), its workspace, leading counter bytes and launch.
 int compact_count(int kind);
-int compact_pick(int kind, int idx, int64_t n, int64_t ld);
+int compact_pick(int kind, int idx, int64_t n, int64_t ld, int dtype = 1);
 size_t compact_workspace_bytes(int kind, int idx, int64_t n, int64_t batch);
 size_t compact_counter_bytes(int kind, int idx, int64_t n, int64_t batch);
 hipError_t launch_compact(int kind, int idx, int64_t n, int64_t batch, int64_t ld,
                           const void* const dg[5], const void* y, void* x, int32_t* info,
                           double* ws, hipStream_t st, const int32_t* skip = nullptr);
+// The compact-state kernels on FP64 storage (FP64 matrix, right-hand side
+// and x; FP32 per-row state, so x has the compact state's FP32-level error):
+// the refinement's solves.  acc: x += the solution instead of x = (the
+// variant and workspace as compact_pick / compact_workspace_bytes); act
+// (nullable): systems with act[s] == 0 are not touched (x, info).
+hipError_t launch_compact_f64(int kind, int idx, int64_t n, int64_t batch, int64_t ld,
+                              const double* const dg[5], const double* y, double* x,
+                              int32_t* info, double* ws, hipStream_t st, const int32_t* skip,
+                              bool acc, const int32_t* act);
 // MNPDM (outer diagonals as a per-system list) on the split kernels: the
 // variant to use for (n, ld) (-1 if none) and its launch; the workspace is
 // part_workspace_bytes(5, idx, n, batch).
@@ -117,6 +126,8 @@ hipError_t launch_long_path(int kind, int dtype, int64_t n, int64_t batch, int64
                             double* ws, hipStream_t st, const int32_t* skip = nullptr);
 
 // ---- mixed-precision refinement (refine.hip) ------------------------------
+// BS_OPT_F32_STATE != 0 (abi.hip): the compact chunk state is in use.
+bool f32_compact_state();
 size_t refine_workspace_bytes(int kind, int64_t n, int64_t batch, int64_t ld);
 hipError_t launch_refine(int kind, int64_t n, int64_t batch, int64_t ld, const double* const dg[5],
                          const double* rhs, double* x, double tol, int32_t max_steps,

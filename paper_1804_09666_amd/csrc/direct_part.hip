@@ -61,8 +61,10 @@ using namespace split;
 // instead of being loaded (the ADI sweep of the PDE, see assemble_chunk).
 // TS: type of the per-row chunk state: double, or float for the compact
 // state of FP32 storage (chunk_pd_rows / chunk_td_rows on float arrays).
+// ACC (compact state, FP64 x only): x += the solution instead of x = (a
+// refinement step's correction).
 template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false,
-          bool ASM = false, typename TS = double>
+          bool ASM = false, typename TS = double, bool ACC = false>
 __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void part_kernel(
     int64_t n, int64_t batch, int64_t ld, const TIO* __restrict__ E,
     const TIO* __restrict__ C, const TIO* __restrict__ D,
@@ -70,14 +72,16 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
     const TIO* __restrict__ Y, TIO* __restrict__ X,
     int32_t* __restrict__ info, double* __restrict__ xch,
     unsigned* __restrict__ cnt, int T, const int32_t* __restrict__ skip, Outer ol,
-    double rcoef, uint64_t wait_ticks, double* __restrict__ rws, int64_t rpitch, int redo_gaveup) {
+    double rcoef, uint64_t wait_ticks, double* __restrict__ rws, int64_t rpitch, int redo_gaveup,
+    const int32_t* __restrict__ act) {
   constexpr int NB = KIND == 5 ? 2 : 1;
   constexpr int RS = kRecSz<NB>;
   constexpr int RT = M * PW;
   static_assert((PW & (PW - 1)) == 0 && (TMAX & (TMAX - 1)) == 0 && M >= 4, "shape");
   static_assert(G <= 32 && TMAX <= 32, "masks");
   static_assert(G >= 16, "the counter region is sized for groups of at least 16 systems");
-  static_assert(sizeof(TS) == 8 || (sizeof(TIO) == 4 && !ASM && !SPARSE), "compact state");
+  static_assert(sizeof(TS) == 8 || (!ASM && !SPARSE), "compact state");
+  static_assert(!ACC || (sizeof(TS) == 4 && sizeof(TIO) == 8), "accumulating store");
   if (skip != nullptr && *skip) return;  // uniform: a refinement loop has finished
   __shared__ double s_node[(PW - 1) * G * RS];
   __shared__ double s_gnode[(TMAX > 1 ? TMAX - 1 : 1) * G * RS];
@@ -102,7 +106,9 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
     }
   }
   const int64_t s = grp * G + g;
-  const bool live = s < batch;
+  // act (nullable): systems with act[s] == 0 are left alone (no loads, no
+  // stores, no info)
+  const bool live = s < batch && (act == nullptr || act[s] != 0);
   const int64_t r0 = (tile * PW + j) * M;
   if (tid < G) s_bad[tid] = kBadNone;
   if (tid == 0) s_timeout = 0;
@@ -113,7 +119,10 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
   bool list_bad = false;
   // rows in flight: at most 63 loads per wave; at two waves per SIMD the
   // register budget halves
-  constexpr int DPF = WPE == 1 ? (KIND == 5 && !SPARSE ? 10 : 15) : (KIND == 5 ? 6 : 9);
+  // (compact state: 8 rows of FP32 loads measured best, 43.6 against 44.7 us
+  // for 10 on the PD sweep batch; 6 rows of FP64 loads keep its registers)
+  constexpr int DPF = sizeof(TS) == 4 ? (sizeof(TIO) == 4 ? 8 : 6)
+                      : WPE == 1 ? (KIND == 5 && !SPARSE ? 10 : 15) : (KIND == 5 ? 6 : 9);
   if constexpr (ASM) {
     stream_assemble<KIND, M>(n, ld, s, live, r0, reinterpret_cast<const double*>(Y), rcoef, p,
                              v, w, bad);
@@ -243,7 +252,10 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
 
   // ---- 3. back down the tile's tree, then x = p - V x_L - W x_R ---------
   tree_down<NB, PW, G>(xl, xr, j, g, s_node);
-  write_chunk<NB, M>(n, ld, s, write, r0, 0, p, v, w, xl, xr, X);
+  if constexpr (sizeof(TS) == 4)
+    write_chunk<NB, M, TIO, ACC>(n, ld, s, write, r0, 0, p, v, w, xl, xr, X);
+  else
+    write_chunk<NB, M>(n, ld, s, write, r0, 0, p, v, w, xl, xr, X);
   // info at the device-coherent level: the last tile to leave may overwrite
   // it from another XCD
   if (j == 0 && tile == 0 && live && !s_timeout && !redo)
@@ -285,7 +297,13 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
     const int64_t plane = n * rpitch;
     const seq::Planes P{rws, rws + plane, rpitch, rws + (KIND == 5 ? 2 : 1) * plane, rpitch, s};
     const int64_t sb = seq::solve<KIND>(
-        n, fetch, P, [&](int64_t i, double xv) { X[i * ld + s] = (TIO)xv; },
+        n, fetch, P,
+        [&](int64_t i, double xv) {
+          if constexpr (ACC)
+            X[i * ld + s] = X[i * ld + s] + xv;
+          else
+            X[i * ld + s] = (TIO)xv;
+        },
         [&](int64_t i) { return ((tiles_mask >> (uint32_t)(i / RT)) & 1u) != 0u; });
     st_coherent_i32(&info[s], sb < 0 ? 0 : (int32_t)(sb + 1));
   };
@@ -578,23 +596,23 @@ PartWs part_ws(int kind, int64_t n, int64_t batch, int64_t M, int64_t PW, int64_
 }
 
 template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false,
-          bool ASM = false, typename TS = double>
+          bool ASM = false, typename TS = double, bool ACC = false>
 hipError_t launch_cfg(int64_t n, int64_t batch, int64_t ld, const void* const* dg,
                       const void* y, void* x, int32_t* info, double* ws, hipStream_t st,
                       const int32_t* skip, Outer ol = Outer{0, nullptr, nullptr, nullptr},
-                      double rcoef = 0.0) {
+                      double rcoef = 0.0, const int32_t* act = nullptr) {
   constexpr int RT = M * PW;
   const int T = (int)((n + RT - 1) / RT);
   const int64_t groups = (batch + G - 1) / G;
   const PartWs W = part_ws(KIND, n, batch, M, PW, G);
   unsigned* cnt = (T > 1) ? reinterpret_cast<unsigned*>(ws) : nullptr;
   double* xch = (T > 1) ? ws + W.xch : nullptr;
-  hipLaunchKernelGGL((part_kernel<TIO, KIND, M, PW, G, TMAX, WPE, SPARSE, ASM, TS>),
+  hipLaunchKernelGGL((part_kernel<TIO, KIND, M, PW, G, TMAX, WPE, SPARSE, ASM, TS, ACC>),
                      dim3((unsigned)(groups * T)), dim3(G * PW), 0, st, n, batch, ld,
                      (const TIO*)dg[0], (const TIO*)dg[1], (const TIO*)dg[2], (const TIO*)dg[3],
                      (const TIO*)dg[4], (const TIO*)y, (TIO*)x, info, xch, cnt, T, skip, ol,
                      rcoef, (uint64_t)g_exchange_wait_us.load() * 100u, ws + W.planes,
-                     ws_ld(batch), (int)(x != y));
+                     ws_ld(batch), (int)(x != y), act);
   return hipGetLastError();
 }
 
@@ -752,11 +770,11 @@ int compact_count(int kind) {
   return k;
 }
 
-int compact_pick(int kind, int idx, int64_t n, int64_t ld) {
+int compact_pick(int kind, int idx, int64_t n, int64_t ld, int dtype) {
   const Variant* v = find_compact(kind, idx);
-  if (v && covers(v, n, ld, 1)) return idx;
+  if (v && covers(v, n, ld, dtype)) return idx;
   for (int k = 0; k < compact_count(kind); ++k)
-    if (covers(find_compact(kind, k), n, ld, 1)) return k;
+    if (covers(find_compact(kind, k), n, ld, dtype)) return k;
   return -1;
 }
 
@@ -786,6 +804,28 @@ hipError_t launch_compact(int kind, int idx, int64_t n, int64_t batch, int64_t l
   BS_PC(5, 64, 8, 32, 4, 1) BS_PC(5, 64, 8, 32, 8, 1)
   BS_PC(3, 64, 8, 32, 4, 1) BS_PC(3, 64, 8, 32, 8, 1)
 #undef BS_PC
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_compact_f64(int kind, int idx, int64_t n, int64_t batch, int64_t ld,
+                              const double* const dg[5], const double* y, double* x,
+                              int32_t* info, double* ws, hipStream_t st, const int32_t* skip,
+                              bool acc, const int32_t* act) {
+  const Variant* v = find_compact(kind, idx);
+  if (!v) return hipErrorInvalidValue;
+  const void* const* d = reinterpret_cast<const void* const*>(dg);
+#define BS_PF(K, MM, PP, GG, TT, WW)                                                        \
+  if (v->kind == K && v->M == MM && v->PW == PP && v->G == GG && v->TMAX == TT &&           \
+      v->WPE == WW)                                                                         \
+    return acc ? launch_cfg<double, K, MM, PP, GG, TT, WW, false, false, float, true>(      \
+                     n, batch, ld, d, y, x, info, ws, st, skip, Outer{0, nullptr, nullptr,  \
+                     nullptr}, 0.0, act)                                                    \
+               : launch_cfg<double, K, MM, PP, GG, TT, WW, false, false, float, false>(     \
+                     n, batch, ld, d, y, x, info, ws, st, skip, Outer{0, nullptr, nullptr,  \
+                     nullptr}, 0.0, act);
+  BS_PF(5, 64, 8, 32, 4, 1) BS_PF(5, 64, 8, 32, 8, 1)
+  BS_PF(3, 64, 8, 32, 4, 1) BS_PF(3, 64, 8, 32, 8, 1)
+#undef BS_PF
   return hipErrorInvalidValue;
 }
 

@@ -1,12 +1,16 @@
-// refine.hip -- mixed-precision direct solve with FP64 iterative refinement.
+// refine.hip -- low-precision direct solves with FP64 iterative refinement.
 //
-// The FP32-storage solve (FP32 diagonals, right-hand side and result; all
-// arithmetic, pivot recurrences included, in FP64) moves half the bytes of the
-// FP64 solve.  Its error comes from rounding A and the data to FP32; FP64
-// residuals on the original A remove it:
-//   A32 = fl32(A), r = b, x = 0
-//   repeat: solve A32 d = fl32(r);  x += d;  r = b - A x (FP64)
+//   r = b, x = 0
+//   repeat: solve A d = r in low precision;  x += d;  r = b - A x (FP64)
 //   until ||r||_inf < tol ||b||_inf per system (masked), or max_steps.
+// Two ways to solve in low precision:
+//  - compact (the sweep's systems, n <= 4096, the default FP32 state): the
+//    split kernel with FP32 per-row state reads the FP64 A and r directly (no
+//    FP32 copy of A is made) and adds d into x as it stores it; the residual
+//    pass writes r in FP64 and, on the first pass, takes ||b||.
+//  - FP32 storage (longer systems, or BS_OPT_F32_STATE = 0): A32 = fl32(A)
+//    once, then solve A32 d = fl32(r) with the FP32-storage kernels and add d
+//    in a separate pass.
 // All steps run on the stream without host round-trips: a device flag makes
 // the remaining launches return at once when every system has converged.
 #include "bs_internal.h"
@@ -73,18 +77,23 @@ __global__ __launch_bounds__(kBlock) void update_kernel(
 // r32 = fl32(r), |r|_inf per system.  Work item q = (s, part) walks rows
 // part, part + P, ... of system s; consecutive items are consecutive
 // systems, so each row access of a wave is one contiguous segment.
-template <int KIND>
+// TR: type of the stored residual (float for the FP32-storage solve, double
+// for the compact one).  BNORM: also |b|_inf into bmax.  act (nullable):
+// systems with act[s] == 0 are skipped.
+template <int KIND, typename TR, bool BNORM>
 __global__ __launch_bounds__(kBlock) void residual_kernel(
     int64_t n, int64_t batch, int64_t ld, const double* __restrict__ E,
     const double* __restrict__ C, const double* __restrict__ D, const double* __restrict__ A,
     const double* __restrict__ B, const double* __restrict__ b, const double* __restrict__ x,
-    float* __restrict__ r32, unsigned long long* __restrict__ rmax, int64_t parts,
-    const int32_t* __restrict__ done) {
+    TR* __restrict__ r32, unsigned long long* __restrict__ rmax, int64_t parts,
+    const int32_t* __restrict__ done, unsigned long long* __restrict__ bmax,
+    const int32_t* __restrict__ act) {
   if (*done) return;
   for (int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x; q < batch * parts;
        q += (int64_t)gridDim.x * kBlock) {
     const int64_t s = q % batch, part = q / batch;
-    double m = 0.0;
+    if (act != nullptr && !act[s]) continue;
+    double m = 0.0, mb = 0.0;
     for (int64_t i = part; i < n; i += parts) {
       const int64_t o = i * ld + s;
       double ax = D[o] * x[o];
@@ -94,12 +103,18 @@ __global__ __launch_bounds__(kBlock) void residual_kernel(
         if (i >= 2) ax = fma(E[o], x[o - 2 * ld], ax);
         if (i + 2 < n) ax = fma(B[o], x[o + 2 * ld], ax);
       }
-      const double r = b[o] - ax;
-      r32[o] = (float)r;
+      const double bv = b[o];
+      const double r = bv - ax;
+      r32[o] = (TR)r;
       const double ar = fabs(r);
       m = (ar > m || ar != ar) ? ar : m;  // a NaN residual stays visible
+      if (BNORM) {
+        const double ab = fabs(bv);
+        mb = (ab > mb || ab != ab) ? ab : mb;
+      }
     }
     atomic_max_nonneg(&rmax[s], m);
+    if (BNORM) atomic_max_nonneg(&bmax[s], mb);
   }
 }
 
@@ -156,28 +171,43 @@ __global__ void init_flags_kernel(int64_t batch, int32_t* active, unsigned long 
   if (blockIdx.x == 0 && threadIdx.x == 0) *done = 0;
 }
 
+// The compact path is taken for the sweep's systems (a compact variant
+// covers n and ld with FP64 storage) unless the FP32 state is off.
+int compact_idx(int kind, int64_t n, int64_t ld) {
+  return f32_compact_state() ? compact_pick(kind, 0, n, ld, 0) : -1;
+}
+
 struct Layout {
-  int nplanes;
-  int64_t plane;  // floats per plane
-  size_t a32, r32, d32, act, sinfo, rmax, bmax, done, solver, total;  // byte offsets
+  int nplanes, cidx;
+  int64_t plane;  // elements per plane
+  size_t solver, a32, r32, r64, d32, act, sinfo, rmax, bmax, done, total;  // byte offsets
 };
 
+// The solver's workspace comes first, so its meeting counters sit at the
+// same bytes on either path (a workspace may serve both in turn).
 Layout layout(int kind, int64_t n, int64_t batch, int64_t ld) {
   Layout L;
   L.nplanes = kind == 5 ? 5 : 3;
   L.plane = n * ld;
+  L.cidx = compact_idx(kind, n, ld);
   auto up = [](size_t v) { return (v + 255) / 256 * 256; };
   size_t o = 0;
-  L.a32 = o;  o = up(o + (size_t)L.nplanes * L.plane * 4);
-  L.r32 = o;  o = up(o + (size_t)L.plane * 4);
-  L.d32 = o;  o = up(o + (size_t)L.plane * 4);
+  L.solver = o;
+  o = up(o + (L.cidx >= 0 ? compact_workspace_bytes(kind, L.cidx, n, batch)
+                          : direct_ws_bytes(kind, 1, n, batch, ld)));
+  L.a32 = L.r32 = L.r64 = L.d32 = o;
+  if (L.cidx >= 0) {
+    L.r64 = o;  o = up(o + (size_t)L.plane * 8);
+  } else {
+    L.a32 = o;  o = up(o + (size_t)L.nplanes * L.plane * 4);
+    L.r32 = o;  o = up(o + (size_t)L.plane * 4);
+    L.d32 = o;  o = up(o + (size_t)L.plane * 4);
+  }
   L.act = o;  o = up(o + (size_t)batch * 4);
   L.sinfo = o; o = up(o + (size_t)batch * 4);
   L.rmax = o; o = up(o + (size_t)batch * 8);
   L.bmax = o; o = up(o + (size_t)batch * 8);
   L.done = o; o = up(o + 4);
-  L.solver = o;
-  o = up(o + direct_ws_bytes(kind, 1, n, batch, ld));
   L.total = o;
   return L;
 }
@@ -201,20 +231,14 @@ hipError_t launch_refine(int kind, int64_t n, int64_t batch, int64_t ld, const d
   char* base = static_cast<char*>(ws);
   float* a32 = reinterpret_cast<float*>(base + L.a32);
   float* r32 = reinterpret_cast<float*>(base + L.r32);
+  double* r64 = reinterpret_cast<double*>(base + L.r64);
   float* d32 = reinterpret_cast<float*>(base + L.d32);
   int32_t* act = reinterpret_cast<int32_t*>(base + L.act);
   int32_t* sinfo = reinterpret_cast<int32_t*>(base + L.sinfo);
   unsigned long long* rmax = reinterpret_cast<unsigned long long*>(base + L.rmax);
   unsigned long long* bmax = reinterpret_cast<unsigned long long*>(base + L.bmax);
   int32_t* done = reinterpret_cast<int32_t*>(base + L.done);
-  void* sws = base + L.solver;
-
-  // planes of A in the order of the FP32 copy: PD e c d a b, TD c d a
-  Planes pl;
-  int np = 0;
-  for (int k = 0; k < 5; ++k) pl.p[k] = nullptr;
-  for (int k = 0; k < 5; ++k)
-    if (kind == 5 || (k >= 1 && k <= 3)) pl.p[np++] = dg[k];
+  double* sws = reinterpret_cast<double*>(base + L.solver);
 
   hipLaunchKernelGGL(init_flags_kernel, dim3(grid_for(batch)), dim3(kBlock), 0, st, batch, act,
                      rmax, bmax, steps, relres, done);
@@ -224,11 +248,45 @@ hipError_t launch_refine(int kind, int64_t n, int64_t batch, int64_t ld, const d
   // (256 CUs x 32 waves x 64 lanes), at least one row each
   int64_t parts = ((int64_t(1) << 19) + batch - 1) / batch;
   if (parts > n) parts = n;
+  const dim3 rgrid(grid_for(batch * parts));
+  auto status = [&](int32_t step) {
+    hipLaunchKernelGGL(status_kernel, dim3(1), dim3(1024), 0, st, batch, tol, rmax, bmax, sinfo,
+                       act, steps, relres, info, done, step, (int32_t)(step == max_steps - 1));
+    return hipGetLastError();
+  };
+
+  if (L.cidx >= 0) {
+    // compact solves on the FP64 data: x = solve(b), then x += solve(r) for
+    // the systems still refining
+    for (int32_t step = 0; step < max_steps; ++step) {
+      e = launch_compact_f64(kind, L.cidx, n, batch, ld, dg, step == 0 ? rhs : r64, x, sinfo, sws,
+                             st, done, step > 0, step > 0 ? act : nullptr);
+      if (e != hipSuccess) return e;
+#define BS_RES(K, BN)                                                                              \
+  hipLaunchKernelGGL((residual_kernel<K, double, BN>), rgrid, dim3(kBlock), 0, st, n, batch, ld,   \
+                     dg[0], dg[1], dg[2], dg[3], dg[4], rhs, x, r64, rmax, parts, done, bmax, act)
+      if (kind == 5) {
+        if (step == 0) BS_RES(5, true); else BS_RES(5, false);
+      } else {
+        if (step == 0) BS_RES(3, true); else BS_RES(3, false);
+      }
+#undef BS_RES
+      e = status(step);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+
+  // FP32 storage: planes of A in the order of the FP32 copy (PD e c d a b, TD c d a)
+  Planes pl;
+  int np = 0;
+  for (int k = 0; k < 5; ++k) pl.p[k] = nullptr;
+  for (int k = 0; k < 5; ++k)
+    if (kind == 5 || (k >= 1 && k <= 3)) pl.p[np++] = dg[k];
   hipLaunchKernelGGL(setup_kernel, dim3(grid_for(batch * parts)), dim3(kBlock), 0, st, n, batch,
                      ld, np, pl, a32, rhs, r32, x, bmax, parts);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-
   const void* d32planes[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   {
     int q = 0;
@@ -241,16 +299,14 @@ hipError_t launch_refine(int kind, int64_t n, int64_t batch, int64_t ld, const d
     hipLaunchKernelGGL(update_kernel, dim3(grid_for(n * batch)), dim3(kBlock), 0, st, n, batch,
                        ld, d32, x, act, done);
     if (kind == 5)
-      hipLaunchKernelGGL(residual_kernel<5>, dim3(grid_for(batch * parts)), dim3(kBlock), 0, st,
-                         n, batch, ld, dg[0], dg[1], dg[2], dg[3], dg[4], rhs, x, r32, rmax,
-                         parts, done);
+      hipLaunchKernelGGL((residual_kernel<5, float, false>), rgrid, dim3(kBlock), 0, st, n, batch,
+                         ld, dg[0], dg[1], dg[2], dg[3], dg[4], rhs, x, r32, rmax, parts, done,
+                         bmax, nullptr);
     else
-      hipLaunchKernelGGL(residual_kernel<3>, dim3(grid_for(batch * parts)), dim3(kBlock), 0, st,
-                         n, batch, ld, dg[0], dg[1], dg[2], dg[3], dg[4], rhs, x, r32, rmax,
-                         parts, done);
-    hipLaunchKernelGGL(status_kernel, dim3(1), dim3(1024), 0, st, batch, tol, rmax, bmax, sinfo,
-                       act, steps, relres, info, done, step, (int32_t)(step == max_steps - 1));
-    e = hipGetLastError();
+      hipLaunchKernelGGL((residual_kernel<3, float, false>), rgrid, dim3(kBlock), 0, st, n, batch,
+                         ld, dg[0], dg[1], dg[2], dg[3], dg[4], rhs, x, r32, rmax, parts, done,
+                         bmax, nullptr);
+    e = status(step);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -817,14 +817,15 @@ __device__ inline void write_chunk(int64_t n, int64_t ld, int64_t s, bool live, 
   }
 }
 
-// x from the compact (FP32) chunk state, in FP32.
-template <int NB, int M, typename TIO>
+// x from the compact (FP32) chunk state, in FP32.  ACC: the store adds the
+// value to what X holds (x += d of a refinement step, FP64 X).
+template <int NB, int M, typename TIO, bool ACC = false>
 __device__ inline void write_chunk(int64_t n, int64_t ld, int64_t s, bool live, int64_t r0,
                                    int64_t row_base,
                                    const float (&p)[M], const float (&v)[NB][M],
                                    const float (&w)[NB][M], const double (&xl)[NB],
                                    const double (&xr)[NB], TIO* __restrict__ X) {
-  static_assert(sizeof(TIO) == 4, "the compact state is for FP32 storage");
+  static_assert(!ACC || sizeof(TIO) == 8, "accumulation into FP64 x");
   const uint32_t row_bytes = (uint32_t)(ld * sizeof(TIO));
   const uint32_t off0 = (uint32_t)((r0 * ld + s) * (int64_t)sizeof(TIO));
   float fl[NB], fr[NB];
@@ -839,9 +840,13 @@ __device__ inline void write_chunk(int64_t n, int64_t ld, int64_t s, bool live, 
     float xv = p[r];
 #pragma unroll
     for (int k = 0; k < NB; ++k) xv = fmaf(-v[k][r], fl[k], fmaf(-w[k][r], fr[k], xv));
-    if (live && i < n)
-      __builtin_nontemporal_store(xv, reinterpret_cast<TIO*>(reinterpret_cast<char*>(X) + off0 +
-                                                              (uint32_t)r * row_bytes));
+    if (live && i < n) {
+      TIO* dst = reinterpret_cast<TIO*>(reinterpret_cast<char*>(X) + off0 + (uint32_t)r * row_bytes);
+      if constexpr (ACC)
+        *dst = *dst + (double)xv;
+      else
+        __builtin_nontemporal_store((TIO)xv, dst);
+    }
   }
 }
 

@@ -131,12 +131,22 @@ def test_workspace_query(bs):
     assert lib.bs_workspace_bytes(bs.OP_SOLVE, 5, bs.BS_F32, 4, batch, batch) == bad
     assert lib.bs_workspace_bytes(bs.OP_SIP, 5, bs.BS_F32, n, batch, batch) == bad
     assert lib.bs_workspace_bytes(bs.OP_REFINE, 5, bs.BS_F32, n, batch, batch) == bad
-    # refinement: FP32 copy of A (5 or 3 planes), r, d, per-system flags, solver
+    # refinement: the solver's workspace first, then (compact FP32 state, the
+    # default, n <= 4096) an FP64 residual plane, or (FP32 storage) the FP32
+    # copy of A (5 or 3 planes), r and d; then per-system flags
     for kind, planes in ((5, 5), (3, 3)):
         got = bs.workspace_bytes(bs.OP_REFINE, kind, 2048, batch)
-        assert got >= (planes + 2) * 2048 * batch * 4 + \
-            bs.workspace_bytes(bs.OP_SOLVE, kind, 2048, batch, bs.BS_F32)
+        assert got >= 2048 * batch * 8 + bs.workspace_bytes(bs.OP_SOLVE, kind, 2048, batch, bs.BS_F32)
         assert got % 256 == 0
+        bs.set_option(bs.OPT_F32_STATE, 0)
+        try:
+            got = bs.workspace_bytes(bs.OP_REFINE, kind, 2048, batch)
+            assert got >= (planes + 2) * 2048 * batch * 4 + \
+                bs.workspace_bytes(bs.OP_SOLVE, kind, 2048, batch, bs.BS_F32)
+        finally:
+            bs.set_option(bs.OPT_F32_STATE, 1)
+        got = bs.workspace_bytes(bs.OP_REFINE, kind, 40000, batch)   # beyond the compact kernels
+        assert got >= (planes + 2) * 40000 * batch * 4
     assert lib.bs_workspace_bytes(bs.OP_REFINE, 5, 0, 4, batch, batch) == bad
     bs.set_option(bs.OPT_DIRECT_PATH, bs.PATH_LANE)
     try:   # one lane per system has no FP32 kernel

@@ -251,18 +251,18 @@ def refine_check(ws, kind, batch, tol, err_bar, max_steps=8, ld=None):
 
 
 @pytest.mark.parametrize("kind", [5, 3])
-def test_refine_dominant(kind):
+def test_refine_dominant(kind, f32_state):
     ws = wl.dominant_batch(45, 1999, kind=kind, seed=51)
-    say(f"refine dominant kind={kind}")
+    say(f"refine dominant kind={kind} state={f32_state}")
     # kappa_inf of these matrices is below 10: error <= kappa * tol
     st = refine_check(ws, kind, 45, 1e-12, 1e-11, ld=64)
     assert st.max() <= 3
 
 
-def test_refine_config1_pde_to_1e10():
+def test_refine_config1_pde_to_1e10(f32_state):
     pd, td, _ = wl.config1()
     for kind, ws in ((5, pd), (3, td)):
-        say(f"refine config1 kind={kind} n=2048 batch=2048")
+        say(f"refine config1 kind={kind} n=2048 batch=2048 state={f32_state}")
         # r = 4 lines: kappa_inf <= 164, so relres < 1e-10 bounds the error by 2e-8
         st = refine_check(ws, kind, 2048, 1e-10, 2e-8)
         assert st.max() <= 3
@@ -277,7 +277,7 @@ def test_refine_long_stiff_lines():
     assert st.max() <= 6
 
 
-def test_refine_status_cases():
+def test_refine_status_cases(f32_state):
     ws = wl.dominant_batch(6, 300, kind=5, seed=61)
     ws["y"][2] = 0.0                   # zero rhs: x = 0 after one solve, relres 0
     ws["d"][4, 0] = 0.0                # bad pivot of the FP32 elimination at row 0
@@ -297,7 +297,7 @@ def test_refine_status_cases():
     assert (steps.cpu().numpy() == 1).all()
 
 
-def test_refine_graph_replay():
+def test_refine_graph_replay(f32_state):
     ws = wl.dominant_batch(64, 3000, kind=5, seed=71)
     t = to_device(ws, 64)
     xr, _ = oracle_direct(ws, 5)
