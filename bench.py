@@ -31,7 +31,10 @@ from paper_1804_09666_amd import workloads as wl  # noqa: E402
 
 N_ROWS = 2048
 BATCH = 2048
-R_ADI = 4.0
+R_ADI = 4.0           # r = tau / h^2 of the sweep batch (--r)
+SEED = None           # sweep-batch seed (--seed; None: the workloads' default)
+HB_S = (3, 4)         # SIP-HB steps of the SIP row (--hb-s)
+TOL = 1e-10           # SIP and refinement tolerance (--tol)
 PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
 PD_BYTES_PER_ROW = 56            # e, c, d, a, b, y read + x written (FP64)
 TD_BYTES_PER_ROW = 40            # c, d, a, y read + x written
@@ -148,6 +151,12 @@ def traffic_from_profile():
         return None
 
 
+def config1():
+    """The sweep batch (first y-sweep of the ADI step, n = batch = 2048)."""
+    return wl.config1(r=R_ADI, N=N_ROWS) if SEED is None else wl.config1(r=R_ADI, N=N_ROWS,
+                                                                        seed=SEED)
+
+
 def cpu_baseline(pd, samples):
     """The CPU leg: the FP64 oracle (serial NPDM per system, OpenMP over
     systems) timed on the host cores on the full sweep batch, repeated to
@@ -254,7 +263,7 @@ def precision_rows():
     KEYS = ("e", "c", "d", "a", "b", "y")
     out, got, samples = {}, {}, {}
     cases = []
-    pd, _, _ = wl.config1(r=R_ADI, N=N_ROWS)
+    pd, _, _ = config1()
     c1 = {k: torch.from_numpy(wl.interleave(pd[k], BATCH)).cuda() for k in KEYS}
     idx = [0, 97, 1024, 2047]
     cases.append(("adi_sweep_pd_n2048_b2048", c1, BATCH, N_ROWS,
@@ -294,7 +303,7 @@ def precision_rows():
         res = {}
 
         def ir():
-            _, st, rr, inf = bs.refine(diags_of(dev, 5), dev["y"], xir, batch=batch, tol=1e-10,
+            _, st, rr, inf = bs.refine(diags_of(dev, 5), dev["y"], xir, batch=batch, tol=TOL,
                                        max_steps=8, workspace=wir)
             res.update(st=st, rr=rr, inf=inf)
         msir = t_ms(ir)
@@ -404,12 +413,12 @@ def other_rows(pd, td):
     res = {}
 
     def sip():
-        xs, it, rr, si = bs.sip(diags_of(t, 5), t["y"], tol=1e-10, max_iter=200, s_L=3, s_U=4,
-                                factors=f, batch=BATCH)
+        xs, it, rr, si = bs.sip(diags_of(t, 5), t["y"], tol=TOL, max_iter=200, s_L=HB_S[0],
+                                s_U=HB_S[1], factors=f, batch=BATCH)
         res.update(it=it, rr=rr, si=si)
     ms = t_ms(sip, reps=1)
     its = res["it"].float()
-    out["sip_hb_pd"] = {"us": ms * 1e3, "hb_s": [3, 4], "tol": 1e-10,
+    out["sip_hb_pd"] = {"us": ms * 1e3, "hb_s": list(HB_S), "tol": TOL,
                         "iters_mean": float(its.mean()), "iters_max": int(res["it"].max()),
                         "us_per_iteration": ms * 1e3 / max(float(its.max()), 1.0),
                         "converged": int((res["si"] == 0).sum())}
@@ -607,7 +616,7 @@ def profile_rows():
     """Workload for `rocprofv3 --kernel-trace --stats`: a few launches of every
     hot-path row (the per-kernel durations are read from the profiler)."""
     KEYS = ("e", "c", "d", "a", "b", "y")
-    pd, td, _ = wl.config1(r=R_ADI, N=N_ROWS)
+    pd, td, _ = config1()
     t5 = {k: torch.from_numpy(wl.interleave(pd[k])).cuda() for k in KEYS}
     t3 = {k: torch.from_numpy(wl.interleave(td[k])).cuda() for k in ("c", "d", "a", "y")}
     D5, D3 = diags_of(t5, 5), diags_of(t3, 3)
@@ -712,7 +721,7 @@ def pmc_run():
     """Workload for the rocprofv3 counter passes: 5 PD solves of the sweep
     batch (rotating inputs) and one plain 1 GiB device copy whose HBM bytes
     are known, to scale FETCH_SIZE / WRITE_SIZE."""
-    pd, _, _ = wl.config1(r=R_ADI, N=N_ROWS)
+    pd, _, _ = config1()
     sets = [to_dev(pd) for _ in range(ROTATE)]
     x = torch.empty_like(sets[0]["y"])
     info = torch.empty(BATCH, dtype=torch.int32, device="cuda")
@@ -779,11 +788,17 @@ def summarize_pmc(fetch_dir, write_dir, out_path=TRAFFIC_FILE):
 
 
 def main():
+    global R_ADI, SEED, HB_S, TOL
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--r", type=float, default=R_ADI, help="r = tau / h^2 of the sweep batch")
+    ap.add_argument("--seed", type=int, default=None, help="seed of the sweep batch")
+    ap.add_argument("--hb-s", default=f"{HB_S[0]},{HB_S[1]}",
+                    help="HB steps s_L,s_U of the SIP row")
+    ap.add_argument("--tol", type=float, default=TOL, help="SIP and refinement tolerance")
     ap.add_argument("--no-rows", action="store_true", help="skip the other hot-path rows")
     ap.add_argument("--pmc-run", action="store_true",
                     help="only run the workload of the rocprofv3 counter passes")
@@ -795,6 +810,10 @@ def main():
                     metavar=("CSV_DIR", "OUT", "TITLE", "COMMAND"),
                     help="write a kernel-statistics table from rocprofv3 CSV output")
     args = ap.parse_args()
+    R_ADI, SEED, TOL = args.r, args.seed, args.tol
+    HB_S = tuple(int(v) for v in args.hb_s.split(","))
+    if len(HB_S) != 2 or min(HB_S) < 0 or not (TOL > 0):
+        raise SystemExit("--hb-s takes two non-negative integers s_L,s_U; --tol must be positive")
     if args.summarize_stats:
         summarize_stats(*args.summarize_stats)
         return
@@ -814,7 +833,7 @@ def main():
         sys.exit(2)
     torch.cuda.init()
     log(f"device: {torch.cuda.get_device_name(0)}")
-    pd, td, _ = wl.config1(r=R_ADI, N=N_ROWS)
+    pd, td, _ = config1()
     sets = [to_dev(pd) for _ in range(ROTATE)]
     xs = [torch.empty_like(sets[0]["y"]) for _ in range(ROTATE)]
     info = torch.empty(BATCH, dtype=torch.int32, device="cuda")
@@ -847,7 +866,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "adi_sweep_pd_n2048_b2048", "n": N_ROWS, "batch": BATCH,
-                   "r": R_ADI, "method": "NPDM (split-row band_solve)",
+                   "r": R_ADI, "seed": SEED, "hb_s": list(HB_S), "tol": TOL,
+                   "method": "NPDM (split-row band_solve)",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,

@@ -278,7 +278,17 @@ __global__ __launch_bounds__(kG * KPW) __attribute__((amdgpu_waves_per_eu(WPE, W
   for (int u = 0; u < NS; ++u) {
     if (u > 0) __syncthreads();  // every read of the previous step's exchanges is done
     const double m = residual<KM, KPW>(x, e, c, d, a, b, w, v, H, j, g, ext0, c0, c1, n);
-    if (live && m != 0.0) atomicMax(&s_m[u][g], (unsigned long long)__double_as_longlong(m));
+    {  // max over the wave's lanes of each system (lanes g, g + kG, ...: non-negative
+       // doubles, NaN included, order like their bit patterns), then one LDS
+       // atomic per system and wave
+      unsigned long long mb = live ? (unsigned long long)__double_as_longlong(m) : 0ull;
+#pragma unroll
+      for (int off = kG; off < 64; off <<= 1) {
+        const unsigned long long o = __shfl_xor(mb, off, 64);
+        mb = o > mb ? o : mb;
+      }
+      if ((tid & 63) < kG && mb != 0ull) atomicMax(&s_m[u][g], mb);
+    }
     lower_sweeps<KM, KPW>(KL, v, l1, l2, y, H, j, g);
     upper_sweeps<KM, KPW>(KU, y, u1, b, ru, z, H, j, g);
 #pragma unroll
