@@ -63,6 +63,8 @@ using namespace split;
 // state of FP32 storage (chunk_pd_rows / chunk_td_rows on float arrays).
 // ACC (compact state, FP64 x only): x += the solution instead of x = (a
 // refinement step's correction).
+constexpr int kListLds = 64;  // MNPDM list entries per system staged in LDS
+
 template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false,
           bool ASM = false, typename TS = double, bool ACC = false>
 __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE))) void part_kernel(
@@ -88,6 +90,11 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
   __shared__ double s_bnd[G * 2 * NB];
   __shared__ int s_bad[G];
   __shared__ int s_timeout;
+  // MNPDM: the block's lists in LDS (entry k of system g at [k * G + g]), up
+  // to kListLds entries per system; their used lengths and verdicts
+  __shared__ int32_t s_lrow[SPARSE ? kListLds * G : 1];
+  __shared__ double s_le[SPARSE ? kListLds * G : 1], s_lb[SPARSE ? kListLds * G : 1];
+  __shared__ int s_lcnt[SPARSE ? G : 1], s_lbad[SPARSE ? G : 1];
 
   const int tid = threadIdx.x;
   const int g = tid % G;
@@ -131,32 +138,82 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
 #pragma unroll
     for (int r = 0; r < M; ++r) eo[r] = bo[r] = 0.0;
     if constexpr (SPARSE) {
-      // every lane of the system checks the whole list (strictly ascending
-      // rows in [0, n), then only -1) and picks the entries of its rows
-      int64_t prev = -1;
-      bool ended = false;
-      for (int k = 0; k < ol.kmax; ++k) {
-        const int64_t lo = (int64_t)k * ld + s;
-        const int32_t rr = live ? ol.row[lo] : -1;
-        if (rr < 0) {
-          ended = true;
-          continue;
-        }
-        if (ended || rr >= n || rr <= prev) {
-          list_bad = true;
-          continue;
-        }
-        prev = rr;
+      // A list is valid when its used entries (row >= 0) come first, in
+      // strictly ascending rows in [0, n).  Up to kListLds entries per
+      // system, the block stages its systems' lists in LDS once (loads of
+      // consecutive systems), one lane per system checks its list there, and
+      // every lane finds its rows by binary search; longer lists are scanned
+      // in global memory by every lane.
+      auto pick = [&](int32_t rr, double ev, double bv) __attribute__((always_inline)) {
         const int64_t loc = rr - r0;
-        if (loc >= 0 && loc < M) {
-          const double ev = (rr >= 2) ? ol.e[lo] : 0.0;
-          const double bv = (rr <= n - 3) ? ol.b[lo] : 0.0;
+        ev = (rr >= 2) ? ev : 0.0;
+        bv = (rr <= n - 3) ? bv : 0.0;
+        // a select per register (an indexed store would put eo, bo in memory)
 #pragma unroll
-          for (int r = 0; r < M; ++r)
-            if (loc == r) {
-              eo[r] = ev;
-              bo[r] = bv;
+        for (int r = 0; r < M; ++r) {
+          eo[r] = (loc == r) ? ev : eo[r];
+          bo[r] = (loc == r) ? bv : bo[r];
+        }
+      };
+      if (ol.kmax <= kListLds) {  // uniform
+        for (int q = tid; q < ol.kmax * G; q += G * PW) {
+          const int k = q / G, gg = q % G;
+          const int64_t sg = grp * G + gg;
+          const bool lv = sg < batch && (act == nullptr || act[sg] != 0);
+          const int64_t lo = (int64_t)k * ld + sg;
+          s_lrow[q] = lv ? ol.row[lo] : -1;
+          s_le[q] = lv ? ol.e[lo] : 0.0;
+          s_lb[q] = lv ? ol.b[lo] : 0.0;
+        }
+        __syncthreads();
+        if (j == 0) {
+          int64_t prev = -1;
+          int cnt = 0;
+          bool ended = false, lbad = false;
+          for (int k = 0; k < ol.kmax; ++k) {
+            const int32_t rr = s_lrow[k * G + g];
+            if (rr < 0) {
+              ended = true;
+            } else if (ended || rr >= n || rr <= prev) {
+              lbad = true;
+            } else {
+              prev = rr;
+              cnt = k + 1;
             }
+          }
+          s_lcnt[g] = cnt;
+          s_lbad[g] = lbad;
+        }
+        __syncthreads();
+        list_bad = live && s_lbad[g] != 0;
+        if (live && !list_bad) {
+          int lo = 0, hi = s_lcnt[g];  // first entry with row >= r0
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_lrow[mid * G + g] < r0)
+              lo = mid + 1;
+            else
+              hi = mid;
+          }
+          for (int k = lo; k < s_lcnt[g] && s_lrow[k * G + g] < r0 + M; ++k)
+            pick(s_lrow[k * G + g], s_le[k * G + g], s_lb[k * G + g]);
+        }
+      } else {
+        int64_t prev = -1;
+        bool ended = false;
+        for (int k = 0; k < ol.kmax; ++k) {
+          const int64_t lo = (int64_t)k * ld + s;
+          const int32_t rr = live ? ol.row[lo] : -1;
+          if (rr < 0) {
+            ended = true;
+            continue;
+          }
+          if (ended || rr >= n || rr <= prev) {
+            list_bad = true;
+            continue;
+          }
+          prev = rr;
+          pick(rr, ol.e[lo], ol.b[lo]);
         }
       }
     }
@@ -265,6 +322,7 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
   // Lane g of the redoing tile solves system g; rows i with keep(i) are
   // written (all rows, or the rows of the tiles that gave up).
   auto redo_system = [&](uint32_t tiles_mask) {
+    int kc = 0;  // cursor in the staged list (MNPDM)
     auto fetch = [&](int64_t i) {
       const int64_t o = i * ld + s;
       seq::Row rw;
@@ -280,11 +338,19 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
         rw.y = (double)Y[o];
         rw.e = rw.b = 0.0;
         if constexpr (KIND == 5 && SPARSE) {
-          for (int k = 0; k < ol.kmax; ++k) {
-            const int64_t lo = (int64_t)k * ld + s;
-            if (ol.row[lo] == i) {
-              rw.e = (i >= 2) ? ol.e[lo] : 0.0;
-              rw.b = (i <= n - 3) ? ol.b[lo] : 0.0;
+          if (ol.kmax <= kListLds) {  // the staged list: rows come in ascending order
+            while (kc < s_lcnt[g] && s_lrow[kc * G + g] < i) ++kc;
+            if (kc < s_lcnt[g] && s_lrow[kc * G + g] == i) {
+              rw.e = (i >= 2) ? s_le[kc * G + g] : 0.0;
+              rw.b = (i <= n - 3) ? s_lb[kc * G + g] : 0.0;
+            }
+          } else {
+            for (int k = 0; k < ol.kmax; ++k) {
+              const int64_t lo = (int64_t)k * ld + s;
+              if (ol.row[lo] == i) {
+                rw.e = (i >= 2) ? ol.e[lo] : 0.0;
+                rw.b = (i <= n - 3) ? ol.b[lo] : 0.0;
+              }
             }
           }
         } else if constexpr (KIND == 5) {

@@ -255,12 +255,16 @@ def test_mnpdm_full_sweep_batch():
 
 
 @pytest.mark.parametrize("n,batch,ld,kmax", [(2048, 100, 128, 5), (3001, 33, 40, 9),
-                                             (5000, 7, 8, 4), (300, 64, 64, 0)])
+                                             (5000, 7, 8, 4), (300, 64, 64, 0),
+                                             (2048, 64, 64, 64), (2048, 48, 64, 100),
+                                             (1999, 40, 40, 300)])
 def test_mnpdm_random_lists(n, batch, ld, kmax, path):
     """Random sparse outer diagonals (K entries per system, some lists shorter
     than kmax): MNPDM against the oracle and bitwise against NPDM on the
-    zero-filled diagonals; several tiles, ragged batch, padded ld, and a
-    length beyond the split variants (one lane per system)."""
+    zero-filled diagonals; several tiles, ragged batch, padded ld, a length
+    beyond the split variants (one lane per system), and lists up to the 64
+    entries per system the split kernel stages in LDS and beyond (scanned in
+    global memory)."""
     rng = np.random.default_rng(n + batch)
     ws = wl.dominant_batch(batch, n, kind=5, seed=600 + n)
     rows = np.full((max(kmax, 1), batch), -1, dtype=np.int32)
