@@ -63,7 +63,8 @@ using namespace split;
 // state of FP32 storage (chunk_pd_rows / chunk_td_rows on float arrays).
 // ACC (compact state, FP64 x only): x += the solution instead of x = (a
 // refinement step's correction).
-constexpr int kListLds = 64;  // MNPDM list entries per system staged in LDS
+constexpr int kListScan = 8;  // MNPDM lists up to this length: scanned by every lane
+constexpr int kListLds = 64;  // longer ones up to this length: staged in LDS
 
 template <typename TIO, int KIND, int M, int PW, int G, int TMAX, int WPE, bool SPARSE = false,
           bool ASM = false, typename TS = double, bool ACC = false>
@@ -139,11 +140,13 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
     for (int r = 0; r < M; ++r) eo[r] = bo[r] = 0.0;
     if constexpr (SPARSE) {
       // A list is valid when its used entries (row >= 0) come first, in
-      // strictly ascending rows in [0, n).  Up to kListLds entries per
-      // system, the block stages its systems' lists in LDS once (loads of
-      // consecutive systems), one lane per system checks its list there, and
-      // every lane finds its rows by binary search; longer lists are scanned
-      // in global memory by every lane.
+      // strictly ascending rows in [0, n).  Lists of kListScan entries or
+      // fewer per system, and lists longer than kListLds, are scanned in
+      // global memory by every lane (a few loads, no barrier: 61.9 against
+      // 64.6 us with the LDS path at K = 2 on the sweep batch); in between,
+      // the block stages its systems' lists in LDS once (loads of consecutive
+      // systems), one lane per system checks its list there, and every lane
+      // finds its rows by binary search.
       auto pick = [&](int32_t rr, double ev, double bv) __attribute__((always_inline)) {
         const int64_t loc = rr - r0;
         ev = (rr >= 2) ? ev : 0.0;
@@ -155,7 +158,7 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
           bo[r] = (loc == r) ? bv : bo[r];
         }
       };
-      if (ol.kmax <= kListLds) {  // uniform
+      if (ol.kmax > kListScan && ol.kmax <= kListLds) {  // uniform
         for (int q = tid; q < ol.kmax * G; q += G * PW) {
           const int k = q / G, gg = q % G;
           const int64_t sg = grp * G + gg;
@@ -213,7 +216,17 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
             continue;
           }
           prev = rr;
-          pick(rr, ol.e[lo], ol.b[lo]);
+          const int64_t loc = rr - r0;
+          if (loc >= 0 && loc < M) {
+            const double ev = (rr >= 2) ? ol.e[lo] : 0.0;
+            const double bv = (rr <= n - 3) ? ol.b[lo] : 0.0;
+#pragma unroll
+            for (int r = 0; r < M; ++r)
+              if (loc == r) {
+                eo[r] = ev;
+                bo[r] = bv;
+              }
+          }
         }
       }
     }
@@ -338,7 +351,7 @@ __global__ __launch_bounds__(G * PW) __attribute__((amdgpu_waves_per_eu(WPE, WPE
         rw.y = (double)Y[o];
         rw.e = rw.b = 0.0;
         if constexpr (KIND == 5 && SPARSE) {
-          if (ol.kmax <= kListLds) {  // the staged list: rows come in ascending order
+          if (ol.kmax > kListScan && ol.kmax <= kListLds) {  // the staged list, rows ascending
             while (kc < s_lcnt[g] && s_lrow[kc * G + g] < i) ++kc;
             if (kc < s_lcnt[g] && s_lrow[kc * G + g] == i) {
               rw.e = (i >= 2) ? s_le[kc * G + g] : 0.0;

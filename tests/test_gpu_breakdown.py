@@ -149,9 +149,11 @@ def test_cancellation_at_chunk_start(kind):
     assert info_lane[5] == i + 1 and (np.delete(info_lane, 5) == 0).all()
 
 
-def test_mnpdm_redo():
+@pytest.mark.parametrize("kmax", [2, 20])
+def test_mnpdm_redo(kmax):
     """MNPDM on the split kernels: a zero diagonal at a chunk start is redone
-    sequentially with the outer entries taken from the list."""
+    sequentially with the outer entries taken from the list (kmax 2: each
+    lane scans the list; 20: the list staged in LDS, unused entries -1)."""
     batch, n = 16, 2048
     ws = wl.sweep_lines(wl.smooth_lines(batch, n, 45), 4.0, 2)
     ws = {k: np.array(ws[k]) for k in KEYS}
@@ -161,9 +163,9 @@ def test_mnpdm_redo():
     assert (ir == 0).all()
     t = to_device(ws, batch)
     ld = t["y"].shape[1]
-    rows = np.full((2, ld), -1, dtype=np.int32)
-    oe = np.zeros((2, ld))
-    ob = np.zeros((2, ld))
+    rows = np.full((kmax, ld), -1, dtype=np.int32)
+    oe = np.zeros((kmax, ld))
+    ob = np.zeros((kmax, ld))
     rows[0, :batch], ob[0, :batch] = 0, ws["b"][:, 0]
     rows[1, :batch], oe[1, :batch] = n - 1, ws["e"][:, n - 1]
     dev = lambda a: torch.from_numpy(a).cuda()

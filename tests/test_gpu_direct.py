@@ -257,7 +257,7 @@ def test_mnpdm_full_sweep_batch():
 @pytest.mark.parametrize("n,batch,ld,kmax", [(2048, 100, 128, 5), (3001, 33, 40, 9),
                                              (5000, 7, 8, 4), (300, 64, 64, 0),
                                              (2048, 64, 64, 64), (2048, 48, 64, 100),
-                                             (1999, 40, 40, 300)])
+                                             (1999, 40, 40, 300), (2048, 80, 128, 12)])
 def test_mnpdm_random_lists(n, batch, ld, kmax, path):
     """Random sparse outer diagonals (K entries per system, some lists shorter
     than kmax): MNPDM against the oracle and bitwise against NPDM on the
