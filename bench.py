@@ -800,6 +800,11 @@ def main():
                     help="HB steps s_L,s_U of the SIP row")
     ap.add_argument("--tol", type=float, default=TOL, help="SIP and refinement tolerance")
     ap.add_argument("--no-rows", action="store_true", help="skip the other hot-path rows")
+    ap.add_argument("--rows", default="all",
+                    help="comma list of row groups to measure besides the headline: direct "
+                         "(TD, ADI, MNPDM, ILU(0), SIP on the sweep batch), precision (FP32 + "
+                         "refinement, sweep batch and 256 x 1e6), warmstart (4096 x 4096 ADI run), "
+                         "varlen (10 000 systems), rsens (r = 1, 64, 2047); or all")
     ap.add_argument("--pmc-run", action="store_true",
                     help="only run the workload of the rocprofv3 counter passes")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -885,20 +890,31 @@ def main():
         "info_ok": ok,
     }
     samples = {"timed": {k: pd[k][idx] for k in ("e", "c", "d", "a", "b", "y")}}
-    if not args.no_rows:
+    groups = set() if args.no_rows else (
+        {"direct", "precision", "warmstart", "varlen", "rsens"} if args.rows == "all"
+        else set(args.rows.split(",")))
+    unknown = groups - {"direct", "precision", "warmstart", "varlen", "rsens"}
+    if unknown:
+        raise SystemExit(f"--rows: unknown group(s) {sorted(unknown)}")
+    prec_x, vl_x, rs_x = {}, {}, {}
+    if "direct" in groups:
         log("measuring the other hot-path rows")
         line["rows"] = other_rows(pd, td)
-        del sets, xs
-        torch.cuda.empty_cache()
+    del sets, xs
+    torch.cuda.empty_cache()
+    if "precision" in groups:
         prec, prec_x, prec_samples = precision_rows()
         line["fp32_ir"] = prec
         samples.update(prec_samples)
+    if "warmstart" in groups:
         log("learned warm start (4096 x 4096 ADI run)")
         line["warm_start"] = warmstart_rows()
         torch.cuda.empty_cache()
+    if "varlen" in groups:
         log("uneven batch (10 000 systems, n log-uniform in [64, 65536])")
         line["uneven_batch"], vl_x, vl_samples = varlen_rows()
         samples.update(vl_samples)
+    if "rsens" in groups:
         log("the sweep batch at r = 1, 64, 2047")
         line["r_sensitivity"], rs_x, rs_samples = r_sensitivity_rows()
         samples.update(rs_samples)
@@ -909,16 +925,16 @@ def main():
         def rel(x, ref):
             return float((np.abs(x - ref).max(axis=1) / np.abs(ref).max(axis=1)).max())
         line["parity_max_rel_err_sampled"] = rel(x_last, refs["timed"])
-        if not args.no_rows:
+        if vl_x:
             line["uneven_batch"]["sampled_err_vs_oracle"] = max(
                 rel(xv, refs[k]) for k, xv in vl_x.items())
-            for name, xsamp in rs_x.items():
-                for key, xv in xsamp.items():
-                    line["r_sensitivity"][name][f"{key}_err_vs_oracle"] = rel(xv, refs["r_" + name])
-            for name, xsamp in prec_x.items():
-                ref = refs["prec_" + name]
-                for key, xv in xsamp.items():
-                    line["fp32_ir"][name][f"{key}_err_vs_oracle"] = rel(xv, ref)
+        for name, xsamp in rs_x.items():
+            for key, xv in xsamp.items():
+                line["r_sensitivity"][name][f"{key}_err_vs_oracle"] = rel(xv, refs["r_" + name])
+        for name, xsamp in prec_x.items():
+            ref = refs["prec_" + name]
+            for key, xv in xsamp.items():
+                line["fp32_ir"][name][f"{key}_err_vs_oracle"] = rel(xv, ref)
     print(json.dumps(line), flush=True)
 
 
