@@ -146,6 +146,43 @@ def test_workspace_shared_across_dtypes_and_states():
         bs.set_option(bs.OPT_F32_STATE, 1)
 
 
+def test_compact_state_gave_up_waiting_is_redone():
+    """The compact-state kernels under forced give-ups (no time to wait for
+    the other blocks of a system): the FP32 solve redoes the rows of the
+    blocks that gave up sequentially (FP64 on the FP32 values), and in the
+    refinement, whose solves add d into x, the redo adds too; every system
+    reports 0, the results meet their bars, and the meeting counters are clean."""
+    kind, n, batch = 5, 2048, 96
+    ws = wl.dominant_batch(batch, n, kind=kind, seed=88)
+    w32 = fp32_rounded(ws)
+    xr32, _ = oracle_direct(w32, kind)
+    xr, _ = oracle_direct(ws, kind)
+    t32 = to_device(w32, batch, dtype=torch.float32)
+    t64 = to_device(ws, batch)
+    lead = (batch + 15) // 16 * 4
+    nb = bs.workspace_bytes(bs.OP_SOLVE, kind, n, batch, bs.BS_F32)
+    w_s = torch.zeros((nb + 7) // 8, dtype=torch.float64, device="cuda")
+    nb = bs.workspace_bytes(bs.OP_REFINE, kind, n, batch, ld=t64["y"].shape[1])
+    w_r = torch.zeros((nb + 7) // 8, dtype=torch.float64, device="cuda")
+    try:
+        bs.set_option(bs.OPT_EXCHANGE_WAIT_US, 0)
+        for rep in range(5):
+            say(f"compact state, no wait: rep {rep}")
+            x, info = bs.solve(diags_of(t32, kind), t32["y"], kind=kind, batch=batch, workspace=w_s)
+            torch.cuda.synchronize()
+            assert (info.cpu().numpy() == 0).all()
+            assert (w_s.view(torch.int32)[:lead] == 0).all()
+            check_fp32(w32, kind, host(x, batch), xr32, 1, dominant=True)
+            xi, steps, relres, info = bs.refine(diags_of(t64, kind), t64["y"], batch=batch,
+                                                tol=1e-12, max_steps=6, workspace=w_r)
+            torch.cuda.synchronize()
+            assert (info.cpu().numpy() == 0).all() and (relres.cpu().numpy() < 1e-12).all()
+            assert (w_r.view(torch.int32)[:lead] == 0).all()
+            assert rel_err(host(xi, batch), xr).max() <= 1e-11
+    finally:
+        bs.set_option(bs.OPT_EXCHANGE_WAIT_US, 1000000)
+
+
 def test_fp32_pde_lines_and_in_place(f32_state):
     """Second-order (non-dominant boundary) PDE rows in FP32 storage on the
     full 2048 x 2048 sweep batch the benchmark times, every element of every
