@@ -357,6 +357,33 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
                   double* relres, int32_t* info, void* workspace,
                   size_t ws_bytes, void* stream);
 
+/* Explicit Hotelling-Bodewig approximate inverses of the ILU(0) factors
+ * (Remark of Sec. 2; Appendix): for T = L (unit lower: l2, l1 below the
+ * diagonal) and T = U (u0 on it, u1 and u2 = b above; for kind 3: l1, and u0,
+ * u1 = a), s steps of X_{j+1} = X_j (2I - T X_j) from X_0 = diag(T)^{-1}.
+ * X_s is a band matrix on T's side of the diagonal of width
+ * K = min(n - 1, q (2^s - 1)), q = 2 (kind 5) or 1 (kind 3).
+ * factors: band_factor's output for the same kind and ld; diags: A's
+ *   diagonals (only the upper ones are read: b for kind 5, a for kind 3).
+ * XL (s_L steps) and XU (s_U steps): K + 1 planes of n*ld doubles in the
+ *   batch-interleaved layout; plane d holds X_L[i, i - d] (XL) or
+ *   X_U[i, i + d] (XU) at d*n*ld + i*ld + s, and 0 where i - d < 0 or
+ *   i + d >= n.  Either may be NULL (that factor is skipped), not both.
+ * Every product is summed over its inner index in ascending order with one
+ *   rounding per multiply and per add, so each entry is bitwise the same
+ *   recursion on dense n x n matrices.
+ * workspace: hb_inverse_band_workspace_bytes(...) bytes, 8-byte aligned, no
+ *   initialisation needed; (size_t)-1 for a bad kind, n or batch < 1,
+ *   ld < batch, s < 0 or s > 30.  Device pointers, dtype FP64 only.
+ * BS_EINVAL for bad sizes or NULL / misaligned pointers, BS_EWORKSPACE when
+ *   ws_bytes is short.  Two launches per step and factor on `stream`. */
+size_t hb_inverse_band_workspace_bytes(int32_t kind, int64_t n, int64_t batch, int64_t ld,
+                                       int32_t s_L, int32_t s_U);
+int32_t hb_inverse_band(int32_t kind, int64_t n, int64_t batch, int64_t ld,
+                        const void* const diags[5], const double* factors, int32_t s_L,
+                        int32_t s_U, double* XL, double* XU, void* workspace, size_t ws_bytes,
+                        void* stream);
+
 /* ---- Uneven batches --------------------------------------------------------
  * NPDM / NTDM (Sec. 1) for `count` systems of different lengths n[i] >= 8 in
  * one solve.  Layout: systems sorted by length (longest first) in groups of

@@ -31,7 +31,8 @@ EXPORTED = ("bs_status_str", "bs_version", "bs_workspace_bytes", "bs_set_option"
             "bs_varlen_variants",
             "bs_varlen_variant_shape", "bs_varlen_layout", "bs_varlen_workspace_bytes",
             "band_solve_varlen", "bs_varlen_tune", "bs_pack_interleave", "bs_unpack_interleave",
-            "bs_stream_probe", "band_solve_noalloc")
+            "bs_stream_probe", "band_solve_noalloc",
+            "hb_inverse_band_workspace_bytes", "hb_inverse_band")
 (OPT_DIRECT_PATH, OPT_PART_PD_VARIANT, OPT_PART_TD_VARIANT, OPT_SIP_PATH, OPT_EXCHANGE_WAIT_US,
  OPT_F32_STATE) = range(6)
 PATH_AUTO, PATH_LANE, PATH_PART = range(3)
@@ -93,6 +94,8 @@ def load():
         "bs_pack_interleave": (i32, [i64, i64, vp, i64, vp, i64, vp]),
         "band_solve_noalloc": (i32, [i32, i32, i64, i64, i64, vp5, vp, vp, vp, vp]),
         "bs_unpack_interleave": (i32, [i64, i64, vp, i64, vp, i64, vp]),
+        "hb_inverse_band_workspace_bytes": (sz, [i32, i64, i64, i64, i32, i32]),
+        "hb_inverse_band": (i32, [i32, i64, i64, i64, vp5, vp, i32, i32, vp, vp, vp, sz, vp]),
     })
     for name, (res, args) in sig.items():
         if not hasattr(lib, name):
@@ -358,6 +361,39 @@ def solve_mnpdm(cda, outer_row, outer_e, outer_b, rhs, x=None, *, batch=None,
                               _stream(stream))
     _raise(st, "band_solve_mnpdm")
     return x, info
+
+
+def hb_band_width(kind, s, n):
+    """Bandwidth of the HB iterate X_s of an ILU(0) factor: q (2^s - 1), q = 2
+    (kind 5) or 1 (kind 3), at most n - 1."""
+    return min(n - 1, (2 if kind == 5 else 1) * (2 ** s - 1))
+
+
+def hb_inverse(diags, factors, *, s_L=None, s_U=None, kind=None, batch=None, workspace=None,
+               stream=None):
+    """Explicit banded HB iterates of the ILU(0) factors -> (XL, XU): XL[d, i, s]
+    = X_L[i, i - d] (s_L steps), XU[d, i, s] = X_U[i, i + d] (s_U steps), each
+    [K + 1, n, ld] (None where the step count is None)."""
+    lib = load()
+    kind, n, ld, batch, dtype = _prep(diags, None, kind, batch)
+    dev = diags[2].device
+    sl = -1 if s_L is None else int(s_L)
+    su = -1 if s_U is None else int(s_U)
+    XL = None if sl < 0 else torch.zeros((hb_band_width(kind, sl, n) + 1, n, ld),
+                                         dtype=torch.float64, device=dev)
+    XU = None if su < 0 else torch.zeros((hb_band_width(kind, su, n) + 1, n, ld),
+                                         dtype=torch.float64, device=dev)
+    nb = lib.hb_inverse_band_workspace_bytes(kind, n, batch, ld, max(sl, 0), max(su, 0))
+    if nb == ctypes.c_size_t(-1).value:
+        raise BandSolveError(BS_EINVAL, "hb_inverse_band_workspace_bytes")
+    if workspace is None:
+        workspace = _ws(nb, dev)
+    st = lib.hb_inverse_band(kind, n, batch, ld, lib.VP5(*[_ptr(t) for t in diags]),
+                             _ptr(factors), max(sl, 0), max(su, 0), _ptr(XL), _ptr(XU),
+                             _ptr(workspace), workspace.numel() * workspace.element_size(),
+                             _stream(stream))
+    _raise(st, "hb_inverse_band")
+    return XL, XU
 
 
 def sip(diags, rhs, x0=None, *, tol, max_iter, s_L=-1, s_U=-1, factors=None,

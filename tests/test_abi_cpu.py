@@ -366,3 +366,27 @@ def test_interleave_conversion_rejections_on_host(bs):
     assert lib.bs_unpack_interleave(10, 4, a, 4, ctypes.c_void_p(0x10004), 10, None) == E
     assert lib.bs_unpack_interleave(10, 4, a, 4, b, 9, None) == E
     assert lib.bs_unpack_interleave(1 << 26, 4, a, 4, b, 1 << 26, None) == E
+
+
+def test_hb_inverse_band_host_checks(bs):
+    lib = bs.load()
+    ws = lib.hb_inverse_band_workspace_bytes
+    bad = ctypes.c_size_t(-1).value
+    # K = min(n - 1, q (2^s - 1)); two buffers of K + 1 planes of n*ld doubles
+    assert ws(5, 100, 30, 32, 3, 2) == 2 * (14 + 1) * 100 * 32 * 8
+    assert ws(3, 100, 30, 32, 1, 4) == 2 * (15 + 1) * 100 * 32 * 8
+    assert ws(5, 12, 4, 4, 6, 0) == 2 * 12 * 12 * 4 * 8
+    for args in ((4, 10, 2, 2, 1, 1), (5, 0, 2, 2, 1, 1), (5, 10, 3, 2, 1, 1),
+                 (5, 10, 2, 2, -1, 1), (5, 10, 2, 2, 1, 31)):
+        assert ws(*args) == bad, args
+    assert bs.hb_band_width(5, 6, 2048) == 126 and bs.hb_band_width(3, 11, 100) == 99
+    d5 = lib.VP5(*[_fake(k) for k in range(5)])
+    call = lib.hb_inverse_band
+    assert call(5, 16, 8, 8, d5, _fake(7), 1, 1, None, None, _fake(8), 1 << 20,
+                None) == bs.BS_EINVAL                     # no output
+    assert call(5, 16, 8, 8, d5, None, 1, 1, _fake(3), None, _fake(8), 1 << 20,
+                None) == bs.BS_EINVAL                     # no factors
+    assert call(5, 16, 8, 8, d5, _fake(7), 1, 1, _fake(3), _fake(4), _fake(8), 64,
+                None) == bs.BS_EWORKSPACE
+    assert call(5, 16, 8, 8, d5, _fake(7), 1, 1, _fake(3), _fake(4), _fake(8), 1 << 20,
+                None) == bs.BS_ENODEV
