@@ -24,6 +24,12 @@ namespace bs {
 namespace {
 
 constexpr int kBlock = 256;
+#ifndef HB_XT_R
+#define HB_XT_R 4  // rows per lane in the product step
+#endif
+#ifndef HB_XT_D
+#define HB_XT_D 16  // distances per lane in the product step (wide bands)
+#endif
 
 struct Tri {  // the factor T: diagonal (null: unit), then q off-diagonals
   const double* dg;
@@ -31,25 +37,36 @@ struct Tri {  // the factor T: diagonal (null: unit), then q off-diagonals
   const double* o2;  // second off-diagonal (l2 / u2), null when q = 1
 };
 
-// T[i, l] for |l - i| <= q on the factor's side of the diagonal (0 outside).
-template <bool LOWER>
-__device__ inline double tval(const Tri& T, int64_t n, int64_t ld, int64_t i, int64_t l,
-                              int64_t s) {
-  const int64_t dist = LOWER ? i - l : l - i;
-  if (l < 0 || l >= n || dist < 0 || dist > 2) return 0.0;
-  const int64_t o = i * ld + s;
-  if (dist == 0) return T.dg ? T.dg[o] : 1.0;
-  if (dist == 1) return T.o1[o];
-  return T.o2 ? T.o2[o] : 0.0;
+// Work-item layout shared by the step kernels: a block is four waves; lane =
+// system within a group of 64, wave = row tile within the block's four.  The
+// row, distance and plane arithmetic is wave-uniform (scalar registers), so
+// a lane's only private address part is its byte offset 8 s.
+struct Item {
+  int64_t chunk, tile, s;
+  uint32_t boff;  // byte offset of the lane's system (clamped to a live one)
+  bool live;
+};
+
+__device__ inline Item work_item(int64_t batch, int64_t tiles, int64_t chunks, int64_t work) {
+  int64_t w = blockIdx.x;
+  if (work % 8 == 0) w = (w % 8) * (work / 8) + w / 8;  // XCD-contiguous work ranges
+  Item it;
+  it.chunk = w % chunks;
+  const int64_t rest = w / chunks;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  it.tile = (rest % tiles) * 4 + wave;
+  it.s = (rest / tiles) * 64 + (threadIdx.x & 63);
+  it.live = it.s < batch;
+  it.boff = (uint32_t)((it.live ? it.s : batch - 1) * 8);
+  return it;
 }
 
-// X[r, c] of a band stored by distance (0 outside the band or the matrix).
-template <bool LOWER>
-__device__ inline double bval(const double* X, int64_t n, int64_t ld, int64_t band, int64_t r,
-                              int64_t c, int64_t s) {
-  const int64_t dist = LOWER ? r - c : c - r;
-  if (r < 0 || r >= n || c < 0 || c >= n || dist < 0 || dist > band) return 0.0;
-  return X[(dist * n + r) * ld + s];
+__device__ inline double at(const double* base, int64_t uniform_off, uint32_t boff) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base + uniform_off) +
+                                          boff);
+}
+__device__ inline void put(double* base, int64_t uniform_off, uint32_t boff, double v) {
+  *reinterpret_cast<double*>(reinterpret_cast<char*>(base + uniform_off) + boff) = v;
 }
 
 // X_0 = diag(T)^{-1} into plane 0.
@@ -62,58 +79,124 @@ __global__ __launch_bounds__(kBlock) void hb_init_kernel(int64_t n, int64_t batc
   }
 }
 
-// M = 2 I - T X_j (band bm = bx + q): row i of system s per work item.
-template <bool LOWER>
+// M = 2 I - T X_j (band bm = bx + q).  A lane forms D consecutive distances
+// of one row: (T X_j)[i, k] takes its q + 1 terms in ascending inner index l
+// (X_j entries outside its band enter as zeros), then M = 2 delta - (T X_j).
+template <bool LOWER, int D>
 __global__ __launch_bounds__(kBlock) void hb_m_kernel(int64_t n, int64_t batch, int64_t ld,
                                                       Tri T, int q, const double* __restrict__ X,
                                                       int64_t bx, double* __restrict__ Mb,
-                                                      int64_t bm) {
+                                                      int64_t bm, int64_t tiles, int64_t chunks,
+                                                      int64_t work) {
 #pragma clang fp contract(off)
-  for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < n * batch;
-       w += (int64_t)gridDim.x * kBlock) {
-    const int64_t s = w % batch, i = w / batch;
-    for (int64_t d = 0; d <= bm; ++d) {
-      const int64_t k = LOWER ? i - d : i + d;
-      double v = 0.0;
-      if (k >= 0 && k < n) {
-        double acc = 0.0;  // (T X)[i, k], inner index ascending
-        const int64_t l0 = LOWER ? i - q : i, l1 = LOWER ? i : i + q;
-        for (int64_t l = l0; l <= l1; ++l) {
-          const double t = tval<LOWER>(T, n, ld, i, l, s);
-          const double x = bval<LOWER>(X, n, ld, bx, l, k, s);
-          if (t != 0.0 && x != 0.0) acc = acc + t * x;
-        }
-        v = (d == 0 ? 2.0 : 0.0) - acc;
-      }
-      Mb[(d * n + i) * ld + s] = v;
+  const Item it = work_item(batch, tiles, chunks, work);
+  const int64_t i = it.tile, d0 = it.chunk * D, plane = n * ld;
+  if (i >= n) return;
+  // t[m]: T[i, l] for the m-th inner index l in ascending order
+  double t[3];
+  const int64_t lbeg = LOWER ? i - q : i;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const int64_t l = lbeg + m;
+    const int64_t dist = LOWER ? i - l : l - i;
+    t[m] = 0.0;
+    if (m <= q && l >= 0 && l < n) {
+      const double* src = dist == 0 ? T.dg : (dist == 1 ? T.o1 : T.o2);
+      t[m] = src ? at(src, i * ld, it.boff) : 1.0;
     }
+  }
+  double acc[D];
+#pragma unroll
+  for (int c = 0; c < D; ++c) acc[c] = 0.0;
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    const int64_t l = lbeg + m;
+    if (m > q || l < 0 || l >= n) continue;
+    // X_j[l, k] for k = i -+ d lies at distance e = d - (i - l) (lower) or
+    // d - (l - i) (upper) from row l's diagonal
+    const int64_t shift = LOWER ? i - l : l - i;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const int64_t e = d0 + c - shift;
+      const double x = (e >= 0 && e <= bx) ? at(X, e * plane + l * ld, it.boff) : 0.0;
+      acc[c] = acc[c] + t[m] * x;
+    }
+  }
+  if (!it.live) return;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const int64_t d = d0 + c;
+    if (d > bm) break;
+    const int64_t k = LOWER ? i - d : i + d;
+    const double v = (k >= 0 && k < n) ? (d == 0 ? 2.0 : 0.0) - acc[c] : 0.0;
+    put(Mb, d * plane + i * ld, it.boff, v);
   }
 }
 
-// X_{j+1} = X_j M (band bo = bx + bm): row i of system s per work item.
-template <bool LOWER>
-__global__ __launch_bounds__(kBlock) void hb_x_kernel(int64_t n, int64_t batch, int64_t ld,
-                                                      const double* __restrict__ X, int64_t bx,
-                                                      const double* __restrict__ Mb, int64_t bm,
-                                                      double* __restrict__ Xo, int64_t bo) {
+// X_{j+1} = X_j M, register-tiled: a lane owns one system, R consecutive
+// rows and D consecutive distances d0 .. d0 + D - 1.  It sweeps the inner
+// index l upwards once; at each l it loads the R entries X[i, l] of its rows
+// and the D + R - 1 entries of M's row l that those rows need, then updates
+// the R x D sums.  Entries outside a band or the matrix enter as zeros, which
+// leave a sum unchanged (a sum that starts at +0 is never -0), so each output
+// still takes its terms in ascending l with one rounding per multiply and add.
+template <bool LOWER, int R, int D>
+__global__ __launch_bounds__(kBlock) void hb_xt_kernel(int64_t n, int64_t batch, int64_t ld,
+                                                       const double* __restrict__ X, int64_t bx,
+                                                       const double* __restrict__ Mb, int64_t bm,
+                                                       double* __restrict__ Xo, int64_t bo,
+                                                       int64_t tiles, int64_t chunks,
+                                                       int64_t work) {
 #pragma clang fp contract(off)
-  for (int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x; w < n * batch;
-       w += (int64_t)gridDim.x * kBlock) {
-    const int64_t s = w % batch, i = w / batch;
-    for (int64_t d = 0; d <= bo; ++d) {
-      const int64_t k = LOWER ? i - d : i + d;
-      double acc = 0.0;
-      if (k >= 0 && k < n) {
-        // l between i and k, within bx of i and bm of k, ascending
-        const int64_t lo = LOWER ? (k > i - bx ? k : i - bx) : (i > k - bm ? i : k - bm);
-        const int64_t hi = LOWER ? (i < k + bm ? i : k + bm) : (k < i + bx ? k : i + bx);
-        for (int64_t l = lo; l <= hi; ++l) {
-          const double x = bval<LOWER>(X, n, ld, bx, i, l, s);
-          const double m = bval<LOWER>(Mb, n, ld, bm, l, k, s);
-          if (x != 0.0 && m != 0.0) acc = acc + x * m;
-        }
+  const Item it = work_item(batch, tiles, chunks, work);
+  const int64_t i0 = it.tile * R, d0 = it.chunk * D, plane = n * ld;
+  if (i0 >= n) return;
+  const int64_t elo = d0 - bm > 0 ? d0 - bm : 0;
+  const int64_t ehi = bx < d0 + D - 1 ? bx : d0 + D - 1;
+  int64_t lfirst = LOWER ? i0 - ehi : i0 + elo;
+  int64_t llast = LOWER ? i0 + R - 1 - elo : i0 + R - 1 + ehi;
+  if (lfirst < 0) lfirst = 0;
+  if (llast > n - 1) llast = n - 1;
+  double acc[R][D];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int t = 0; t < D; ++t) acc[r][t] = 0.0;
+  for (int64_t l = lfirst; l <= llast; ++l) {
+    double xr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = i0 + r;
+      const int64_t e = LOWER ? i - l : l - i;
+      xr[r] = (e >= 0 && e <= bx && i < n) ? at(X, e * plane + i * ld, it.boff) : 0.0;
+    }
+    // window entry v holds M at distance f = fb + v from row l
+    const int64_t fb = LOWER ? d0 - i0 + l - (R - 1) : d0 - (l - i0);
+    double mw[D + R - 1];
+#pragma unroll
+    for (int v = 0; v < D + R - 1; ++v) {
+      const int64_t f = fb + v;
+      mw[v] = (f >= 0 && f <= bm) ? at(Mb, f * plane + l * ld, it.boff) : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int t = 0; t < D; ++t) {
+        const double m = LOWER ? mw[t - r + R - 1] : mw[t + r];
+        acc[r][t] = acc[r][t] + xr[r] * m;
       }
-      Xo[(d * n + i) * ld + s] = acc;
+  }
+  if (!it.live) return;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = i0 + r;
+    if (i >= n) break;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+      const int64_t d = d0 + t;
+      if (d > bo) break;
+      const int64_t k = LOWER ? i - d : i + d;
+      put(Xo, d * plane + i * ld, it.boff, (k >= 0 && k < n) ? acc[r][t] : 0.0);
     }
   }
 }
@@ -127,6 +210,46 @@ int64_t band_width(int q, int s, int64_t n) {
   if (s >= 62) return n - 1;
   const int64_t w = (int64_t)q * ((int64_t(1) << s) - 1);
   return w < n - 1 ? w : n - 1;
+}
+
+template <bool LOWER, int R, int D>
+hipError_t launch_xt_rd(int64_t n, int64_t batch, int64_t ld, const double* X, int64_t bx,
+                        const double* Mb, int64_t bm, double* Xo, int64_t bo, hipStream_t st) {
+  const int64_t tiles = (n + 4 * R - 1) / (4 * R);
+  const int64_t chunks = (bo + D) / D;
+  const int64_t work = ((batch + 63) / 64) * tiles * chunks;
+  if (work > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((hb_xt_kernel<LOWER, R, D>), dim3((unsigned)work), dim3(kBlock), 0, st, n,
+                     batch, ld, X, bx, Mb, bm, Xo, bo, tiles, chunks, work);
+  return hipGetLastError();
+}
+
+// Tile shape by the output band: D covers it where it is narrow.
+template <bool LOWER>
+hipError_t launch_xt(int64_t n, int64_t batch, int64_t ld, const double* X, int64_t bx,
+                     const double* Mb, int64_t bm, double* Xo, int64_t bo, hipStream_t st) {
+  if (bo < 4) return launch_xt_rd<LOWER, 4, 4>(n, batch, ld, X, bx, Mb, bm, Xo, bo, st);
+  if (bo < 8) return launch_xt_rd<LOWER, 4, 8>(n, batch, ld, X, bx, Mb, bm, Xo, bo, st);
+  return launch_xt_rd<LOWER, HB_XT_R, HB_XT_D>(n, batch, ld, X, bx, Mb, bm, Xo, bo, st);
+}
+
+template <bool LOWER, int D>
+hipError_t launch_m_d(int64_t n, int64_t batch, int64_t ld, const Tri& T, int q, const double* X,
+                      int64_t bx, double* Mb, int64_t bm, hipStream_t st) {
+  const int64_t tiles = (n + 3) / 4;
+  const int64_t chunks = (bm + D) / D;
+  const int64_t work = ((batch + 63) / 64) * tiles * chunks;
+  if (work > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((hb_m_kernel<LOWER, D>), dim3((unsigned)work), dim3(kBlock), 0, st, n, batch,
+                     ld, T, q, X, bx, Mb, bm, tiles, chunks, work);
+  return hipGetLastError();
+}
+
+template <bool LOWER>
+hipError_t launch_m(int64_t n, int64_t batch, int64_t ld, const Tri& T, int q, const double* X,
+                    int64_t bx, double* Mb, int64_t bm, hipStream_t st) {
+  if (bm < 4) return launch_m_d<LOWER, 4>(n, batch, ld, T, q, X, bx, Mb, bm, st);
+  return launch_m_d<LOWER, 8>(n, batch, ld, T, q, X, bx, Mb, bm, st);
 }
 
 // One factor: s steps; the result lands in `out`, intermediates alternate
@@ -143,10 +266,10 @@ hipError_t hb_factor(int64_t n, int64_t batch, int64_t ld, const Tri& T, int q, 
     const int64_t bx = band_width(q, j, n);
     const int64_t bm = bx + q < n - 1 ? bx + q : n - 1;
     const int64_t bo = band_width(q, j + 1, n);
-    hipLaunchKernelGGL((hb_m_kernel<LOWER>), grid, block, 0, st, n, batch, ld, T, q, buf(j), bx,
-                       mw, bm);
-    hipLaunchKernelGGL((hb_x_kernel<LOWER>), grid, block, 0, st, n, batch, ld, buf(j), bx, mw,
-                       bm, buf(j + 1), bo);
+    e = launch_m<LOWER>(n, batch, ld, T, q, buf(j), bx, mw, bm, st);
+    if (e != hipSuccess) return e;
+    e = launch_xt<LOWER>(n, batch, ld, buf(j), bx, mw, bm, buf(j + 1), bo, st);
+    if (e != hipSuccess) return e;
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
