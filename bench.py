@@ -422,7 +422,38 @@ def other_rows(pd, td):
                         "iters_mean": float(its.mean()), "iters_max": int(res["it"].max()),
                         "us_per_iteration": ms * 1e3 / max(float(its.max()), 1.0),
                         "converged": int((res["si"] == 0).sum())}
+    # explicit banded HB inverses of both factors, s = (5, 6)
+    sL, sU = 5, 6
+    KL, KU = bs.hb_band_width(5, sL, N_ROWS), bs.hb_band_width(5, sU, N_ROWS)
+    XL = torch.empty((KL + 1, N_ROWS, BATCH), dtype=torch.float64, device="cuda")
+    XU = torch.empty((KU + 1, N_ROWS, BATCH), dtype=torch.float64, device="cuda")
+    wsh = torch.empty(bs.load().hb_inverse_band_workspace_bytes(5, N_ROWS, BATCH, BATCH, sL, sU)
+                      // 8, dtype=torch.float64, device="cuda")
+    ms = t_ms(lambda: bs.hb_inverse(diags_of(t, 5), f, s_L=sL, s_U=sU, batch=BATCH,
+                                    workspace=wsh, out=(XL, XU)), reps=2)
+    terms, planes = hb_work(2, (sL, sU), N_ROWS)
+    out["hb_band_pd"] = {"us": ms * 1e3, "hb_s": [sL, sU], "output_GB": (KL + KU + 2) * N_ROWS *
+                         BATCH * 8 / 1e9,
+                         "hbm_GBps_algorithmic": planes * N_ROWS * BATCH * 8 / ms / 1e6,
+                         "fp64_GFLOPs": 2 * terms * BATCH / ms / 1e6}
+    del XL, XU, wsh
     return out
+
+
+def hb_work(q, steps, n):
+    """Products and streamed planes of the banded HB recursion, per system:
+    step j reads X_j (b + 1 planes) to form M = 2I - T X_j (b + q + 1 planes,
+    written), then reads both and writes X_{j+1}; a product entry of X_j M
+    takes (b + 1)(b + q + 1) terms per row when the bands fit the matrix."""
+    terms = planes = 0
+    for s in steps:
+        for j in range(s):
+            b = min(n - 1, q * (2 ** j - 1))
+            bm = min(n - 1, b + q)
+            bo = min(n - 1, q * (2 ** (j + 1) - 1))
+            terms += n * (b + 1) * (bm + 1) + n * (bm + 1) * (q + 1)
+            planes += (b + 1) + (bm + 1) + (b + 1) + (bm + 1) + (bo + 1)
+    return terms, planes
 
 
 def varlen_rows(reps=5):
@@ -651,6 +682,7 @@ def profile_rows():
                                       factors=f, batch=BATCH), k=1)
     rep("sip exact", lambda: bs.sip(D5, t5["y"], tol=1e-10, max_iter=3, factors=f, batch=BATCH),
         k=1)
+    rep("hb band inverses s=(5,6)", lambda: bs.hb_inverse(D5, f, s_L=5, s_U=6, batch=BATCH), k=2)
     del t5, t3, t32, x, x32, f
     nsys, n = 256, 1_000_000
     v = wl.smooth_lines(nsys, n, wl.BASE_SEED + 3)

@@ -370,19 +370,25 @@ def hb_band_width(kind, s, n):
 
 
 def hb_inverse(diags, factors, *, s_L=None, s_U=None, kind=None, batch=None, workspace=None,
-               stream=None):
+               out=None, stream=None):
     """Explicit banded HB iterates of the ILU(0) factors -> (XL, XU): XL[d, i, s]
     = X_L[i, i - d] (s_L steps), XU[d, i, s] = X_U[i, i + d] (s_U steps), each
-    [K + 1, n, ld] (None where the step count is None)."""
+    [K + 1, n, ld] (None where the step count is None).  out: optional
+    (XL, XU) tensors of those shapes to write into."""
     lib = load()
     kind, n, ld, batch, dtype = _prep(diags, None, kind, batch)
     dev = diags[2].device
     sl = -1 if s_L is None else int(s_L)
     su = -1 if s_U is None else int(s_U)
-    XL = None if sl < 0 else torch.zeros((hb_band_width(kind, sl, n) + 1, n, ld),
-                                         dtype=torch.float64, device=dev)
-    XU = None if su < 0 else torch.zeros((hb_band_width(kind, su, n) + 1, n, ld),
-                                         dtype=torch.float64, device=dev)
+    shapes = [None if v < 0 else (hb_band_width(kind, v, n) + 1, n, ld) for v in (sl, su)]
+    if out is None:
+        out = [None if sh is None else torch.zeros(sh, dtype=torch.float64, device=dev)
+               for sh in shapes]
+    XL, XU = out
+    for t, sh, name in ((XL, shapes[0], "XL"), (XU, shapes[1], "XU")):
+        if (t is None) != (sh is None) or (t is not None and (
+                tuple(t.shape) != sh or t.dtype != torch.float64 or not t.is_contiguous())):
+            raise ValueError(f"{name} must be a contiguous float64 tensor of shape {sh}")
     nb = lib.hb_inverse_band_workspace_bytes(kind, n, batch, ld, max(sl, 0), max(su, 0))
     if nb == ctypes.c_size_t(-1).value:
         raise BandSolveError(BS_EINVAL, "hb_inverse_band_workspace_bytes")

@@ -112,3 +112,20 @@ def test_rejections():
     with pytest.raises(bs.BandSolveError) as ei:
         bs.hb_inverse(diags_of(t), f, s_L=2, s_U=2, batch=4, workspace=small)
     assert ei.value.status == bs.BS_EWORKSPACE
+
+
+def test_every_slot_written_into_given_outputs():
+    """Outputs passed in (filled with NaN) come back with every slot of the
+    live systems written: band entries, and zeros outside the matrix."""
+    batch, n = 50, 40
+    ws = wl.dominant_batch(batch, n, kind=5, seed=wl.BASE_SEED + 73)
+    t = to_device(ws, batch, ld=64)
+    f, _ = bs.factor(diags_of(t), batch=batch)
+    ref = bs.hb_inverse(diags_of(t), f, s_L=4, s_U=3, batch=batch)
+    outs = [torch.full_like(r, float("nan")) for r in ref]
+    got = bs.hb_inverse(diags_of(t), f, s_L=4, s_U=3, batch=batch, out=outs)
+    torch.cuda.synchronize()
+    for g, r in zip(got, ref):
+        assert torch.equal(g[:, :, :batch].contiguous().view(torch.int64),
+                           r[:, :, :batch].contiguous().view(torch.int64))
+        assert torch.isnan(g[:, :, batch:]).all()     # padding columns untouched
