@@ -129,3 +129,33 @@ def test_every_slot_written_into_given_outputs():
         assert torch.equal(g[:, :, :batch].contiguous().view(torch.int64),
                            r[:, :, :batch].contiguous().view(torch.int64))
         assert torch.isnan(g[:, :, batch:]).all()     # padding columns untouched
+
+
+def test_full_sweep_batch_sampled_against_vector_form():
+    """The 2048 x 2048 ADI sweep batch at s = (5, 6), as bench.py times it:
+    for sampled systems, X_s v from the GPU's band planes equals the oracle's
+    vector form of the same HB iterate (2^s - 1 sweeps) to rounding."""
+    pd, _, _ = wl.config1()
+    n = batch = 2048
+    t = to_device(pd, batch)
+    f, info = bs.factor(diags_of(t), batch=batch)
+    assert int(info.abs().sum()) == 0
+    say("hb_inverse_band full sweep batch s=(5,6)")
+    XL, XU = bs.hb_inverse(diags_of(t), f, s_L=5, s_U=6, batch=batch)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    for j in (0, 1, 1023, 2047):
+        l2, l1, u0, u1, finfo = oracle.ilu0_band(pd["e"][j], pd["c"][j], pd["d"][j], pd["a"][j],
+                                                 pd["b"][j])
+        assert finfo == 0
+        v = rng.uniform(-1.0, 1.0, n)
+        xl, xu = XL[:, :, j].cpu().numpy(), XU[:, :, j].cpu().numpy()
+        yl, yu = np.zeros(n), np.zeros(n)
+        for d in range(xl.shape[0]):
+            yl[d:] += xl[d, d:] * v[:n - d]
+        for d in range(xu.shape[0]):
+            yu[:n - d] += xu[d, :n - d] * v[d:]
+        rl = oracle.hb_lower_apply(l2, l1, 5, v)
+        ru = oracle.hb_upper_apply(u0, u1, pd["b"][j], 6, v)
+        assert np.abs(yl - rl).max() <= 1e-12 * np.abs(rl).max(), j
+        assert np.abs(yu - ru).max() <= 1e-12 * np.abs(ru).max(), j
