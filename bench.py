@@ -843,6 +843,9 @@ def main():
                     help="write the HBM traffic summary from two counter passes")
     ap.add_argument("--profile-rows", action="store_true",
                     help="only run a few launches of every hot-path row (for rocprofv3)")
+    ap.add_argument("--profile-hb", action="store_true",
+                    help="only one call of the explicit HB band inverses, s = (5, 6), on the "
+                         "sweep batch's factors (for rocprofv3 counters)")
     ap.add_argument("--summarize-stats", nargs=4,
                     metavar=("CSV_DIR", "OUT", "TITLE", "COMMAND"),
                     help="write a kernel-statistics table from rocprofv3 CSV output")
@@ -853,6 +856,14 @@ def main():
         raise SystemExit("--hb-s takes two non-negative integers s_L,s_U; --tol must be positive")
     if args.summarize_stats:
         summarize_stats(*args.summarize_stats)
+        return
+    if args.profile_hb:
+        pd, _, _ = config1()
+        t5 = {k: torch.from_numpy(wl.interleave(pd[k])).cuda() for k in ("e", "c", "d", "a", "b")}
+        f, _ = bs.factor(diags_of(t5, 5), batch=BATCH)
+        bs.hb_inverse(diags_of(t5, 5), f, s_L=5, s_U=6, batch=BATCH)
+        torch.cuda.synchronize()
+        log("profiled hb band inverses s=(5,6)")
         return
     if args.profile_rows:
         profile_rows()
