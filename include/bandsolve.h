@@ -374,7 +374,8 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
  *   recursion on dense n x n matrices.
  * workspace: hb_inverse_band_workspace_bytes(...) bytes, 8-byte aligned, no
  *   initialisation needed; (size_t)-1 for a bad kind, n or batch < 1,
- *   ld < batch, n * ld >= 2^40, s < 0 or s > 30.  Device pointers, FP64.
+ *   batch >= 2^28, ld < batch, n * ld >= 2^40, s < 0 or s > 30, or a grid
+ *   beyond 2^31 - 1 blocks.  Device pointers, FP64.
  * BS_EINVAL for bad sizes or NULL / misaligned pointers, BS_EWORKSPACE when
  *   ws_bytes is short.  Two launches per step and factor on `stream`. */
 size_t hb_inverse_band_workspace_bytes(int32_t kind, int64_t n, int64_t batch, int64_t ld,

@@ -286,10 +286,15 @@ int64_t hb_band_width(int kind, int s, int64_t n) { return band_width(kind == 5 
 
 extern "C" size_t hb_inverse_band_workspace_bytes(int32_t kind, int64_t n, int64_t batch,
                                                   int64_t ld, int32_t s_L, int32_t s_U) {
-  if ((kind != 3 && kind != 5) || n < 1 || batch < 1 || ld < batch || s_L < 0 || s_U < 0 ||
-      s_L > 30 || s_U > 30 || ld > (int64_t(1) << 40) / n)
+  // batch < 2^28: a lane's byte offset 8 s is a 32-bit value
+  if ((kind != 3 && kind != 5) || n < 1 || batch < 1 || batch >= (int64_t(1) << 28) ||
+      ld < batch || s_L < 0 || s_U < 0 || s_L > 30 || s_U > 30 || ld > (int64_t(1) << 40) / n)
     return (size_t)-1;
   const int64_t K = bs::hb_band_width(kind, s_L > s_U ? s_L : s_U, n);
+  // every launch's grid (at most (K + 8) / 8 distance chunks of n / 4 rows
+  // per 64 systems) must fit a one-dimensional grid
+  const int64_t lim = 0x7fffffff, g1 = (batch + 63) / 64, g2 = (n + 3) / 4, g3 = (K + 8) / 8;
+  if (g1 > lim / g2 || g1 * g2 > lim / g3) return (size_t)-1;
   return (size_t)(2 * (K + 1) * n * ld) * sizeof(double);
 }
 

@@ -377,7 +377,7 @@ def test_hb_inverse_band_host_checks(bs):
     assert ws(3, 100, 30, 32, 1, 4) == 2 * (15 + 1) * 100 * 32 * 8
     assert ws(5, 12, 4, 4, 6, 0) == 2 * 12 * 12 * 4 * 8
     for args in ((4, 10, 2, 2, 1, 1), (5, 0, 2, 2, 1, 1), (5, 10, 3, 2, 1, 1),
-                 (5, 10, 2, 2, -1, 1), (5, 10, 2, 2, 1, 31)):
+                 (5, 10, 2, 2, -1, 1), (5, 10, 2, 2, 1, 31), (5, 4, 1 << 28, 1 << 28, 1, 1)):
         assert ws(*args) == bad, args
     assert bs.hb_band_width(5, 6, 2048) == 126 and bs.hb_band_width(3, 11, 100) == 99
     d5 = lib.VP5(*[_fake(k) for k in range(5)])
