@@ -13,10 +13,14 @@
 // rounded multiply and one rounded add per term (no contraction), from an
 // accumulator of zero: terms outside the bands are exact zeros and change no
 // sum, so the band entries are those of the same recursion on dense
-// matrices.  Each step is two launches over (row, system): M = 2 I - T X_j,
-// then X_{j+1} = X_j M.  Entries are stored by distance from the diagonal:
+// matrices.  A step whose output band is narrower than 16 is one launch that
+// forms M = 2 I - T X_j in registers inside the product; a wider one is two
+// launches, M into the workspace, then X_{j+1} = X_j M.  Entries are stored
+// by distance from the diagonal:
 // plane d of a lower factor holds X[i, i - d] at d*n*ld + i*ld + s, plane d
 // of an upper one X[i, i + d]; slots outside the matrix hold 0.
+#include <type_traits>
+
 #include "bandsolve.h"
 #include "bs_internal.h"
 
@@ -201,6 +205,112 @@ __global__ __launch_bounds__(kBlock) void hb_xt_kernel(int64_t n, int64_t batch,
   }
 }
 
+// X_{j+1} = X_j M with M = 2 I - T X_j formed in registers, never stored.
+// In the sweep over l, the M entries a lane needs in row l sit at distances
+// fb + v (v < W = D + R - 1), and M[l, k] takes X_j rows l .. l + q (upper;
+// l - q .. l below the diagonal) at column k.  For a fixed row rho of X_j
+// those columns are one window of W planes whatever l is, so each X_j row
+// window is loaded once and kept for the q + 1 values of l that use it (a
+// ring of q + 1 windows).  Every M entry is the M kernel's: (T X_j)[l, k]
+// over the inner index in ascending order, then 2 delta - (T X_j), so the
+// result is bitwise the two-kernel step.
+template <bool LOWER, int Q, int R, int D>
+__global__ __launch_bounds__(kBlock) void hb_xf_kernel(int64_t n, int64_t batch, int64_t ld,
+                                                       Tri T, const double* __restrict__ X,
+                                                       int64_t bx, int64_t bm,
+                                                       double* __restrict__ Xo, int64_t bo,
+                                                       int64_t tiles, int64_t chunks,
+                                                       int64_t work) {
+#pragma clang fp contract(off)
+  constexpr int W = D + R - 1, NR = Q + 1;
+  const Item it = work_item(batch, tiles, chunks, work);
+  const int64_t i0 = it.tile * R, d0 = it.chunk * D, plane = n * ld;
+  if (i0 >= n) return;
+  const int64_t elo = d0 - bm > 0 ? d0 - bm : 0;
+  const int64_t ehi = bx < d0 + D - 1 ? bx : d0 + D - 1;
+  int64_t lfirst = LOWER ? i0 - ehi : i0 + elo;
+  int64_t llast = LOWER ? i0 + R - 1 - elo : i0 + R - 1 + ehi;
+  if (lfirst < 0) lfirst = 0;
+  if (llast > n - 1) llast = n - 1;
+  double acc[R][D];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int t = 0; t < D; ++t) acc[r][t] = 0.0;
+  // window of X_j row rho: planes pb(rho) + v (0 outside the band or matrix)
+  auto load_win = [&](int64_t rho, double (&xw)[W]) {
+    const int64_t pb = LOWER ? rho + d0 - i0 - (R - 1) : d0 + i0 - rho;
+#pragma unroll
+    for (int v = 0; v < W; ++v) {
+      const int64_t e = pb + v;
+      xw[v] = (rho >= 0 && rho < n && e >= 0 && e <= bx) ? at(X, e * plane + rho * ld, it.boff)
+                                                         : 0.0;
+    }
+  };
+  double ring[NR][W];
+  // the ring slot of the window of the m-th inner row at rotation K
+  const int64_t rho0 = LOWER ? lfirst - Q : lfirst;  // inner row m = 0 at l = lfirst
+  if (lfirst <= llast) {
+#pragma unroll
+    for (int m = 0; m < Q; ++m) load_win(rho0 + m, ring[m]);
+  }
+  auto body = [&](auto Kc, int64_t l) {
+    constexpr int K = decltype(Kc)::value;
+    load_win(LOWER ? l : l + Q, ring[(K + Q) % NR]);
+    // T[l, inner row m], m ascending (0 where the inner row is outside)
+    double t[NR];
+#pragma unroll
+    for (int m = 0; m < NR; ++m) {
+      const int64_t rho = LOWER ? l - Q + m : l + m;
+      const int dist = LOWER ? Q - m : m;
+      const double* src = dist == 0 ? T.dg : (dist == 1 ? T.o1 : T.o2);
+      t[m] = (rho >= 0 && rho < n) ? (src ? at(src, l * ld, it.boff) : 1.0) : 0.0;
+    }
+    double xr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t i = i0 + r;
+      const int64_t e = LOWER ? i - l : l - i;
+      xr[r] = (e >= 0 && e <= bx && i < n) ? at(X, e * plane + i * ld, it.boff) : 0.0;
+    }
+    const int64_t fb = LOWER ? d0 - i0 + l - (R - 1) : d0 - (l - i0);
+#pragma unroll
+    for (int v = 0; v < W; ++v) {
+      double tx = 0.0;
+#pragma unroll
+      for (int m = 0; m < NR; ++m) tx = tx + t[m] * ring[(K + m) % NR][v];
+      const double mv = (fb + v == 0 ? 2.0 : 0.0) - tx;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int tt = LOWER ? v + r - (R - 1) : v - r;
+        if (tt >= 0 && tt < D) acc[r][tt] = acc[r][tt] + xr[r] * mv;
+      }
+    }
+  };
+  int64_t l = lfirst;
+  for (; l + Q <= llast; l += NR) {
+    body(std::integral_constant<int, 0>{}, l);
+    body(std::integral_constant<int, 1>{}, l + 1);
+    if constexpr (Q == 2) body(std::integral_constant<int, 2>{}, l + 2);
+  }
+  if (l <= llast) body(std::integral_constant<int, 0>{}, l);
+  if constexpr (Q == 2)
+    if (l + 1 <= llast) body(std::integral_constant<int, 1>{}, l + 1);
+  if (!it.live) return;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = i0 + r;
+    if (i >= n) break;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+      const int64_t d = d0 + t;
+      if (d > bo) break;
+      const int64_t k = LOWER ? i - d : i + d;
+      put(Xo, d * plane + i * ld, it.boff, (k >= 0 && k < n) ? acc[r][t] : 0.0);
+    }
+  }
+}
+
 int grid_for(int64_t work) {
   const int64_t b = (work + kBlock - 1) / kBlock;
   return (int)(b < 65536 ? (b > 0 ? b : 1) : 65536);
@@ -252,6 +362,31 @@ hipError_t launch_m(int64_t n, int64_t batch, int64_t ld, const Tri& T, int q, c
   return launch_m_d<LOWER, 8>(n, batch, ld, T, q, X, bx, Mb, bm, st);
 }
 
+template <bool LOWER, int Q, int R, int D>
+hipError_t launch_xf_rd(int64_t n, int64_t batch, int64_t ld, const Tri& T, const double* X,
+                        int64_t bx, int64_t bm, double* Xo, int64_t bo, hipStream_t st) {
+  const int64_t tiles = (n + 4 * R - 1) / (4 * R);
+  const int64_t chunks = (bo + D) / D;
+  const int64_t work = ((batch + 63) / 64) * tiles * chunks;
+  if (work > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((hb_xf_kernel<LOWER, Q, R, D>), dim3((unsigned)work), dim3(kBlock), 0, st,
+                     n, batch, ld, T, X, bx, bm, Xo, bo, tiles, chunks, work);
+  return hipGetLastError();
+}
+
+// The fused step wins while the output band is narrow (measured on the
+// 2048 x 2048 sweep factors: 0.57 against 0.75 ms for the first three steps
+// of each factor at s = (5, 6)); from band 16 on, the step whose product
+// only loads M is faster (band 126: 6.4 against 8.8 ms).
+constexpr int64_t kFusedBelow = 16;
+
+template <bool LOWER, int Q>
+hipError_t launch_xf(int64_t n, int64_t batch, int64_t ld, const Tri& T, const double* X,
+                     int64_t bx, int64_t bm, double* Xo, int64_t bo, hipStream_t st) {
+  if (bo < 4) return launch_xf_rd<LOWER, Q, 4, 4>(n, batch, ld, T, X, bx, bm, Xo, bo, st);
+  return launch_xf_rd<LOWER, Q, 4, 8>(n, batch, ld, T, X, bx, bm, Xo, bo, st);
+}
+
 // One factor: s steps; the result lands in `out`, intermediates alternate
 // between `out` and `xw` so that the last step writes `out`.
 template <bool LOWER>
@@ -266,9 +401,14 @@ hipError_t hb_factor(int64_t n, int64_t batch, int64_t ld, const Tri& T, int q, 
     const int64_t bx = band_width(q, j, n);
     const int64_t bm = bx + q < n - 1 ? bx + q : n - 1;
     const int64_t bo = band_width(q, j + 1, n);
-    e = launch_m<LOWER>(n, batch, ld, T, q, buf(j), bx, mw, bm, st);
-    if (e != hipSuccess) return e;
-    e = launch_xt<LOWER>(n, batch, ld, buf(j), bx, mw, bm, buf(j + 1), bo, st);
+    if (bo < kFusedBelow) {  // narrow bands: M formed inside the product
+      e = q == 2 ? launch_xf<LOWER, 2>(n, batch, ld, T, buf(j), bx, bm, buf(j + 1), bo, st)
+                 : launch_xf<LOWER, 1>(n, batch, ld, T, buf(j), bx, bm, buf(j + 1), bo, st);
+    } else {
+      e = launch_m<LOWER>(n, batch, ld, T, q, buf(j), bx, mw, bm, st);
+      if (e != hipSuccess) return e;
+      e = launch_xt<LOWER>(n, batch, ld, buf(j), bx, mw, bm, buf(j + 1), bo, st);
+    }
     if (e != hipSuccess) return e;
     e = hipGetLastError();
     if (e != hipSuccess) return e;
