@@ -377,7 +377,8 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
  *   batch >= 2^28, ld < batch, n * ld >= 2^40, s < 0 or s > 30, or a grid
  *   beyond 2^31 - 1 blocks.  Device pointers, FP64.
  * BS_EINVAL for bad sizes or NULL / misaligned pointers, BS_EWORKSPACE when
- *   ws_bytes is short.  Two launches per step and factor on `stream`. */
+ *   ws_bytes is short.  One launch per step and factor on `stream` while the
+ *   output band is narrower than 16, two from there on. */
 size_t hb_inverse_band_workspace_bytes(int32_t kind, int64_t n, int64_t batch, int64_t ld,
                                        int32_t s_L, int32_t s_U);
 int32_t hb_inverse_band(int32_t kind, int64_t n, int64_t batch, int64_t ld,
