@@ -101,6 +101,18 @@ def test_forward_backward_against_oracle(dt, tol):
         eb = np.abs(bg - bo).max() / np.abs(bo).max()
         say(f"  layer {k + 1}: dW rel err {ew:.2e}, db rel err {eb:.2e}")
         assert ew <= tol and eb <= tol
+    if dt == "bf16":
+        # element-wise: the same chain on |dY|, |activations| and |weights|
+        # (the ReLU masks are unchanged: hidden activations are >= 0) bounds
+        # every term's magnitude; each stored BF16 operand may sit one
+        # rounding (2^-8) away from the oracle's where its FP32 value is near
+        # a rounding boundary, once per layer forward and once backward (8
+        # for four layers), and the FP32 sums add (P + 2) 2^-24
+        mag = mo.backward(np.abs(host(dY)), [np.abs(a) for a in acts], np.abs(p), bf16=False)
+        bound = (8 * 2.0**-8 + (P + 2) * 2.0**-24) * mag + 1e-30
+        ratio = np.abs(g - go) / bound
+        say(f"  bf16 gradient: max |g - g_orc| / element-wise bound = {ratio.max():.3f}")
+        assert (ratio <= 1.0).all()
 
 
 def test_adam_step_against_oracle():
