@@ -95,6 +95,15 @@ def test_forward_backward_against_oracle(dt, tol):
     # end to end (the element-wise bounds are per layer: test_network_layers_elementwise)
     assert np.abs(host(Y) - Yo).max() <= tol * np.abs(Yo).max()
     assert np.abs(host(dY) - dYo).max() <= tol * np.abs(dYo).max()
+    if dt == "bf16":
+        # element-wise.  dY = 2 (Y - T) / size is linear in Y: its bound is
+        # that map applied to Y's bound plus the FP32 roundings of T, of the
+        # difference and of the scaling (a few 2^-24 of |Y| + |T|)
+        bY = forward_bound(X, p)
+        assert (np.abs(host(Y) - Yo) <= bY).all()
+        delta = bY + 2.0**-21 * (np.abs(Yo) + np.abs(T))
+        bdY = np.abs(mo.mse(Yo + delta, T)[1] - dYo) + 1e-30
+        assert (np.abs(host(dY) - dYo) <= bdY).all()
     g = host(grads)
     for k, ((Wg, bg), (Wo, bo)) in enumerate(zip(mo.unpack(g), mo.unpack(go))):
         ew = np.abs(Wg - Wo).max() / np.abs(Wo).max()
