@@ -131,17 +131,20 @@ def test_every_slot_written_into_given_outputs():
         assert torch.isnan(g[:, :, batch:]).all()     # padding columns untouched
 
 
-def test_full_sweep_batch_sampled_against_vector_form():
-    """The 2048 x 2048 ADI sweep batch at s = (5, 6), as bench.py times it:
-    for sampled systems, X_s v from the GPU's band planes equals the oracle's
-    vector form of the same HB iterate (2^s - 1 sweeps) to rounding."""
-    pd, _, _ = wl.config1()
+@pytest.mark.parametrize("kind", [5, 3])
+def test_full_sweep_batch_sampled_against_vector_form(kind):
+    """The 2048 x 2048 ADI sweep batch at s = (5, 6), as bench.py times it
+    (pentadiagonal; and the tridiagonal sweep): for sampled systems, X_s v
+    from the GPU's band planes equals the oracle's vector form of the same HB
+    iterate (2^s - 1 sweeps) to rounding."""
+    pd5, td, _ = wl.config1()
+    pd = pd5 if kind == 5 else {**td, "e": 0 * td["d"], "b": 0 * td["d"]}
     n = batch = 2048
     t = to_device(pd, batch)
-    f, info = bs.factor(diags_of(t), batch=batch)
+    f, info = bs.factor(diags_of(t, kind), kind=kind, batch=batch)
     assert int(info.abs().sum()) == 0
-    say("hb_inverse_band full sweep batch s=(5,6)")
-    XL, XU = bs.hb_inverse(diags_of(t), f, s_L=5, s_U=6, batch=batch)
+    say(f"hb_inverse_band full sweep batch kind={kind} s=(5,6)")
+    XL, XU = bs.hb_inverse(diags_of(t, kind), f, s_L=5, s_U=6, kind=kind, batch=batch)
     torch.cuda.synchronize()
     rng = np.random.default_rng(5)
     for j in (0, 1, 1023, 2047):
