@@ -432,10 +432,13 @@ def other_rows(pd, td):
     ms = t_ms(lambda: bs.hb_inverse(diags_of(t, 5), f, s_L=sL, s_U=sU, batch=BATCH,
                                     workspace=wsh, out=(XL, XU)), reps=2)
     terms, planes = hb_work(2, (sL, sU), N_ROWS)
+    gbps = planes * N_ROWS * BATCH * 8 / ms / 1e6
     out["hb_band_pd"] = {"us": ms * 1e3, "hb_s": [sL, sU], "output_GB": (KL + KU + 2) * N_ROWS *
                          BATCH * 8 / 1e9,
-                         "hbm_GBps_algorithmic": planes * N_ROWS * BATCH * 8 / ms / 1e6,
-                         "fp64_GFLOPs": 2 * terms * BATCH / ms / 1e6}
+                         "hbm_GBps_algorithmic": gbps, "hbm_frac": gbps / 8000.0,
+                         "fp64_GFLOPs": 2 * terms * BATCH / ms / 1e6,
+                         # separate multiplies and adds: 39.3 T operations/s
+                         "fp64_op_frac": 2 * terms * BATCH / ms / 1e6 / 39300.0}
     del XL, XU, wsh
     return out
 
