@@ -445,9 +445,11 @@ def other_rows(pd, td):
 
 def hb_work(q, steps, n):
     """Products and streamed planes of the banded HB recursion, per system:
-    step j reads X_j (b + 1 planes) to form M = 2I - T X_j (b + q + 1 planes,
-    written), then reads both and writes X_{j+1}; a product entry of X_j M
-    takes (b + 1)(b + q + 1) terms per row when the bands fit the matrix."""
+    a step j with an output band of 16 or more reads X_j (b + 1 planes) to
+    form M = 2I - T X_j (b + q + 1 planes, written), then reads both and
+    writes X_{j+1}; a narrower step reads X_j once and writes X_{j+1} (M
+    stays in registers).  A product entry of X_j M takes (b + 1)(b + q + 1)
+    terms per row when the bands fit the matrix."""
     terms = planes = 0
     for s in steps:
         for j in range(s):
@@ -455,7 +457,10 @@ def hb_work(q, steps, n):
             bm = min(n - 1, b + q)
             bo = min(n - 1, q * (2 ** (j + 1) - 1))
             terms += n * (b + 1) * (bm + 1) + n * (bm + 1) * (q + 1)
-            planes += (b + 1) + (bm + 1) + (b + 1) + (bm + 1) + (bo + 1)
+            if bo < 16:
+                planes += (b + 1) + (bo + 1)
+            else:
+                planes += (b + 1) + (bm + 1) + (b + 1) + (bm + 1) + (bo + 1)
     return terms, planes
 
 
