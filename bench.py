@@ -280,6 +280,7 @@ def precision_rows():
         log(f"precision rows: {name}")
         info = torch.empty(batch, dtype=torch.int32, device="cuda")
         rows = n * batch
+        ir_floor = 176 if n <= 4096 else 280  # the single-launch and the long-system path
         # FP64 direct solve
         x64 = torch.empty_like(dev["y"])
         w64 = torch.zeros(max(bs.workspace_bytes(bs.OP_SOLVE, 5, n, batch), 8) // 8,
@@ -316,6 +317,12 @@ def precision_rows():
             "fp32_algorithmic_GBps": 28 * rows / ms32 / 1e6,
             "fp32_ir_to_1e-10_us": msir * 1e3,
             "fp32_ir_over_fp64_time": msir / ms64,
+            # least bytes any verified refinement moves per row: a first solve
+            # from the FP64 A and b, a residual-and-correction pass and a
+            # final residual (56 + 64 + 56), with the inputs read twice per
+            # solve on the long-system path (104 + 120 + 56)
+            "fp32_ir_floor_B_per_row": ir_floor,
+            "fp32_ir_GBps_at_floor": ir_floor * rows / msir / 1e6,
             "ir_steps_hist": np.bincount(steps).tolist(),
             "ir_relres_max": float(res["rr"].max()),
             "ir_converged": int((res["inf"] == 0).sum()),
