@@ -363,8 +363,10 @@ int32_t sip_solve(int32_t dtype, int64_t n, int64_t batch, int64_t ld,
  * u1 = a), s steps of X_{j+1} = X_j (2I - T X_j) from X_0 = diag(T)^{-1}.
  * X_s is a band matrix on T's side of the diagonal of width
  * K = min(n - 1, q (2^s - 1)), q = 2 (kind 5) or 1 (kind 3).
- * factors: band_factor's output for the same kind and ld; diags: A's
- *   diagonals (only the upper ones are read: b for kind 5, a for kind 3).
+ * factors: band_factor's output for the same kind and ld, for systems whose
+ *   info is 0 (a zero u0 makes X_0 = diag(U)^{-1} infinite and the system's
+ *   X_U non-finite; nothing else reports it); diags: A's diagonals (only the
+ *   upper ones are read: b for kind 5, a for kind 3).
  * XL (s_L steps) and XU (s_U steps): K + 1 planes of n*ld doubles in the
  *   batch-interleaved layout; plane d holds X_L[i, i - d] (XL) or
  *   X_U[i, i + d] (XU) at d*n*ld + i*ld + s, and 0 where i - d < 0 or
