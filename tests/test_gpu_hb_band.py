@@ -162,3 +162,13 @@ def test_full_sweep_batch_sampled_against_vector_form(kind):
         ru = oracle.hb_upper_apply(u0, u1, pd["b"][j], 6, v)
         assert np.abs(yl - rl).max() <= 1e-12 * np.abs(rl).max(), j
         assert np.abs(yu - ru).max() <= 1e-12 * np.abs(ru).max(), j
+
+
+@pytest.mark.parametrize("kind", [5, 3])
+def test_many_tiles_and_chunks_bitwise(kind):
+    """n = 300 (19 row tiles of 16, the last ragged), s = (5, 6): bands up to
+    126 wide, so the product steps take up to 8 distance chunks and both step
+    forms run (M in registers below band 16, M through the workspace above);
+    sampled systems of a ragged batch bitwise against the dense recursion."""
+    ws = wl.dominant_batch(70, 300, kind=kind, seed=wl.BASE_SEED + 74)
+    check(ws, kind, 70, 5, 6, ld=96, systems=(0, 33, 69))
