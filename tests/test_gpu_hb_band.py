@@ -172,3 +172,35 @@ def test_many_tiles_and_chunks_bitwise(kind):
     sampled systems of a ragged batch bitwise against the dense recursion."""
     ws = wl.dominant_batch(70, 300, kind=kind, seed=wl.BASE_SEED + 74)
     check(ws, kind, 70, 5, 6, ld=96, systems=(0, 33, 69))
+
+
+def test_graph_replays_match_eager():
+    """hb_inverse_band enqueues kernels only (no host synchronisation, no
+    memset), so it can be captured in a HIP graph; every replay, with eager
+    work and synchronisation between replays, equals the eager call bitwise."""
+    batch, n = 40, 64
+    ws = wl.dominant_batch(batch, n, kind=5, seed=wl.BASE_SEED + 75)
+    t = to_device(ws, batch, ld=64)
+    f, _ = bs.factor(diags_of(t), batch=batch)
+    ref = bs.hb_inverse(diags_of(t), f, s_L=3, s_U=4, batch=batch)
+    nb = bs.load().hb_inverse_band_workspace_bytes(5, n, batch, 64, 3, 4)
+    wsb = torch.empty((nb + 7) // 8, dtype=torch.float64, device="cuda")
+    outs = [torch.zeros_like(r) for r in ref]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            bs.hb_inverse(diags_of(t), f, s_L=3, s_U=4, batch=batch, workspace=wsb, out=outs,
+                          stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        wsb.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o[:, :, :batch].contiguous().view(torch.int64),
+                               r[:, :, :batch].contiguous().view(torch.int64)), rep
